@@ -1,0 +1,289 @@
+"""FP64 CPU oracle of the IVHD embedding loop and of its evaluation metrics.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by
+the CPU-baseline leg of the benchmark, never by the product package.  It
+shares no code with the HIP path; both read their inputs from ``synth``.
+
+* ``ivhd_oracle.c`` (plain C, FP64): stress, force, the random-neighbour
+  draw and the momentum loop, each written as the thesis defines it.
+* this module: the ctypes binding of that file, plus numpy FP64 versions of
+  the exact kNN graph and of the quality metrics of the thesis's
+  "Quality metrics" chapter (trustworthiness / continuity, neighbour hit,
+  Q_NX / R_NX / AUC with the rank tie-break by index, kNN gain).
+* ``mlp.py``: the FP64 reference of the parametric encoder.
+
+Parity status of each function is stated in its docstring; every function
+here is pinned by a test in ``tests/test_oracle_*.py`` against something
+other than itself (finite differences, closed forms, invariants, a library
+routine on a special case, or brute force on tiny inputs).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ivhd_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libivhd_oracle.so")
+_lock = threading.Lock()
+_lib = None
+
+GCC_FLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math"]
+
+
+def build(force: bool = True) -> str:
+    """Compile ivhd_oracle.c with gcc into libivhd_oracle.so (in place)."""
+    if not force and os.path.exists(_LIB_PATH) and \
+            os.path.getmtime(_LIB_PATH) >= os.path.getmtime(_SRC):
+        return _LIB_PATH
+    tmp = _LIB_PATH + f".tmp{os.getpid()}"
+    subprocess.run(["gcc", *GCC_FLAGS, "-o", tmp, _SRC, "-lm"], check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        build(force=False)
+        lib = ctypes.CDLL(_LIB_PATH)
+        i64, i32, u64, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double
+        vp = ctypes.c_void_p
+        lib.orc_splitmix64.argtypes = [u64]
+        lib.orc_splitmix64.restype = u64
+        lib.orc_rn_sample.argtypes = [i64, i32, vp, i32, u64, i64, vp]
+        lib.orc_rn_sample.restype = None
+        lib.orc_force.argtypes = [i64, vp, i32, vp, i32, vp, dbl, dbl, vp]
+        lib.orc_force.restype = None
+        lib.orc_stress.argtypes = [i64, vp, i32, vp, i32, vp, dbl]
+        lib.orc_stress.restype = dbl
+        lib.orc_run.argtypes = [i64, vp, vp, i32, vp, i32, vp, dbl, dbl, dbl, dbl, u64,
+                                i64, i64, i64, vp]
+        lib.orc_run.restype = None
+        _lib = lib
+        return lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _graph(nn_idx, rn_idx=None):
+    nn_idx = np.ascontiguousarray(nn_idx, dtype=np.int32)
+    if nn_idx.ndim != 2:
+        raise ValueError("nn_idx must be [M, nn]")
+    if rn_idx is None:
+        rn_idx = np.zeros((nn_idx.shape[0], 0), dtype=np.int32)
+    rn_idx = np.ascontiguousarray(rn_idx, dtype=np.int32)
+    return nn_idx, rn_idx
+
+
+# ---------------------------------------------------------------------------
+# the loop (C)
+# ---------------------------------------------------------------------------
+
+def splitmix64(x: int) -> int:
+    """One SplitMix64 output for state ``x`` (gamma added, then mixed)."""
+    return int(_load().orc_splitmix64(ctypes.c_uint64(x & 0xFFFFFFFFFFFFFFFF)))
+
+
+def rn_sample(nn_idx, rn: int, seed: int, epoch: int) -> np.ndarray:
+    """Random neighbours of one epoch, int32 [M, rn] (see ivhd_oracle.c)."""
+    nn_idx, _ = _graph(nn_idx)
+    M, nn = nn_idx.shape
+    out = np.zeros((M, rn), dtype=np.int32)
+    _load().orc_rn_sample(M, nn, _ptr(nn_idx), rn, seed & 0xFFFFFFFFFFFFFFFF, epoch, _ptr(out))
+    return out
+
+
+def force(Y, nn_idx, rn_idx, c: float, eps: float = 1e-12) -> np.ndarray:
+    """f = -1/2 grad E in FP64, float64 [M, 2]."""
+    nn_idx, rn_idx = _graph(nn_idx, rn_idx)
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    M = Y.shape[0]
+    f = np.empty((M, 2), dtype=np.float64)
+    _load().orc_force(M, _ptr(Y), nn_idx.shape[1], _ptr(nn_idx), rn_idx.shape[1], _ptr(rn_idx),
+                      c, eps, _ptr(f))
+    return f
+
+
+def grad(Y, nn_idx, rn_idx, c: float, eps: float = 1e-12) -> np.ndarray:
+    """grad E = -2 f in FP64."""
+    return -2.0 * force(Y, nn_idx, rn_idx, c, eps)
+
+
+def stress(Y, nn_idx, rn_idx, c: float) -> float:
+    """E(Y) in FP64 (Eq. ivhd_cost_function)."""
+    nn_idx, rn_idx = _graph(nn_idx, rn_idx)
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    return float(_load().orc_stress(Y.shape[0], _ptr(Y), nn_idx.shape[1], _ptr(nn_idx),
+                                    rn_idx.shape[1], _ptr(rn_idx), c))
+
+
+def step(Y, V, f, a: float, b: float):
+    """One momentum update from a given force: (V', Y')."""
+    V1 = a * np.asarray(V, np.float64) + b * np.asarray(f, np.float64)
+    return np.asarray(Y, np.float64) + V1, V1
+
+
+def run(Y0, V0, nn_idx, *, rn: int, a: float, b: float, c: float, eps: float = 1e-12,
+        seed: int = 0, R: int = 0, n0: int = 0, T: int = 1):
+    """T iterations of the loop from (Y0, V0) at iteration n0.
+
+    Returns (Y, V, rn_idx) in FP64; rn_idx is the last epoch's draw.
+    """
+    nn_idx, _ = _graph(nn_idx)
+    M, nn = nn_idx.shape
+    Y = np.array(Y0, dtype=np.float64, order="C", copy=True)
+    V = np.array(V0, dtype=np.float64, order="C", copy=True)
+    rn_idx = np.zeros((M, rn), dtype=np.int32)
+    f = np.empty((M, 2), dtype=np.float64)
+    _load().orc_run(M, _ptr(Y), _ptr(V), nn, _ptr(nn_idx), rn, _ptr(rn_idx), a, b, c, eps,
+                    seed & 0xFFFFFFFFFFFFFFFF, R, n0, T, _ptr(f))
+    return Y, V, rn_idx
+
+
+# ---------------------------------------------------------------------------
+# exact kNN (numpy, FP64)
+# ---------------------------------------------------------------------------
+
+def knn(X, k: int, queries=None, chunk: int = 512) -> np.ndarray:
+    """Exact k nearest neighbours by squared Euclidean distance in FP64.
+
+    Self is excluded (for the rows of ``queries``, the query's own index),
+    and ties are broken by the lower index, i.e. the order is (d, j).
+    Returns int32 [len(queries), k].
+    """
+    X = np.asarray(X, dtype=np.float64)
+    M = X.shape[0]
+    q_idx = np.arange(M) if queries is None else np.asarray(queries, dtype=np.int64)
+    out = np.empty((q_idx.size, k), dtype=np.int32)
+    for s in range(0, q_idx.size, chunk):
+        qi = q_idx[s:s + chunk]
+        diff = X[qi][:, None, :] - X[None, :, :] if M * qi.size * X.shape[1] < 2e7 else None
+        if diff is not None:
+            d = np.einsum("qmn,qmn->qm", diff, diff)
+        else:
+            d = np.empty((qi.size, M))
+            for r, q in enumerate(qi):
+                t = X - X[q]
+                d[r] = np.einsum("mn,mn->m", t, t)
+        d[np.arange(qi.size), qi] = np.inf
+        # stable sort on d keeps index order among equal distances
+        order = np.argsort(d, axis=1, kind="stable")[:, :k]
+        out[s:s + qi.size] = order
+    return out
+
+
+# ---------------------------------------------------------------------------
+# quality metrics (numpy, FP64), chapter "Quality metrics"
+# ---------------------------------------------------------------------------
+
+def _sq_dists_rows(Z, rows):
+    Z = np.asarray(Z, dtype=np.float64)
+    out = np.empty((len(rows), Z.shape[0]))
+    for r, i in enumerate(rows):
+        t = Z - Z[i]
+        out[r] = np.einsum("mn,mn->m", t, t)
+    return out
+
+
+def rank_neighbours(Z, k: int, rows=None) -> np.ndarray:
+    """Sets v_i^k of the rank definition: the j with 1 <= rho_ij <= k.
+
+    rho_ij = |{l : delta_il < delta_ij or (delta_il = delta_ij and l < j)}|,
+    so all points (i included) are ordered by (distance, index) and the
+    positions 1..k are taken.  Returns int64 [len(rows), k].
+    """
+    M = np.asarray(Z).shape[0]
+    rows = np.arange(M) if rows is None else np.asarray(rows)
+    out = np.empty((rows.size, k), dtype=np.int64)
+    for s in range(0, rows.size, 256):
+        d = _sq_dists_rows(Z, rows[s:s + 256])
+        order = np.argsort(d, axis=1, kind="stable")
+        out[s:s + 256] = order[:, 1:k + 1]
+    return out
+
+
+def q_nx(X, Y, k: int, rows=None) -> float:
+    """Q_NX(k) = 1/(kM) sum_i |v_i^k & n_i^k| (neighbourhood preservation).
+
+    With ``rows`` the mean runs over that sample of query points instead
+    (each still ranked against all M points).
+    """
+    v = rank_neighbours(X, k, rows)
+    n = rank_neighbours(Y, k, rows)
+    hits = sum(len(np.intersect1d(v[r], n[r], assume_unique=True)) for r in range(v.shape[0]))
+    return hits / (k * v.shape[0])
+
+
+def r_nx(q: float, k: int, M: int) -> float:
+    """R_NX(k) = ((M - 1) Q_NX(k) - k) / (M - 1 - k)."""
+    return ((M - 1) * q - k) / (M - 1 - k)
+
+
+def auc_rnx(X, Y) -> float:
+    """AUC of R_NX(k) on a log axis: sum_k R_NX(k)/k / sum_k 1/k, k = 1..M-2."""
+    M = np.asarray(X).shape[0]
+    full_v = rank_neighbours(X, M - 1)
+    full_n = rank_neighbours(Y, M - 1)
+    num = den = 0.0
+    for k in range(1, M - 1):
+        hits = sum(len(np.intersect1d(full_v[i, :k], full_n[i, :k], assume_unique=True))
+                   for i in range(M))
+        num += r_nx(hits / (k * M), k, M) / k
+        den += 1.0 / k
+    return num / den
+
+
+def cf_k(Y, labels, k: int, rows=None) -> float:
+    """Neighbour hit cf_nn (Eq. eq12): the share of the k 2-D nearest
+    neighbours of each point that carry its class label."""
+    labels = np.asarray(labels)
+    n = rank_neighbours(Y, k, rows)
+    rows = np.arange(labels.size) if rows is None else np.asarray(rows)
+    return float((labels[n] == labels[rows][:, None]).sum() / (k * rows.size))
+
+
+def _ranks_full(Z):
+    """r[i, j] = rho_ij (position of j in i's (distance, index) order)."""
+    M = np.asarray(Z).shape[0]
+    d = _sq_dists_rows(Z, np.arange(M))
+    order = np.argsort(d, axis=1, kind="stable")
+    r = np.empty_like(order)
+    r[np.arange(M)[:, None], order] = np.arange(M)[None, :]
+    return r
+
+
+def trustworthiness(X, Y, k: int) -> float:
+    """M1(k) = 1 - 2/(Mk(2M-3k-1)) sum_i sum_{j in U_k(i)} (r(x_i,x_j) - k),
+    U_k(i): in the k-neighbourhood of y_i but not of x_i; r: rank in X."""
+    M = np.asarray(X).shape[0]
+    rX = _ranks_full(X)
+    rY = _ranks_full(Y)
+    s = 0.0
+    for i in range(M):
+        U = np.flatnonzero((rY[i] >= 1) & (rY[i] <= k) & ~((rX[i] >= 1) & (rX[i] <= k)))
+        s += float((rX[i, U] - k).sum())
+    return 1.0 - 2.0 / (M * k * (2 * M - 3 * k - 1)) * s
+
+
+def continuity(X, Y, k: int) -> float:
+    """M2(k): the same with the roles of X and Y exchanged."""
+    return trustworthiness(Y, X, k)
+
+
+def g_nn(X, Y, labels, k: int) -> float:
+    """kNN gain G_NN(k): mean over i of (same-class count among the k 2-D
+    neighbours - same-class count among the k N-D neighbours) / k."""
+    labels = np.asarray(labels)
+    v = rank_neighbours(X, k)
+    n = rank_neighbours(Y, k)
+    own = labels[:, None]
+    return float(((labels[n] == own).sum(1) - (labels[v] == own).sum(1)).mean() / k)

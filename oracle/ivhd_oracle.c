@@ -1,0 +1,151 @@
+/*
+ * Plain FP64 CPU oracle of the IVHD embedding loop.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
+ * includes this file; it shares no code, header or constant table with the
+ * HIP path.  Its only callers are the tests, the smoke check and the CPU
+ * baseline leg of the benchmark.
+ *
+ * Every function is the definition written out, one edge at a time, in the
+ * order the thesis states it, with no blocking, fusion or reordering:
+ *
+ *   stress   E(Y) = sum_i [ sum_{j in O_nn(i)} d_ij^2
+ *                           + c * sum_{k in O_rn(i)} (1 - d_ik)^2 ]
+ *            (Sec. "Improving classical MDS", Eq. ivhd_cost_function;
+ *             binary targets 0 / 1 of Eq. ivhd_binary_distances)
+ *   force    f = -1/2 grad E, assembled edge by edge, each directed edge
+ *            acting on both of its ends with opposite signs (IVHD-CUDA
+ *            section: one positive and one negative slot per connection).
+ *            nn edge (i,j): F = -(y_i - y_j)                       (Eq. eq13)
+ *            rn edge (i,k): F = +c (1 - d) (y_i - y_k) / max(d, eps)
+ *            The sign of the rn term follows -1/2 grad of the stress; the
+ *            printed Eq. eq13 carries the opposite sign (a misprint: with
+ *            it the random edges would pull points together).
+ *   step     V <- a V + b f ;  Y <- Y + V, all vertices from the same Y_n
+ *            (Eq. ivhd_force_1 / ivhd_position_update; Eq.
+ *             force_directed_update of Sec. "Force directed").
+ *   rn       per vertex, rn distinct random non-neighbours other than
+ *            itself, drawn ad hoc (Sec. "Improving classical MDS"; the
+ *            practical rules of Sec. "Force directed": a connected
+ *            neighbour cannot be a random one).  The draws come from the
+ *            counter-based SplitMix64 generator (Steele, Lea and Flood,
+ *            OOPSLA 2014; Vigna's public-domain reference), keyed by
+ *            (seed, epoch, vertex, slot, try).
+ *
+ * Build: gcc -O2 -std=c11 -fPIC -shared -ffp-contract=off -fno-fast-math
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <string.h>
+
+/* ---- SplitMix64: state advanced by the golden gamma, then the mix ---- */
+uint64_t orc_splitmix64(uint64_t x)
+{
+    uint64_t z = x + 0x9e3779b97f4a7c15ULL;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+/* Random-neighbour draw for one epoch.
+ * For vertex i and slot r the t-th try is
+ *     ctr = ((epoch * M + i) * rn + r) * 256 + t
+ *     h   = splitmix64(seed XOR splitmix64(ctr))
+ *     j   = h mod (M - 1), shifted past i (so j != i, uniform on the rest)
+ * A try is rejected when j is an nn out-neighbour of i or was already drawn
+ * for i; the try with t = 255 is accepted whatever it gives.            */
+void orc_rn_sample(int64_t M, int32_t nn, const int32_t *nn_idx, int32_t rn,
+                   uint64_t seed, int64_t epoch, int32_t *rn_out)
+{
+    for (int64_t i = 0; i < M; ++i) {
+        for (int32_t r = 0; r < rn; ++r) {
+            int64_t pick = -1;
+            for (int t = 0; t < 256; ++t) {
+                uint64_t ctr = (((uint64_t)epoch * (uint64_t)M + (uint64_t)i) * (uint64_t)rn
+                                + (uint64_t)r) * 256u + (uint64_t)t;
+                uint64_t h = orc_splitmix64(seed ^ orc_splitmix64(ctr));
+                int64_t j = (int64_t)(h % (uint64_t)(M - 1));
+                if (j >= i) j += 1;
+                int clash = 0;
+                for (int32_t q = 0; q < nn; ++q)
+                    if (nn_idx[i * nn + q] == j) clash = 1;
+                for (int32_t q = 0; q < r; ++q)
+                    if (rn_out[i * rn + q] == j) clash = 1;
+                pick = j;
+                if (!clash) break;
+            }
+            rn_out[i * rn + r] = (int32_t)pick;
+        }
+    }
+}
+
+/* f = -1/2 grad E, edge by edge; f must hold 2*M doubles (overwritten). */
+void orc_force(int64_t M, const double *Y, int32_t nn, const int32_t *nn_idx,
+               int32_t rn, const int32_t *rn_idx, double c, double eps, double *f)
+{
+    for (int64_t i = 0; i < 2 * M; ++i) f[i] = 0.0;
+    for (int64_t i = 0; i < M; ++i) {
+        for (int32_t q = 0; q < nn; ++q) {
+            int64_t j = nn_idx[i * nn + q];
+            if (j < 0) continue;                      /* absent neighbour */
+            double dx = Y[2 * i] - Y[2 * j];
+            double dy = Y[2 * i + 1] - Y[2 * j + 1];
+            double Fx = -dx, Fy = -dy;
+            f[2 * i] += Fx;  f[2 * i + 1] += Fy;
+            f[2 * j] -= Fx;  f[2 * j + 1] -= Fy;
+        }
+        for (int32_t q = 0; q < rn; ++q) {
+            int64_t k = rn_idx[i * rn + q];
+            double dx = Y[2 * i] - Y[2 * k];
+            double dy = Y[2 * i + 1] - Y[2 * k + 1];
+            double d = sqrt(dx * dx + dy * dy);
+            double s = c * (1.0 - d) / (d > eps ? d : eps);
+            double Fx = s * dx, Fy = s * dy;
+            f[2 * i] += Fx;  f[2 * i + 1] += Fy;
+            f[2 * k] -= Fx;  f[2 * k + 1] -= Fy;
+        }
+    }
+}
+
+double orc_stress(int64_t M, const double *Y, int32_t nn, const int32_t *nn_idx,
+                  int32_t rn, const int32_t *rn_idx, double c)
+{
+    double E = 0.0;
+    for (int64_t i = 0; i < M; ++i) {
+        for (int32_t q = 0; q < nn; ++q) {
+            int64_t j = nn_idx[i * nn + q];
+            if (j < 0) continue;
+            double dx = Y[2 * i] - Y[2 * j];
+            double dy = Y[2 * i + 1] - Y[2 * j + 1];
+            E += dx * dx + dy * dy;                   /* d_ij^2 */
+        }
+        for (int32_t q = 0; q < rn; ++q) {
+            int64_t k = rn_idx[i * rn + q];
+            double dx = Y[2 * i] - Y[2 * k];
+            double dy = Y[2 * i + 1] - Y[2 * k + 1];
+            double d = sqrt(dx * dx + dy * dy);
+            E += c * (1.0 - d) * (1.0 - d);           /* c (1 - d_ik)^2 */
+        }
+    }
+    return E;
+}
+
+/* T iterations starting at iteration n0.  Y, V: 2*M doubles, updated in
+ * place.  rn_idx: M*rn ints, in/out.  f: 2*M doubles of scratch.
+ * The random neighbours of epoch e = (R > 0 ? n / R : 0) are drawn at the
+ * first iteration of the call and whenever n is a multiple of R.         */
+void orc_run(int64_t M, double *Y, double *V, int32_t nn, const int32_t *nn_idx,
+             int32_t rn, int32_t *rn_idx, double a, double b, double c, double eps,
+             uint64_t seed, int64_t R, int64_t n0, int64_t T, double *f)
+{
+    for (int64_t n = n0; n < n0 + T; ++n) {
+        if (n == n0 || (R > 0 && n % R == 0))
+            orc_rn_sample(M, nn, nn_idx, rn, seed, R > 0 ? n / R : 0, rn_idx);
+        orc_force(M, Y, nn, nn_idx, rn, rn_idx, c, eps, f);
+        for (int64_t i = 0; i < 2 * M; ++i) {
+            V[i] = a * V[i] + b * f[i];
+            Y[i] = Y[i] + V[i];
+        }
+    }
+}

@@ -1,0 +1,210 @@
+"""Seeded synthetic inputs shared by the CPU oracle and the HIP path.
+
+This module only draws random numbers and lays them out; it holds none of
+the embedding method's arithmetic (no forces, no stress, no neighbour
+search).  Both sides of every parity test take their inputs from here, so
+that they read identical bytes.
+
+The datasets the method is evaluated on in the thesis (MNIST 70,000 x 784,
+YAHOO 1.4M x 100, see the dataset table of the appendix) are not available,
+so Gaussian mixtures of the same shape stand in for them:
+
+* ``C1``  2,000 x 32, 10 equal clusters, centres ~ N(0, 25 I), sigma = 1
+* ``C2``  70,000 x 784, 10 equal clusters, centres ~ N(0, 16 I), sigma = 1,
+          values clipped to [0, inf)  (MNIST shape)
+* ``C3``  1,400,000 x 100, 50 clusters with Zipf(1.1) sizes (largest
+          remainder), centres ~ N(0, 16 I), sigma = 1  (YAHOO shape)
+* ``C4``  1,000,000 x 64, 8 equal clusters, centres ~ N(0, 16 I)
+* ``C5``  1,000,000 (+200,000 held out) x 784, 20 equal clusters,
+          centres ~ N(0, 16 I), clipped to [0, inf)
+
+Point order is shuffled (the labels are a random permutation of the
+cluster assignment), so vertex ids carry no locality by construction.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+__all__ = [
+    "Config", "CONFIGS", "cluster_sizes", "gaussian_mixture", "init_positions",
+    "make_inputs", "random_neighbour_graph", "rng_for",
+]
+
+
+@dataclasses.dataclass(frozen=True)
+class Config:
+    """One frozen workload: data shape, graph sizes and loop constants."""
+    name: str
+    cfg_id: int
+    M: int
+    N: int
+    K: int
+    centre_var: float
+    sigma: float
+    sizes: str            # "equal" or "zipf"
+    zipf_s: float
+    clip: bool
+    nn: int
+    rn: int
+    R: int                # rn resampling period (0 = sampled once)
+    T: int                # iterations
+    c: float
+    a: float
+    b: float
+    seed: int = 0
+    M_heldout: int = 0
+
+
+# a, b: the thesis gives neither (only "a close to 1"); see the stability
+# reading in the design notes: b * lambda_max(L) < 2 (1 + a) with
+# lambda_max <= 2 * max degree, taken with a wide margin.
+CONFIGS = {
+    "C1": Config("C1", 1, 2_000, 32, 10, 25.0, 1.0, "equal", 0.0, False,
+                 nn=2, rn=1, R=0, T=500, c=0.1, a=0.9, b=0.002),
+    "C2": Config("C2", 2, 70_000, 784, 10, 16.0, 1.0, "equal", 0.0, True,
+                 nn=5, rn=1, R=0, T=2000, c=0.01, a=0.9, b=0.002),
+    "C3": Config("C3", 3, 1_400_000, 100, 50, 16.0, 1.0, "zipf", 1.1, False,
+                 nn=2, rn=1, R=100, T=2000, c=0.1, a=0.9, b=0.002),
+    "C4": Config("C4", 4, 1_000_000, 64, 8, 16.0, 1.0, "equal", 0.0, False,
+                 nn=5, rn=1, R=0, T=0, c=0.1, a=0.9, b=0.002),
+    "C5": Config("C5", 5, 1_000_000, 784, 20, 16.0, 1.0, "equal", 0.0, True,
+                 nn=5, rn=1, R=0, T=0, c=0.1, a=0.9, b=0.002,
+                 M_heldout=200_000),
+}
+
+
+def rng_for(cfg_id: int, seed: int = 0, stream: int = 0) -> np.random.Generator:
+    """The generator of config ``cfg_id``; stream 1 is the held-out set."""
+    if stream == 0:
+        return np.random.default_rng([seed, cfg_id])
+    return np.random.default_rng([seed, cfg_id, stream])
+
+
+def cluster_sizes(M: int, K: int, kind: str = "equal", s: float = 1.1) -> np.ndarray:
+    """Cluster sizes summing to M.
+
+    equal: M // K each, the remainder one each to the lowest cluster ids.
+    zipf:  proportional to k^-s (k = 1..K), rounded by largest remainder
+           (ties to the lower id).
+    """
+    if kind == "equal":
+        sizes = np.full(K, M // K, dtype=np.int64)
+        sizes[: M - sizes.sum()] += 1
+        return sizes
+    if kind == "zipf":
+        w = np.arange(1, K + 1, dtype=np.float64) ** (-s)
+        raw = M * w / w.sum()
+        sizes = np.floor(raw).astype(np.int64)
+        rem = int(M - sizes.sum())
+        order = np.argsort(-(raw - sizes), kind="stable")
+        sizes[order[:rem]] += 1
+        return sizes
+    raise ValueError(f"unknown size kind {kind!r}")
+
+
+def gaussian_mixture(M: int, N: int, K: int, *, centre_var: float, sigma: float,
+                     sizes: str = "equal", zipf_s: float = 1.1, clip: bool = False,
+                     rng: np.random.Generator, chunk: int = 65536):
+    """Isotropic Gaussian mixture; returns (X float32 [M,N], labels int32 [M]).
+
+    The centres are drawn first (K x N), then the shuffled labels, then the
+    points in chunks of ``chunk`` rows (so memory stays near the output).
+    """
+    centres = rng.normal(0.0, np.sqrt(centre_var), size=(K, N))
+    counts = cluster_sizes(M, K, sizes, zipf_s)
+    labels = np.repeat(np.arange(K, dtype=np.int32), counts)
+    labels = labels[rng.permutation(M)]
+    X = np.empty((M, N), dtype=np.float32)
+    for s in range(0, M, chunk):
+        e = min(M, s + chunk)
+        block = centres[labels[s:e]] + sigma * rng.standard_normal((e - s, N))
+        if clip:
+            np.maximum(block, 0.0, out=block)
+        X[s:e] = block
+    return X, labels
+
+
+def init_positions(M: int, rng: np.random.Generator) -> np.ndarray:
+    """Initial 2-D layout, uniform on [0, 1)^2, float32 [M, 2]."""
+    return rng.random((M, 2)).astype(np.float32)
+
+
+def make_inputs(cfg: Config, *, heldout: bool = False):
+    """(X, labels, Y0) for a config, from its own generator.
+
+    Y0 takes the next draws of the same generator after X.  With
+    ``heldout`` the held-out points of stream 1 are returned instead
+    (no Y0).
+    """
+    if heldout:
+        rng = rng_for(cfg.cfg_id, cfg.seed, stream=1)
+        # same centres as the training set: redraw them from stream 0
+        rng0 = rng_for(cfg.cfg_id, cfg.seed)
+        centres = rng0.normal(0.0, np.sqrt(cfg.centre_var), size=(cfg.K, cfg.N))
+        Mh = cfg.M_heldout
+        counts = cluster_sizes(Mh, cfg.K, cfg.sizes, cfg.zipf_s)
+        labels = np.repeat(np.arange(cfg.K, dtype=np.int32), counts)[rng.permutation(Mh)]
+        X = np.empty((Mh, cfg.N), dtype=np.float32)
+        for s in range(0, Mh, 65536):
+            e = min(Mh, s + 65536)
+            block = centres[labels[s:e]] + cfg.sigma * rng.standard_normal((e - s, cfg.N))
+            if cfg.clip:
+                np.maximum(block, 0.0, out=block)
+            X[s:e] = block
+        return X, labels, None
+    rng = rng_for(cfg.cfg_id, cfg.seed)
+    X, labels = gaussian_mixture(cfg.M, cfg.N, cfg.K, centre_var=cfg.centre_var,
+                                 sigma=cfg.sigma, sizes=cfg.sizes, zipf_s=cfg.zipf_s,
+                                 clip=cfg.clip, rng=rng)
+    Y0 = init_positions(cfg.M, rng)
+    return X, labels, Y0
+
+
+def random_neighbour_graph(M: int, nn: int, rng: np.random.Generator, *,
+                           labels: Optional[np.ndarray] = None, hub_alpha: float = 0.0,
+                           absent_frac: float = 0.0) -> np.ndarray:
+    """A kNN-shaped directed graph without a neighbour search: int32 [M, nn].
+
+    Each vertex draws ``nn`` distinct targets other than itself, from its own
+    cluster when ``labels`` is given.  ``hub_alpha > 0`` weights targets by a
+    Pareto(hub_alpha) popularity, which gives the heavy-tailed in-degree of
+    high-dimensional kNN graphs.  ``absent_frac`` of the slots are set to -1
+    (a vertex with fewer than nn neighbours).  Used where the exact kNN graph
+    is too costly to compute on the CPU (large M), and for edge cases.
+    """
+    if labels is None:
+        labels = np.zeros(M, dtype=np.int32)
+    out = np.empty((M, nn), dtype=np.int32)
+    pop = rng.pareto(hub_alpha, size=M) + 1.0 if hub_alpha > 0 else np.ones(M)
+    for lab in np.unique(labels):
+        members = np.flatnonzero(labels == lab)
+        m = members.size
+        if m - 1 < nn:
+            raise ValueError("cluster smaller than nn + 1")
+        p = pop[members] / pop[members].sum()
+        cdf = np.cumsum(p)
+        cdf[-1] = 1.0
+        rows = np.empty((m, nn), dtype=np.int64)
+        filled = np.zeros(m, dtype=np.int64)
+        # rejection: draw candidates until every row holds nn distinct non-self ids
+        while True:
+            todo = np.flatnonzero(filled < nn)
+            if todo.size == 0:
+                break
+            cand = np.searchsorted(cdf, rng.random(todo.size), side="right")
+            cand = np.minimum(cand, m - 1)
+            ok = cand != todo
+            for r in range(nn):
+                has = filled[todo] > r
+                ok &= ~(has & (rows[todo, r] == cand))
+            sel = todo[ok]
+            rows[sel, filled[sel]] = cand[ok]
+            filled[sel] += 1
+        out[members] = members[rows].astype(np.int32)
+    if absent_frac > 0:
+        mask = rng.random((M, nn)) < absent_frac
+        out[mask] = -1
+    return out
