@@ -1,0 +1,171 @@
+/*
+ * ivhd.h -- C ABI of the MI355X (gfx950) IVHD embedding library.
+ *
+ * IVHD embeds a kNN graph in 2-D.  Every vertex i has up to nn
+ * nearest-neighbour out-edges O_nn(i) (target distance 0) and rn random
+ * out-edges O_rn(i) (target distance 1) drawn by the library.  The layout Y
+ * minimises the binary-distance stress
+ *
+ *     E(Y) = sum_i [ sum_{j in O_nn(i)} |y_i - y_j|^2
+ *                    + c * sum_{k in O_rn(i)} (1 - |y_i - y_k|)^2 ]
+ *
+ * (thesis: Sec. "Improving classical MDS", Eq. ivhd_cost_function with the
+ * binary dissimilarities of Eq. ivhd_binary_distances) by the damped
+ * particle method of Sec. "Force directed", Eq. force_directed_update:
+ *
+ *     f  = -1/2 grad E        (every edge acts on both of its ends)
+ *     V <- a V + b f ;  Y <- Y + V      (all vertices from the same Y)
+ *
+ * Conventions shared by every entry point
+ *  - All pointers named d_* are HIP device pointers on the current device,
+ *    owned by the CALLER, contiguous, row-major.  h_* are host pointers.
+ *  - Positions and velocities are float32 [M][2] (x, y interleaved).
+ *  - Vertex ids are int32; a neighbour slot holding -1 is absent (a vertex
+ *    with fewer than nn neighbours keeps all it has, Sec. "Force directed").
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued on it; calls return before the GPU finishes unless the
+ *    entry point says it synchronises.
+ *  - Every call returns an ivhd_status.  Nothing is thrown or aborted across
+ *    the ABI.  On failure ivhd_last_error() holds a message (thread-local,
+ *    valid until the next call on that thread).  Arguments are validated on
+ *    the host before any device work, so an IVHD_EINVAL from validation
+ *    leaves device memory untouched.
+ */
+#ifndef IVHD_H
+#define IVHD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ivhd_status {
+    IVHD_OK = 0,
+    IVHD_EINVAL = -1,    /* bad argument, or (at init) a bad neighbour index */
+    IVHD_ENOMEM = -2,    /* device allocation failed */
+    IVHD_EDEVICE = -3,   /* a HIP call failed */
+    IVHD_ESTATE = -4,    /* NULL or destroyed context */
+    IVHD_ENUMERIC = -5   /* a non-finite position or force was produced */
+} ivhd_status;
+
+typedef enum ivhd_mode {
+    IVHD_MODE_DET = 0,     /* per-vertex gather over out-edges and transposed
+                              in-edges, fixed order, no atomics: bitwise
+                              reproducible run to run                        */
+    IVHD_MODE_ATOMIC = 1   /* per-vertex out-edge pass adding each reaction to
+                              the other end with float atomics, then an update
+                              pass; summation order varies run to run        */
+} ivhd_mode;
+
+typedef struct ivhd_params {
+    int64_t  M;       /* vertices; 2 <= M <= 2^31 - 2                        */
+    int32_t  nn;      /* nn slots per vertex, 1..64                          */
+    int32_t  rn;      /* random neighbours per vertex, 0..64; nn + rn <= M-1 */
+    float    a;       /* momentum (friction) factor, 0 <= a <= 1             */
+    float    b;       /* force step, b > 0                                   */
+    float    c;       /* random-edge weight, 0 < c < 1                       */
+    float    eps;     /* guard of the rn unit vector y_ik / max(d, eps); >= 0 */
+    uint64_t seed;    /* random-neighbour generator key                       */
+    int32_t  rn_resample_every; /* R: draw new random neighbours at every
+                                   iteration n with n % R == 0; 0 = draw once */
+    int32_t  mode;    /* ivhd_mode                                            */
+} ivhd_params;
+
+typedef struct ivhd_ctx ivhd_ctx;   /* opaque */
+
+/* Random-neighbour draw (the rule of Sec. "Improving classical MDS": rn
+ * random non-neighbours per vertex, generated ad hoc; Sec. "Force directed":
+ * a connected neighbour is never a random one).  For epoch e, vertex i, slot
+ * r and try t = 0..255:
+ *     ctr = ((e*M + i)*rn + r)*256 + t
+ *     h   = splitmix64(seed ^ splitmix64(ctr))       (SplitMix64, Steele et al. 2014)
+ *     j   = h mod (M-1); if (j >= i) j += 1
+ * the try is rejected if j is in O_nn(i) or already drawn for i; try 255 is
+ * accepted whatever it gives.  Epoch e covers iterations [e*R, (e+1)*R).   */
+
+/* ivhd_init: create a context for one graph and one layout.
+ *   d_nn_idx  int32 [M][nn], read at init and at every random-neighbour draw;
+ *             must stay valid and unchanged for the context's lifetime.
+ *   d_y, d_v  float32 [M][2]; the context advances them in place (ivhd_step);
+ *             they must stay valid for the context's lifetime.  d_v is
+ *             normally zeros.
+ *   stream    hipStream_t all later calls enqueue on.
+ * Draws the random neighbours of epoch 0 and builds the transposed edge
+ * lists.  Synchronises `stream`.  Returns IVHD_EINVAL (and no context) when
+ * an nn entry is outside [-1, M) or equals its own row.                      */
+int ivhd_init(ivhd_ctx **out, const ivhd_params *p, const int32_t *d_nn_idx,
+              float *d_y, float *d_v, void *stream);
+
+/* ivhd_step: n_iters >= 0 iterations of the loop; asynchronous.  Y and V are
+ * left in the caller's buffers.  Iterations are replayed from captured HIP
+ * graphs when possible (one graph per random-neighbour epoch).             */
+int ivhd_step(ivhd_ctx *ctx, int64_t n_iters);
+
+/* ivhd_stress: E(Y) accumulated in FP64 from the FP32 positions, with a
+ * fixed-order (deterministic) reduction.  d_y = NULL uses the context's Y;
+ * otherwise float32 [M][2] evaluated with the context's current edges.
+ * Synchronises the stream.  IVHD_ENUMERIC if E is not finite.             */
+int ivhd_stress(ivhd_ctx *ctx, const float *d_y, double *h_E);
+
+/* ivhd_grad: d_grad = grad E (= -2 f) in FP32, float32 [M][2]; d_y as in
+ * ivhd_stress.  Asynchronous.                                               */
+int ivhd_grad(ivhd_ctx *ctx, const float *d_y, float *d_grad);
+
+/* ivhd_get_rn: copy the current epoch's random neighbours, int32 [M][rn]. */
+int ivhd_get_rn(ivhd_ctx *ctx, int32_t *d_rn_out);
+
+/* ivhd_get_in_edges: copy the transposed (in-edge) lists the deterministic
+ * mode gathers over: which = 0 for the nn edges, 1 for the current epoch's
+ * rn edges.  d_ptr int32 [M+1] (offsets), d_src int32 [M*nn] or [M*rn]
+ * (sources of the edges into each vertex, ascending; only the first
+ * d_ptr[M] entries are written).  IVHD_EINVAL in atomic mode for which = 1
+ * (that mode keeps no rn in-edge lists).                                    */
+int ivhd_get_in_edges(ivhd_ctx *ctx, int32_t which, int32_t *d_ptr, int32_t *d_src);
+
+/* ivhd_get_iteration: the number of iterations done so far.                */
+int ivhd_get_iteration(const ivhd_ctx *ctx, int64_t *h_n);
+
+/* ivhd_set_graphs: 1 = replay captured HIP graphs (default), 0 = launch each
+ * kernel directly.  Results are identical either way.                       */
+int ivhd_set_graphs(ivhd_ctx *ctx, int32_t enable);
+
+/* ivhd_destroy: free everything the context owns (not the caller's buffers).
+ * Synchronises the stream.  NULL is accepted.                               */
+int ivhd_destroy(ivhd_ctx *ctx);
+
+/* ---- input preparation: exact kNN graph (brute force, FP32) ------------- */
+
+/* ivhd_knn_build: the nn nearest neighbours of every row of X, the kNN graph
+ * the loop embeds (its edges are the nn lists of Sec. "Improving classical
+ * MDS"; the thesis obtains them from an approximate GPU index, this is the
+ * exact graph).  Order: squared Euclidean distance, ties to the lower index,
+ * the row itself excluded.
+ *   d_x    float32 [M][N], row-major (read only)
+ *   d_idx  int32 [M][k] output, nearest first
+ * 1 <= k <= min(28, M-1), N >= 1.  Allocates a temporary [M] float buffer
+ * and synchronises the stream.                                              */
+int ivhd_knn_build(const float *d_x, int64_t M, int32_t N, int32_t k, int32_t *d_idx,
+                   void *stream);
+
+/* ivhd_knn_query: the k nearest rows of X to each of Q query rows (used for
+ * the quality metrics on a sample of points).
+ *   d_q     float32 [Q][N] queries;  d_self int32 [Q] or NULL: row d_self[q]
+ *           of X is excluded for query q (-1 = none)
+ *   d_idx   int32 [Q][k];  d_dist float32 [Q][k] squared distances, or NULL
+ * 1 <= k <= min(28, M-1).  Synchronises the stream.                         */
+int ivhd_knn_query(const float *d_x, int64_t M, int32_t N, const float *d_q, int64_t Q,
+                   const int32_t *d_self, int32_t k, int32_t *d_idx, float *d_dist,
+                   void *stream);
+
+/* ivhd_last_error: message of the last failure on this thread ("" if none). */
+const char *ivhd_last_error(void);
+
+/* ivhd_version: library version as major*10000 + minor*100 + patch.        */
+int ivhd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IVHD_H */

@@ -1,0 +1,226 @@
+"""Python binding of the C ABI in include/ivhd.h.
+
+The functions keep the C names and only marshal arguments: torch tensors
+give device pointers and the current HIP stream; every computation runs in
+libivhd's kernels.  ``Context`` is a small convenience wrapper that keeps the
+tensors a context points at alive.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import torch
+
+from . import _lib
+from ._lib import IvhdError, check, ivhd_params
+
+MODES = {"det": 0, "atomic": 1}
+
+__all__ = [
+    "IvhdError", "Context", "make_params", "ivhd_init", "ivhd_step", "ivhd_stress", "ivhd_grad",
+    "ivhd_get_rn", "ivhd_get_in_edges", "ivhd_get_iteration", "ivhd_set_graphs", "ivhd_destroy", "ivhd_last_error",
+    "ivhd_version", "ivhd_knn_build", "ivhd_knn_query",
+]
+
+
+def _stream_handle(stream: Optional[torch.cuda.Stream]) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, shape, name: str) -> int:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a HIP device, got {t.device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def make_params(M: int, nn: int, rn: int, *, a: float, b: float, c: float, eps: float = 1e-12,
+                seed: int = 0, rn_resample_every: int = 0, mode: str = "det") -> ivhd_params:
+    return ivhd_params(M=M, nn=nn, rn=rn, a=a, b=b, c=c, eps=eps, seed=seed & (2**64 - 1),
+                       rn_resample_every=rn_resample_every, mode=MODES[mode])
+
+
+def ivhd_init(params: ivhd_params, nn_idx: torch.Tensor, y: torch.Tensor, v: torch.Tensor,
+              stream: Optional[torch.cuda.Stream] = None) -> ctypes.c_void_p:
+    lib = _lib.load()
+    M, nn = params.M, params.nn
+    p_nn = _dev(nn_idx, torch.int32, (M, nn), "nn_idx")
+    p_y = _dev(y, torch.float32, (M, 2), "y")
+    p_v = _dev(v, torch.float32, (M, 2), "v")
+    h = ctypes.c_void_p()
+    check(lib.ivhd_init(ctypes.byref(h), ctypes.byref(params), p_nn, p_y, p_v, _stream_handle(stream)))
+    return h
+
+
+def ivhd_step(ctx, n_iters: int) -> None:
+    check(_lib.load().ivhd_step(ctx, int(n_iters)))
+
+
+def ivhd_stress(ctx, y: Optional[torch.Tensor] = None, M: Optional[int] = None) -> float:
+    E = ctypes.c_double()
+    p_y = None if y is None else _dev(y, torch.float32, (M if M is not None else y.shape[0], 2), "y")
+    check(_lib.load().ivhd_stress(ctx, p_y, ctypes.byref(E)))
+    return E.value
+
+
+def ivhd_grad(ctx, out: torch.Tensor, y: Optional[torch.Tensor] = None) -> torch.Tensor:
+    M = out.shape[0]
+    p_out = _dev(out, torch.float32, (M, 2), "out")
+    p_y = None if y is None else _dev(y, torch.float32, (M, 2), "y")
+    check(_lib.load().ivhd_grad(ctx, p_y, p_out))
+    return out
+
+
+def ivhd_get_rn(ctx, out: torch.Tensor) -> torch.Tensor:
+    p = out.data_ptr() if out.numel() else None
+    if out.numel():
+        _dev(out, torch.int32, tuple(out.shape), "out")
+    check(_lib.load().ivhd_get_rn(ctx, p))
+    return out
+
+
+def ivhd_get_in_edges(ctx, which: int, ptr_out: torch.Tensor, src_out: torch.Tensor):
+    _dev(ptr_out, torch.int32, tuple(ptr_out.shape), "ptr_out")
+    _dev(src_out, torch.int32, tuple(src_out.shape), "src_out")
+    check(_lib.load().ivhd_get_in_edges(ctx, int(which), ptr_out.data_ptr(), src_out.data_ptr()))
+    return ptr_out, src_out
+
+
+def ivhd_get_iteration(ctx) -> int:
+    n = ctypes.c_int64()
+    check(_lib.load().ivhd_get_iteration(ctx, ctypes.byref(n)))
+    return n.value
+
+
+def ivhd_set_graphs(ctx, enable: bool) -> None:
+    check(_lib.load().ivhd_set_graphs(ctx, 1 if enable else 0))
+
+
+def ivhd_destroy(ctx) -> None:
+    check(_lib.load().ivhd_destroy(ctx))
+
+
+def ivhd_knn_build(x: torch.Tensor, k: int, out: Optional[torch.Tensor] = None,
+                   stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """Exact kNN graph of the rows of x (float32 [M, N] on the GPU): int32 [M, k]."""
+    M, N = x.shape
+    _dev(x, torch.float32, (M, N), "x")
+    if out is None:
+        out = torch.empty((M, k), dtype=torch.int32, device=x.device)
+    _dev(out, torch.int32, (M, k), "out")
+    check(_lib.load().ivhd_knn_build(x.data_ptr(), M, N, k, out.data_ptr(), _stream_handle(stream)))
+    return out
+
+
+def ivhd_knn_query(x: torch.Tensor, q: torch.Tensor, k: int, self_idx: Optional[torch.Tensor] = None,
+                   with_dist: bool = False, stream: Optional[torch.cuda.Stream] = None):
+    """k nearest rows of x to each row of q: int32 [Q, k] (and float32 squared distances)."""
+    M, N = x.shape
+    Q = q.shape[0]
+    _dev(x, torch.float32, (M, N), "x")
+    _dev(q, torch.float32, (Q, N), "q")
+    p_self = None
+    if self_idx is not None:
+        p_self = _dev(self_idx, torch.int32, (Q,), "self_idx")
+    idx = torch.empty((Q, k), dtype=torch.int32, device=x.device)
+    dist = torch.empty((Q, k), dtype=torch.float32, device=x.device) if with_dist else None
+    check(_lib.load().ivhd_knn_query(x.data_ptr(), M, N, q.data_ptr(), Q, p_self, k, idx.data_ptr(),
+                                     dist.data_ptr() if dist is not None else None,
+                                     _stream_handle(stream)))
+    return (idx, dist) if with_dist else idx
+
+
+def ivhd_last_error() -> str:
+    m = _lib.load().ivhd_last_error()
+    return m.decode() if m else ""
+
+
+def ivhd_version() -> int:
+    return int(_lib.load().ivhd_version())
+
+
+class Context:
+    """One embedding: a kNN graph, positions and velocities on the GPU.
+
+    ``y`` and ``v`` are advanced in place by ``step``; the context keeps
+    references to ``nn_idx``, ``y`` and ``v`` so they outlive it.
+    """
+
+    def __init__(self, nn_idx: torch.Tensor, y: torch.Tensor, v: Optional[torch.Tensor] = None, *,
+                 rn: int = 1, a: float = 0.9, b: float = 0.01, c: float = 0.1, eps: float = 1e-12,
+                 seed: int = 0, rn_resample_every: int = 0, mode: str = "det",
+                 stream: Optional[torch.cuda.Stream] = None):
+        M, nn = nn_idx.shape
+        if v is None:
+            v = torch.zeros_like(y)
+        self.params = make_params(M, nn, rn, a=a, b=b, c=c, eps=eps, seed=seed,
+                                  rn_resample_every=rn_resample_every, mode=mode)
+        self.nn_idx, self.y, self.v = nn_idx, y, v
+        self.M, self.nn, self.rn = M, nn, rn
+        self._h = None
+        self._h = ivhd_init(self.params, nn_idx, y, v, stream)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise IvhdError(-4, "context is closed")
+        return self._h
+
+    def step(self, n_iters: int) -> "Context":
+        ivhd_step(self.handle, n_iters)
+        return self
+
+    def stress(self, y: Optional[torch.Tensor] = None) -> float:
+        return ivhd_stress(self.handle, y, self.M)
+
+    def grad(self, y: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty((self.M, 2), dtype=torch.float32, device=self.y.device)
+        return ivhd_grad(self.handle, out, y)
+
+    def rn_edges(self) -> torch.Tensor:
+        out = torch.empty((self.M, self.rn), dtype=torch.int32, device=self.y.device)
+        return ivhd_get_rn(self.handle, out)
+
+    def in_edges(self, which: str = "nn"):
+        """(ptr [M+1], src) of the transposed nn or rn edge lists, on the host."""
+        k = self.nn if which == "nn" else self.rn
+        ptr = torch.empty(self.M + 1, dtype=torch.int32, device=self.y.device)
+        src = torch.empty(max(1, self.M * k), dtype=torch.int32, device=self.y.device)
+        ivhd_get_in_edges(self.handle, 0 if which == "nn" else 1, ptr, src)
+        torch.cuda.synchronize()
+        ptr = ptr.cpu().numpy()
+        return ptr, src.cpu().numpy()[: ptr[-1]]
+
+    @property
+    def iteration(self) -> int:
+        return ivhd_get_iteration(self.handle)
+
+    def set_graphs(self, enable: bool) -> None:
+        ivhd_set_graphs(self.handle, enable)
+
+    def close(self) -> None:
+        if self._h is not None:
+            h, self._h = self._h, None
+            ivhd_destroy(h)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,94 @@
+// Internal declarations shared by the HIP translation units of libivhd.
+// Not part of the public ABI (that is include/ivhd.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ivhd.h"
+
+namespace ivhd {
+
+constexpr int kBlock = 256;          // threads per block of the per-vertex kernels
+constexpr int kScanItems = 8;        // items per thread in the block scan
+constexpr int kScanChunk = kBlock * kScanItems;
+constexpr int kSmallSegment = 32;    // in-edge segments up to this size are sorted per thread
+constexpr int kBigSortBlocks = 256;  // blocks that share the list of large segments
+
+// device flag slots
+enum { FLAG_BAD_INDEX = 0, FLAG_NONFINITE = 1, FLAG_BIG_COUNT = 2, FLAG_SLOTS = 4 };
+
+inline unsigned grid_for(int64_t n, int block = kBlock) {
+  int64_t g = (n + block - 1) / block;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+// Transposed (CSC) edge lists: for every target j, the sources s of the
+// edges s -> j, sorted ascending (multiplicity kept).
+struct Csc {
+  int32_t *ptr = nullptr;   // [M+1]
+  int32_t *src = nullptr;   // [capacity]
+};
+
+// Scratch shared by CSC builds.
+struct CscScratch {
+  int32_t *cnt = nullptr;        // [M+1]: counts, then the scatter cursor
+  int32_t *tmp = nullptr;        // [capacity]: unsorted sources
+  int32_t *part = nullptr;       // [ceil((M+1)/kScanChunk)] block partial sums
+  int32_t *big = nullptr;        // [M]: targets with a segment above kSmallSegment
+};
+
+// ---- graph.hip ----
+hipError_t launch_validate_nn(const int32_t *nn_idx, int64_t M, int nn, int32_t *flags, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t value, hipStream_t s);
+// Begins a random-neighbour epoch: epoch += 1; when cnt != NULL zeroes cnt[0..M] and flags[FLAG_BIG_COUNT].
+hipError_t launch_epoch_begin(int64_t *epoch, int32_t *cnt, int64_t M, int32_t *flags, hipStream_t s);
+// rn draw for epoch *epoch; when cnt != NULL also counts in-degrees into cnt.
+hipError_t launch_rn_sample(const int32_t *nn_idx, int64_t M, int nn, int rn, uint64_t seed,
+                            const int64_t *epoch, int32_t *rn_idx, int32_t *cnt, hipStream_t s);
+// in-degree count of an [M][k] index list (entries < 0 skipped); cnt must be zero.
+hipError_t launch_count(const int32_t *idx, int64_t M, int k, int32_t *cnt, hipStream_t s);
+// From counts cnt[0..M-1]: ptr = exclusive scan (ptr[M] = total), cnt = cursor copy.
+hipError_t launch_scan(int32_t *cnt, int64_t M, int32_t *part, int32_t *ptr, hipStream_t s);
+// Scatter + canonical sort: csc.src segments end sorted ascending.
+hipError_t launch_scatter_sort(const int32_t *idx, int64_t M, int k, const int32_t *ptr,
+                               int32_t *cursor, int32_t *tmp, int32_t *big, int32_t *flags,
+                               int32_t *src_out, hipStream_t s);
+
+// ---- step.hip ----
+struct StepArgs {
+  const float2 *y;        // positions read (Y_n)
+  float2 *y_out;          // positions written (Y_{n+1}); det mode: != y
+  float2 *v;              // velocities, in place
+  const int32_t *nn_idx;  // [M][nn]
+  const int32_t *rn_idx;  // [M][rn]
+  const int32_t *nn_ptr, *nn_src;   // CSC of nn edges
+  const int32_t *rn_ptr, *rn_src;   // CSC of rn edges
+  float2 *fbuf;           // atomic mode accumulator [M]
+  int32_t *flags;
+  int64_t M;
+  int nn, rn;
+  float a, b, c, eps;
+};
+hipError_t launch_step_det(const StepArgs &a, hipStream_t s);
+hipError_t launch_step_atomic(const StepArgs &a, hipStream_t s);   // two kernels
+// grad E = -2 f at positions a.y into out (det gather; or atomic scatter via fbuf)
+hipError_t launch_grad_det(const StepArgs &a, float2 *out, hipStream_t s);
+hipError_t launch_grad_atomic(const StepArgs &a, float2 *out, hipStream_t s);
+
+// ---- reduce.hip ----
+// FP64 stress: per-block partial sums (fixed tree), then one block in fixed order.
+hipError_t launch_stress(const float2 *y, int64_t M, const int32_t *nn_idx, int nn,
+                         const int32_t *rn_idx, int rn, double c, double *partials,
+                         int nparts, double *out, hipStream_t s);
+int stress_partials(int64_t M);
+
+// ---- knn.hip ----
+int knn_max_k();
+hipError_t launch_row_norms(const float *X, int64_t M, int N, float *out, hipStream_t s);
+// self_mode: 0 = none, 1 = query q excludes candidate q, 2 = query q excludes self[q]
+hipError_t launch_knn(const float *X, int64_t M, int N, const float *Q, int64_t nq, int self_mode,
+                      const int32_t *self, const float *cnorm, int k, int32_t *idx, float *dist,
+                      hipStream_t s);
+
+}  // namespace ivhd
