@@ -61,6 +61,8 @@ struct ivhd_ctx {
   int64_t *epoch = nullptr;
   int32_t *flags = nullptr;
   float2 *fbuf = nullptr;
+  int32_t *heavy = nullptr;       // vertices served by a whole wavefront (det mode)
+  int32_t n_heavy = 0;
   double *partials = nullptr;
   int nparts = 0;
   double *d_E = nullptr;
@@ -100,7 +102,7 @@ void free_ctx(ivhd_ctx *c) {
   }
   void *bufs[] = {c->y_alt, c->nn_csc.ptr, c->nn_csc.src, c->rn_csc.ptr, c->rn_csc.src,
                   c->sc.cnt, c->sc.tmp, c->sc.part, c->sc.big, c->rn_idx, c->epoch,
-                  c->flags, c->fbuf, c->partials, c->d_E};
+                  c->flags, c->fbuf, c->heavy, c->partials, c->d_E};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (c->cap) (void)hipStreamDestroy(c->cap);
@@ -150,6 +152,9 @@ StepArgs step_args(const ivhd_ctx *c, const float2 *y, float2 *y_out) {
   a.rn_src = c->rn_csc.src;
   a.fbuf = c->fbuf;
   a.flags = c->flags;
+  a.heavy = c->heavy;
+  a.n_heavy = c->n_heavy;
+  a.heavy_blocks = (c->n_heavy + kHeavyPerBlock - 1) / kHeavyPerBlock;
   a.M = c->p.M;
   a.nn = c->p.nn;
   a.rn = c->p.rn;
@@ -299,6 +304,7 @@ int ivhd_init(ivhd_ctx **out, const ivhd_params *p, const int32_t *d_nn_idx, flo
     }
   }
   if (p->mode == IVHD_MODE_ATOMIC) ALLOC(c->fbuf, M, "force accumulator");
+  if (p->mode == IVHD_MODE_DET) ALLOC(c->heavy, M, "heavy-vertex list");
   c->nparts = stress_partials(M);
   ALLOC(c->partials, c->nparts, "stress partials");
   ALLOC(c->d_E, 1, "stress result");
@@ -314,6 +320,13 @@ int ivhd_init(ivhd_ctx **out, const ivhd_params *p, const int32_t *d_nn_idx, flo
     return fail(IVHD_EINVAL, "nn_idx holds an entry outside [-1, M) or a self edge");
   }
   CHK(build_nn_csc(c));
+  if (c->heavy) {
+    HIPCHK_C(launch_fill_i32(c->flags + FLAG_BIG_COUNT, 1, 0, s));
+    HIPCHK_C(launch_heavy_list(c->nn_csc.ptr, M, c->heavy, c->flags + FLAG_BIG_COUNT, s));
+    HIPCHK_C(hipMemcpyAsync(&c->n_heavy, c->flags + FLAG_BIG_COUNT, sizeof c->n_heavy,
+                            hipMemcpyDeviceToHost, s));
+    HIPCHK_C(hipStreamSynchronize(s));
+  }
   if (c->fbuf) HIPCHK_C(launch_fill_i32((int32_t *)c->fbuf, 2 * M, 0, s));
   const int64_t minus_one = -1;
   HIPCHK_C(hipMemcpyAsync(c->epoch, &minus_one, sizeof minus_one, hipMemcpyHostToDevice, s));

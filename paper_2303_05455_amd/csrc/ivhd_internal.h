@@ -14,6 +14,8 @@ constexpr int kScanItems = 8;        // items per thread in the block scan
 constexpr int kScanChunk = kBlock * kScanItems;
 constexpr int kSmallSegment = 32;    // in-edge segments up to this size are sorted per thread
 constexpr int kBigSortBlocks = 256;  // blocks that share the list of large segments
+constexpr int kHeavyDegree = 24;     // nn in-degree above which a vertex gets a whole wavefront
+constexpr int kHeavyPerBlock = kBlock / 64;
 
 // device flag slots
 enum { FLAG_BAD_INDEX = 0, FLAG_NONFINITE = 1, FLAG_BIG_COUNT = 2, FLAG_SLOTS = 4 };
@@ -66,6 +68,9 @@ struct StepArgs {
   const int32_t *rn_ptr, *rn_src;   // CSC of rn edges
   float2 *fbuf;           // atomic mode accumulator [M]
   int32_t *flags;
+  const int32_t *heavy;   // vertices whose nn in-degree exceeds kHeavyDegree
+  int32_t n_heavy;
+  int32_t heavy_blocks;   // leading blocks of a launch that serve the heavy vertices
   int64_t M;
   int nn, rn;
   float a, b, c, eps;
@@ -75,6 +80,10 @@ hipError_t launch_step_atomic(const StepArgs &a, hipStream_t s);   // two kernel
 // grad E = -2 f at positions a.y into out (det gather; or atomic scatter via fbuf)
 hipError_t launch_grad_det(const StepArgs &a, float2 *out, hipStream_t s);
 hipError_t launch_grad_atomic(const StepArgs &a, float2 *out, hipStream_t s);
+
+// list the vertices with nn in-degree > kHeavyDegree (order arbitrary); *count must be zero
+hipError_t launch_heavy_list(const int32_t *nn_ptr, int64_t M, int32_t *list, int32_t *count,
+                             hipStream_t s);
 
 // ---- reduce.hip ----
 // FP64 stress: per-block partial sums (fixed tree), then one block in fixed order.

@@ -67,7 +67,7 @@ CONFIGS = {
     "C2": Config("C2", 2, 70_000, 784, 10, 16.0, 1.0, "equal", 0.0, True,
                  nn=5, rn=1, R=0, T=2000, c=0.01, a=0.9, b=0.01),
     "C3": Config("C3", 3, 1_400_000, 100, 50, 16.0, 1.0, "zipf", 1.1, False,
-                 nn=2, rn=1, R=100, T=2000, c=0.1, a=0.9, b=0.01),
+                 nn=2, rn=1, R=100, T=2000, c=0.1, a=0.9, b=0.002),
     "C4": Config("C4", 4, 1_000_000, 64, 8, 16.0, 1.0, "equal", 0.0, False,
                  nn=5, rn=1, R=0, T=0, c=0.1, a=0.9, b=0.01),
     "C5": Config("C5", 5, 1_000_000, 784, 20, 16.0, 1.0, "equal", 0.0, True,
