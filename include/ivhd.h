@@ -134,6 +134,42 @@ int ivhd_set_graphs(ivhd_ctx *ctx, int32_t enable);
  * Synchronises the stream.  NULL is accepted.                               */
 int ivhd_destroy(ivhd_ctx *ctx);
 
+/* ---- the stress as a differentiable function of the layout ---------------
+ * An edge plan holds the transposed lists of caller-given nn and rn edge
+ * lists so that the stress E(Y) of Eq. ivhd_cost_function and its gradient
+ * can be evaluated for many layouts Y (a loss for gradient-based training).
+ * The plan keeps the caller's index pointers: they must stay valid and
+ * unchanged while the plan lives. */
+typedef struct ivhd_edges ivhd_edges;   /* opaque */
+
+/* ivhd_edges_create: d_nn_idx int32 [M][nn] (-1 = absent slot), d_rn_idx
+ * int32 [M][rn] (every entry in [0, M)), rn may be 0 (d_rn_idx ignored).
+ * Entries equal to their own row are rejected (IVHD_EINVAL).  Synchronises
+ * the stream.                                                              */
+int ivhd_edges_create(ivhd_edges **out, int64_t M, const int32_t *d_nn_idx, int32_t nn,
+                      const int32_t *d_rn_idx, int32_t rn, void *stream);
+
+/* ivhd_edges_stress: *d_E (device double) = E(Y) accumulated in FP64 from the
+ * FP32 layout d_y [M][2], fixed-order reduction.  Asynchronous.             */
+int ivhd_edges_stress(ivhd_edges *e, const float *d_y, float c, double *d_E);
+
+/* ivhd_edges_grad: d_grad [M][2] = s * grad E(Y) in FP32, s = *d_scale (a
+ * device float, e.g. the upstream gradient of a loss) or 1 when d_scale is
+ * NULL.  Each vertex gathers its out- and in-edges in a fixed order (no
+ * atomics; bitwise reproducible).  eps guards the rn unit vector.  Async.   */
+int ivhd_edges_grad(ivhd_edges *e, const float *d_y, float c, float eps, const float *d_scale,
+                    float *d_grad);
+
+/* ivhd_edges_destroy: synchronises the plan's stream and frees it.         */
+int ivhd_edges_destroy(ivhd_edges *e);
+
+/* ivhd_grad_edges: one-shot gradient (plan created, used and destroyed):
+ * d_grad = grad E(Y); if h_E is not NULL also *h_E = E(Y) (FP64).
+ * Synchronises the stream.                                                 */
+int ivhd_grad_edges(const float *d_y, int64_t M, const int32_t *d_nn_idx, int32_t nn,
+                    const int32_t *d_rn_idx, int32_t rn, float c, float eps, float *d_grad,
+                    double *h_E, void *stream);
+
 /* ---- input preparation: exact kNN graph (brute force, FP32) ------------- */
 
 /* ivhd_knn_build: the nn nearest neighbours of every row of X, the kNN graph

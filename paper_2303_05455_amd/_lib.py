@@ -39,6 +39,11 @@ SIGNATURES = {
     "ivhd_get_iteration": (i32, [vp, ctypes.POINTER(i64)]),
     "ivhd_set_graphs": (i32, [vp, i32]),
     "ivhd_destroy": (i32, [vp]),
+    "ivhd_edges_create": (i32, [ctypes.POINTER(vp), i64, vp, i32, vp, i32, vp]),
+    "ivhd_edges_stress": (i32, [vp, vp, f32, vp]),
+    "ivhd_edges_grad": (i32, [vp, vp, f32, f32, vp, vp]),
+    "ivhd_edges_destroy": (i32, [vp]),
+    "ivhd_grad_edges": (i32, [vp, i64, vp, i32, vp, i32, f32, f32, vp, ctypes.POINTER(f64), vp]),
     "ivhd_knn_build": (i32, [vp, i64, i32, i32, vp, vp]),
     "ivhd_knn_query": (i32, [vp, i64, i32, vp, i64, vp, i32, vp, vp, vp]),
     "ivhd_last_error": (ctypes.c_char_p, []),

@@ -20,7 +20,8 @@ MODES = {"det": 0, "atomic": 1}
 __all__ = [
     "IvhdError", "Context", "make_params", "ivhd_init", "ivhd_step", "ivhd_stress", "ivhd_grad",
     "ivhd_get_rn", "ivhd_get_in_edges", "ivhd_get_iteration", "ivhd_set_graphs", "ivhd_destroy", "ivhd_last_error",
-    "ivhd_version", "ivhd_knn_build", "ivhd_knn_query",
+    "ivhd_version", "ivhd_knn_build", "ivhd_knn_query", "ivhd_edges_create", "ivhd_edges_stress",
+    "ivhd_edges_grad", "ivhd_edges_destroy", "ivhd_grad_edges",
 ]
 
 
@@ -107,6 +108,57 @@ def ivhd_set_graphs(ctx, enable: bool) -> None:
 
 def ivhd_destroy(ctx) -> None:
     check(_lib.load().ivhd_destroy(ctx))
+
+
+def ivhd_edges_create(nn_idx: torch.Tensor, rn_idx: Optional[torch.Tensor] = None,
+                      stream: Optional[torch.cuda.Stream] = None) -> ctypes.c_void_p:
+    M, nn = nn_idx.shape
+    p_nn = _dev(nn_idx, torch.int32, (M, nn), "nn_idx")
+    rn, p_rn = 0, None
+    if rn_idx is not None and rn_idx.numel():
+        rn = rn_idx.shape[1]
+        p_rn = _dev(rn_idx, torch.int32, (M, rn), "rn_idx")
+    h = ctypes.c_void_p()
+    check(_lib.load().ivhd_edges_create(ctypes.byref(h), M, p_nn, nn, p_rn, rn, _stream_handle(stream)))
+    return h
+
+
+def ivhd_edges_stress(plan, y: torch.Tensor, c: float, out: torch.Tensor) -> torch.Tensor:
+    _dev(out, torch.float64, tuple(out.shape), "out")
+    check(_lib.load().ivhd_edges_stress(plan, _dev(y, torch.float32, tuple(y.shape), "y"), float(c),
+                                        out.data_ptr()))
+    return out
+
+
+def ivhd_edges_grad(plan, y: torch.Tensor, c: float, eps: float, scale: Optional[torch.Tensor],
+                    out: torch.Tensor) -> torch.Tensor:
+    p_s = None if scale is None else _dev(scale, torch.float32, tuple(scale.shape), "scale")
+    check(_lib.load().ivhd_edges_grad(plan, _dev(y, torch.float32, tuple(y.shape), "y"), float(c),
+                                      float(eps), p_s, _dev(out, torch.float32, tuple(y.shape), "out")))
+    return out
+
+
+def ivhd_edges_destroy(plan) -> None:
+    check(_lib.load().ivhd_edges_destroy(plan))
+
+
+def ivhd_grad_edges(y: torch.Tensor, nn_idx: torch.Tensor, rn_idx: Optional[torch.Tensor], c: float,
+                    eps: float = 1e-12, out: Optional[torch.Tensor] = None, with_stress: bool = False,
+                    stream: Optional[torch.cuda.Stream] = None):
+    M, nn = nn_idx.shape
+    p_y = _dev(y, torch.float32, (M, 2), "y")
+    p_nn = _dev(nn_idx, torch.int32, (M, nn), "nn_idx")
+    rn, p_rn = 0, None
+    if rn_idx is not None and rn_idx.numel():
+        rn = rn_idx.shape[1]
+        p_rn = _dev(rn_idx, torch.int32, (M, rn), "rn_idx")
+    if out is None:
+        out = torch.empty_like(y)
+    E = ctypes.c_double()
+    check(_lib.load().ivhd_grad_edges(p_y, M, p_nn, nn, p_rn, rn, float(c), float(eps),
+                                      _dev(out, torch.float32, (M, 2), "out"),
+                                      ctypes.byref(E) if with_stress else None, _stream_handle(stream)))
+    return (out, E.value) if with_stress else out
 
 
 def ivhd_knn_build(x: torch.Tensor, k: int, out: Optional[torch.Tensor] = None,

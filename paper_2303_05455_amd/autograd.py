@@ -1,0 +1,84 @@
+"""The IVHD stress as a differentiable loss.
+
+E(Y) = sum_i [ sum_{j in O_nn(i)} |y_i - y_j|^2 + c sum_{k in O_rn(i)} (1 - |y_i - y_k|)^2 ]
+(Eq. ivhd_cost_function).  Forward: FP64 accumulation on the GPU, returned as
+an FP32 scalar loss (the FP64 value stays available as ``.last_stress``).
+Backward: the hand-written gather kernel of libivhd, scaled on the device by
+the upstream gradient (no host synchronisation).
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import torch
+
+from . import api
+
+
+class StressEdges:
+    """An edge plan: transposed lists of fixed nn / rn edge lists, reused by
+    every forward and backward call.  Keeps the index tensors alive."""
+
+    def __init__(self, nn_idx: torch.Tensor, rn_idx: Optional[torch.Tensor] = None, *,
+                 c: float = 0.1, eps: float = 1e-12):
+        self.nn_idx = nn_idx.contiguous()
+        self.rn_idx = None if rn_idx is None else rn_idx.contiguous()
+        self.M = nn_idx.shape[0]
+        self.c, self.eps = float(c), float(eps)
+        self._h = None
+        self._h = api.ivhd_edges_create(self.nn_idx, self.rn_idx)
+        self._E = torch.zeros((), dtype=torch.float64, device=nn_idx.device)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise api.IvhdError(-4, "edge plan is closed")
+        return self._h
+
+    def stress64(self, y: torch.Tensor) -> torch.Tensor:
+        """E(y) as a float64 device scalar (asynchronous)."""
+        out = torch.empty((), dtype=torch.float64, device=y.device)
+        return api.ivhd_edges_stress(self.handle, y.contiguous(), self.c, out)
+
+    def grad(self, y: torch.Tensor, scale: Optional[torch.Tensor] = None,
+             out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        y = y.contiguous()
+        if out is None:
+            out = torch.empty_like(y)
+        return api.ivhd_edges_grad(self.handle, y, self.c, self.eps, scale, out)
+
+    def close(self):
+        if self._h is not None:
+            h, self._h = self._h, None
+            api.ivhd_edges_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class IVHDStress(torch.autograd.Function):
+    """loss = IVHDStress.apply(y, edges): y float32 [M, 2] on the GPU."""
+
+    @staticmethod
+    def forward(ctx, y: torch.Tensor, edges: StressEdges):
+        if y.dtype != torch.float32 or y.dim() != 2 or y.shape[1] != 2:
+            raise TypeError("y must be float32 [M, 2]")
+        y = y.contiguous()
+        E64 = edges.stress64(y)
+        edges.last_stress = E64
+        ctx.edges = edges
+        ctx.save_for_backward(y)
+        return E64.to(torch.float32)
+
+    @staticmethod
+    def backward(ctx, g: torch.Tensor):
+        (y,) = ctx.saved_tensors
+        scale = g.detach().to(torch.float32).reshape(1).contiguous()
+        return ctx.edges.grad(y, scale), None
+
+
+def ivhd_stress_loss(y: torch.Tensor, edges: StressEdges) -> torch.Tensor:
+    return IVHDStress.apply(y, edges)

@@ -27,13 +27,13 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
   return z ^ (z >> 31);
 }
 
-__global__ void validate_nn_kernel(const int32_t *__restrict__ nn_idx, int64_t M, int nn,
-                                   int32_t *flags) {
+__global__ void validate_idx_kernel(const int32_t *__restrict__ idx, int64_t M, int k, int32_t lo,
+                                    int32_t *flags) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= M * nn) return;
-  int64_t i = e / nn;
-  int64_t j = nn_idx[e];
-  if (j < -1 || j >= M || j == i) flags[FLAG_BAD_INDEX] = 1;
+  if (e >= M * k) return;
+  int64_t i = e / k;
+  int64_t j = idx[e];
+  if (j < lo || j >= M || j == i) flags[FLAG_BAD_INDEX] = 1;
 }
 
 __global__ void fill_i32_kernel(int32_t *p, int64_t n, int32_t value) {
@@ -227,8 +227,10 @@ __global__ void __launch_bounds__(kBlock) sort_big_kernel(const int32_t *__restr
 
 }  // namespace
 
-hipError_t launch_validate_nn(const int32_t *nn_idx, int64_t M, int nn, int32_t *flags, hipStream_t s) {
-  validate_nn_kernel<<<grid_for(M * nn), kBlock, 0, s>>>(nn_idx, M, nn, flags);
+hipError_t launch_validate_idx(const int32_t *idx, int64_t M, int k, int32_t lo, int32_t *flags,
+                              hipStream_t s) {
+  if (k == 0) return hipSuccess;
+  validate_idx_kernel<<<grid_for(M * k), kBlock, 0, s>>>(idx, M, k, lo, flags);
   return hipGetLastError();
 }
 

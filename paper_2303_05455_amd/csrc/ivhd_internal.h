@@ -41,7 +41,8 @@ struct CscScratch {
 };
 
 // ---- graph.hip ----
-hipError_t launch_validate_nn(const int32_t *nn_idx, int64_t M, int nn, int32_t *flags, hipStream_t s);
+// flags[FLAG_BAD_INDEX] = 1 if an entry is outside [lo, M) or equals its row (lo = -1 allows absent slots)
+hipError_t launch_validate_idx(const int32_t *idx, int64_t M, int k, int32_t lo, int32_t *flags, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t value, hipStream_t s);
 // Begins a random-neighbour epoch: epoch += 1; when cnt != NULL zeroes cnt[0..M] and flags[FLAG_BIG_COUNT].
 hipError_t launch_epoch_begin(int64_t *epoch, int32_t *cnt, int64_t M, int32_t *flags, hipStream_t s);
@@ -68,6 +69,7 @@ struct StepArgs {
   const int32_t *rn_ptr, *rn_src;   // CSC of rn edges
   float2 *fbuf;           // atomic mode accumulator [M]
   int32_t *flags;
+  const float *gscale;    // gradient kernels: output scaled by *gscale (NULL = 1)
   const int32_t *heavy;   // vertices whose nn in-degree exceeds kHeavyDegree
   int32_t n_heavy;
   int32_t heavy_blocks;   // leading blocks of a launch that serve the heavy vertices

@@ -127,7 +127,8 @@ __device__ __forceinline__ void apply_update(const StepArgs &A, int64_t i, float
   if (!(isfinite(yn.x) && isfinite(yn.y))) A.flags[FLAG_NONFINITE] = 1;
 }
 
-// GRAD = false: one iteration (force + update); GRAD = true: out = grad E = -2 f
+// GRAD = false: one iteration (force + update); GRAD = true: out = s grad E = -2 s f
+// with s = *gscale (1 when NULL)
 template <bool GRAD>
 __global__ void __launch_bounds__(kBlock) det_kernel(StepArgs A, float2 *out) {
   if ((int32_t)blockIdx.x < A.heavy_blocks) {
@@ -138,8 +139,12 @@ __global__ void __launch_bounds__(kBlock) det_kernel(StepArgs A, float2 *out) {
     const float2 yi = A.y[i];
     const float2 f = heavy_force(A, i, yi, lane);
     if (lane == 0) {
-      if (GRAD) out[i] = make_float2(-2.f * f.x, -2.f * f.y);
-      else apply_update(A, i, yi, f);
+      if (GRAD) {
+        const float g = -2.f * (A.gscale ? *A.gscale : 1.f);
+        out[i] = make_float2(g * f.x, g * f.y);
+      } else {
+        apply_update(A, i, yi, f);
+      }
     }
     return;
   }
@@ -149,8 +154,12 @@ __global__ void __launch_bounds__(kBlock) det_kernel(StepArgs A, float2 *out) {
   if (ne - ns > kHeavyDegree) return;   // served by a heavy wavefront
   const float2 yi = A.y[i];
   const float2 f = light_force(A, i, yi, ns, ne);
-  if (GRAD) out[i] = make_float2(-2.f * f.x, -2.f * f.y);
-  else apply_update(A, i, yi, f);
+  if (GRAD) {
+    const float g = -2.f * (A.gscale ? *A.gscale : 1.f);
+    out[i] = make_float2(g * f.x, g * f.y);
+  } else {
+    apply_update(A, i, yi, f);
+  }
 }
 
 __global__ void heavy_list_kernel(const int32_t *__restrict__ nn_ptr, int64_t M, int32_t *list,
@@ -194,12 +203,14 @@ __global__ void __launch_bounds__(kBlock) atomic_update_kernel(StepArgs A) {
   apply_update(A, i, A.y[i], f);
 }
 
-__global__ void __launch_bounds__(kBlock) atomic_grad_out_kernel(float2 *fbuf, int64_t M, float2 *out) {
+__global__ void __launch_bounds__(kBlock) atomic_grad_out_kernel(float2 *fbuf, int64_t M, const float *gscale,
+                                                                float2 *out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M) return;
   const float2 f = fbuf[i];
   fbuf[i] = make_float2(0.f, 0.f);
-  out[i] = make_float2(-2.f * f.x, -2.f * f.y);
+  const float g = -2.f * (gscale ? *gscale : 1.f);
+  out[i] = make_float2(g * f.x, g * f.y);
 }
 
 unsigned det_grid(const StepArgs &a) { return (unsigned)a.heavy_blocks + grid_for(a.M); }
@@ -230,7 +241,7 @@ hipError_t launch_grad_det(const StepArgs &a, float2 *out, hipStream_t s) {
 
 hipError_t launch_grad_atomic(const StepArgs &a, float2 *out, hipStream_t s) {
   scatter_force_kernel<<<grid_for(a.M), kBlock, 0, s>>>(a);
-  atomic_grad_out_kernel<<<grid_for(a.M), kBlock, 0, s>>>(a.fbuf, a.M, out);
+  atomic_grad_out_kernel<<<grid_for(a.M), kBlock, 0, s>>>(a.fbuf, a.M, a.gscale, out);
   return hipGetLastError();
 }
 
