@@ -142,8 +142,8 @@ int ivhd_destroy(ivhd_ctx *ctx);
  * unchanged while the plan lives. */
 typedef struct ivhd_edges ivhd_edges;   /* opaque */
 
-/* ivhd_edges_create: d_nn_idx int32 [M][nn] (-1 = absent slot), d_rn_idx
- * int32 [M][rn] (every entry in [0, M)), rn may be 0 (d_rn_idx ignored).
+/* ivhd_edges_create: d_nn_idx int32 [M][nn], d_rn_idx int32 [M][rn] (-1 =
+ * absent slot in either), rn may be 0 (d_rn_idx ignored).
  * Entries equal to their own row are rejected (IVHD_EINVAL).  Synchronises
  * the stream.                                                              */
 int ivhd_edges_create(ivhd_edges **out, int64_t M, const int32_t *d_nn_idx, int32_t nn,
@@ -193,6 +193,74 @@ int ivhd_knn_build(const float *d_x, int64_t M, int32_t N, int32_t k, int32_t *d
 int ivhd_knn_query(const float *d_x, int64_t M, int32_t N, const float *d_q, int64_t Q,
                    const int32_t *d_self, int32_t k, int32_t *d_idx, float *d_dist,
                    void *stream);
+
+/* ---- parametric encoder --------------------------------------------------
+ * A learned map N-D -> 2-D: MLP n_in -> h1 -> h2 -> 2 with ReLU, trained on
+ * the IVHD stress of its own batches' edges, so that new points are placed
+ * in one forward pass.  (Not in the thesis; its MLP conventions follow the
+ * network-inspection chapter: ReLU layers, Glorot-uniform initialisation.)
+ * BF16 weights and activations on the matrix cores with FP32 accumulation;
+ * FP32 master weights and Adam state (beta1 = 0.9, beta2 = 0.999,
+ * eps = 1e-8, bias correction 1/(1 - beta^t)).  Every FP32 -> BF16
+ * conversion rounds to nearest even; ReLU is applied in FP32 before it; the
+ * output Z stays FP32.
+ * Parameter layout (FP32, flat): W1 [h1][n_in], b1 [h1], W2 [h2][h1],
+ * b2 [h2], W3 [2][h2], b3 [2].                                             */
+typedef struct ivhd_enc ivhd_enc;   /* opaque */
+
+/* ivhd_enc_create: Glorot-uniform weights (s = sqrt(6/(fan_in+fan_out)))
+ * from `seed`, zero biases.  h1, h2 multiples of 8.  max_rows bounds the
+ * rows of one forward/training call (activation buffers are sized for it).
+ * Synchronises the stream.                                                 */
+int ivhd_enc_create(ivhd_enc **out, int32_t n_in, int32_t h1, int32_t h2, uint64_t seed,
+                    int64_t max_rows, void *stream);
+int ivhd_enc_num_params(const ivhd_enc *e, int64_t *h_n);
+/* copy the FP32 parameters and/or the last step's (unscaled) gradients into
+ * device buffers of ivhd_enc_num_params floats (either may be NULL).       */
+int ivhd_enc_get_params(ivhd_enc *e, float *d_params, float *d_grads);
+/* load FP32 parameters (device); resets the Adam state.                    */
+int ivhd_enc_set_params(ivhd_enc *e, const float *d_params);
+
+/* ivhd_enc_embed: d_z float32 [rows][2] = the network applied to d_x16
+ * (BF16 [rows][n_in], row-major).  Asynchronous.                           */
+int ivhd_enc_embed(ivhd_enc *e, const uint16_t *d_x16, int64_t rows, float *d_z);
+
+/* ivhd_enc_train_step: one Adam step on a batch of R rows (BF16
+ * [R][n_in]) whose local edge lists are the plan's (indices into the R
+ * rows): loss = loss_scale * E_batch(Z); gradients of E_batch are scaled
+ * by loss_scale before Adam.  *d_loss (device double, may be NULL) gets
+ * E_batch.  Asynchronous.                                                  */
+int ivhd_enc_train_step(ivhd_enc *e, const uint16_t *d_xb16, int64_t R, ivhd_edges *plan, float c,
+                        float eps, float lr, float loss_scale, double *d_loss);
+
+/* ivhd_enc_train_epoch: one pass over M training points (BF16 [M][n_in])
+ * in batches of `batch` sources visited in the order (a b + c0) mod M
+ * (gcd(a, M) = 1, both drawn from seed and epoch).  A batch forwards its
+ * sources, their nn targets (d_nn_idx [M][nn]; an absent slot repeats the
+ * source) and their rn targets (drawn for this epoch exactly as the loop
+ * draws epoch `epoch`), and takes one Adam step on the mean per-source
+ * stress of those edges.  batch * (1 + nn + rn) <= max_rows.  *h_loss =
+ * mean over steps of that loss.  Synchronises the stream.                  */
+int ivhd_enc_train_epoch(ivhd_enc *e, const uint16_t *d_x16, int64_t M, const int32_t *d_nn_idx,
+                         int32_t nn, int32_t rn, uint64_t seed, int64_t epoch, int64_t batch,
+                         float c, float eps, float lr, double *h_loss);
+int ivhd_enc_destroy(ivhd_enc *e);
+
+/* ivhd_f32_to_bf16: d_y[i] = round-to-nearest-even BF16 of d_x[i].  Async. */
+int ivhd_f32_to_bf16(const float *d_x, int64_t n, uint16_t *d_y, void *stream);
+
+/* ivhd_gemm_bf16: C[M][N] = sum_k opA[m][k] opB[k][n] on the matrix cores,
+ * BF16 operands, FP32 accumulation.
+ *   opA[m][k] = trans_a ? A[k*lda + m] : A[m*lda + k]
+ *   opB[k][n] = trans_b ? B[n*ldb + k] : B[k*ldb + n]
+ * epilogue 0: C FP32;  1: C BF16 = relu(acc + bias[n]) (bias may be NULL);
+ *          2: C BF16 = acc if mask[m*ldm + n] > 0 else 0 (ReLU derivative).
+ * splits > 1 splits K (epilogue 0 only): FP32 partials go to d_work
+ * [splits][M][N] and are added in split order into C.  Asynchronous.      */
+int ivhd_gemm_bf16(const uint16_t *d_a, const uint16_t *d_b, int64_t M, int64_t N, int64_t K,
+                   int64_t lda, int64_t ldb, int32_t trans_a, int32_t trans_b, int32_t epilogue,
+                   const float *d_bias, const uint16_t *d_mask, int64_t ldm, void *d_c, int64_t ldc,
+                   int32_t splits, float *d_work, void *stream);
 
 /* ivhd_last_error: message of the last failure on this thread ("" if none). */
 const char *ivhd_last_error(void);

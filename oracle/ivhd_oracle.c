@@ -97,6 +97,7 @@ void orc_force(int64_t M, const double *Y, int32_t nn, const int32_t *nn_idx,
         }
         for (int32_t q = 0; q < rn; ++q) {
             int64_t k = rn_idx[i * rn + q];
+            if (k < 0) continue;                      /* absent slot */
             double dx = Y[2 * i] - Y[2 * k];
             double dy = Y[2 * i + 1] - Y[2 * k + 1];
             double d = sqrt(dx * dx + dy * dy);
@@ -122,6 +123,7 @@ double orc_stress(int64_t M, const double *Y, int32_t nn, const int32_t *nn_idx,
         }
         for (int32_t q = 0; q < rn; ++q) {
             int64_t k = rn_idx[i * rn + q];
+            if (k < 0) continue;
             double dx = Y[2 * i] - Y[2 * k];
             double dy = Y[2 * i + 1] - Y[2 * k + 1];
             double d = sqrt(dx * dx + dy * dy);

@@ -44,6 +44,18 @@ SIGNATURES = {
     "ivhd_edges_grad": (i32, [vp, vp, f32, f32, vp, vp]),
     "ivhd_edges_destroy": (i32, [vp]),
     "ivhd_grad_edges": (i32, [vp, i64, vp, i32, vp, i32, f32, f32, vp, ctypes.POINTER(f64), vp]),
+    "ivhd_enc_create": (i32, [ctypes.POINTER(vp), i32, i32, i32, u64, i64, vp]),
+    "ivhd_enc_num_params": (i32, [vp, ctypes.POINTER(i64)]),
+    "ivhd_enc_get_params": (i32, [vp, vp, vp]),
+    "ivhd_enc_set_params": (i32, [vp, vp]),
+    "ivhd_enc_embed": (i32, [vp, vp, i64, vp]),
+    "ivhd_enc_train_step": (i32, [vp, vp, i64, vp, f32, f32, f32, f32, vp]),
+    "ivhd_enc_train_epoch": (i32, [vp, vp, i64, vp, i32, i32, u64, i64, i64, f32, f32, f32,
+                                   ctypes.POINTER(f64)]),
+    "ivhd_enc_destroy": (i32, [vp]),
+    "ivhd_f32_to_bf16": (i32, [vp, i64, vp, vp]),
+    "ivhd_gemm_bf16": (i32, [vp, vp, i64, i64, i64, i64, i64, i32, i32, i32, vp, vp, i64, vp, i64, i32,
+                             vp, vp]),
     "ivhd_knn_build": (i32, [vp, i64, i32, i32, vp, vp]),
     "ivhd_knn_query": (i32, [vp, i64, i32, vp, i64, vp, i32, vp, vp, vp]),
     "ivhd_last_error": (ctypes.c_char_p, []),

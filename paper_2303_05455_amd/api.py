@@ -276,3 +276,97 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+# ---- parametric encoder --------------------------------------------------
+
+def ivhd_f32_to_bf16(x: torch.Tensor, out: Optional[torch.Tensor] = None,
+                     stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """BF16 (round to nearest even) of an FP32 tensor, as int16 storage of the bits."""
+    x = x.contiguous()
+    _dev(x, torch.float32, tuple(x.shape), "x")
+    if out is None:
+        out = torch.empty(x.shape, dtype=torch.int16, device=x.device)
+    _dev(out, torch.int16, tuple(x.shape), "out")
+    check(_lib.load().ivhd_f32_to_bf16(x.data_ptr(), x.numel(), out.data_ptr(), _stream_handle(stream)))
+    return out
+
+
+def ivhd_gemm_bf16(a: torch.Tensor, b: torch.Tensor, M: int, N: int, K: int, *, lda: int, ldb: int,
+                   trans_a: bool = False, trans_b: bool = False, epilogue: int = 0,
+                   bias: Optional[torch.Tensor] = None, mask: Optional[torch.Tensor] = None,
+                   ldm: int = 0, out: Optional[torch.Tensor] = None, ldc: Optional[int] = None,
+                   splits: int = 1, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """C = opA @ opB on BF16 bit tensors (int16 storage); see include/ivhd.h."""
+    ldc = N if ldc is None else ldc
+    if out is None:
+        out = torch.empty((M, ldc), dtype=torch.float32 if epilogue == 0 else torch.int16, device=a.device)
+    work = None
+    if splits > 1:
+        work = torch.empty((splits, M, N), dtype=torch.float32, device=a.device)
+    check(_lib.load().ivhd_gemm_bf16(a.data_ptr(), b.data_ptr(), M, N, K, lda, ldb, int(trans_a), int(trans_b),
+                                     epilogue, None if bias is None else bias.data_ptr(),
+                                     None if mask is None else mask.data_ptr(), ldm, out.data_ptr(), ldc,
+                                     splits, None if work is None else work.data_ptr(), _stream_handle(stream)))
+    return out
+
+
+def ivhd_enc_create(n_in: int, h1: int, h2: int, seed: int, max_rows: int,
+                    stream: Optional[torch.cuda.Stream] = None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    check(_lib.load().ivhd_enc_create(ctypes.byref(h), n_in, h1, h2, seed & (2**64 - 1), max_rows,
+                                      _stream_handle(stream)))
+    return h
+
+
+def ivhd_enc_num_params(enc) -> int:
+    n = ctypes.c_int64()
+    check(_lib.load().ivhd_enc_num_params(enc, ctypes.byref(n)))
+    return n.value
+
+
+def ivhd_enc_get_params(enc, params: Optional[torch.Tensor], grads: Optional[torch.Tensor] = None) -> None:
+    check(_lib.load().ivhd_enc_get_params(enc, None if params is None else params.data_ptr(),
+                                          None if grads is None else grads.data_ptr()))
+
+
+def ivhd_enc_set_params(enc, params: torch.Tensor) -> None:
+    _dev(params, torch.float32, tuple(params.shape), "params")
+    check(_lib.load().ivhd_enc_set_params(enc, params.data_ptr()))
+
+
+def ivhd_enc_embed(enc, x16: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+    rows = x16.shape[0]
+    _dev(x16, torch.int16, tuple(x16.shape), "x16")
+    _dev(out, torch.float32, (rows, 2), "out")
+    check(_lib.load().ivhd_enc_embed(enc, x16.data_ptr(), rows, out.data_ptr()))
+    return out
+
+
+def ivhd_enc_train_step(enc, xb16: torch.Tensor, plan, c: float, eps: float, lr: float, loss_scale: float,
+                        loss_out: Optional[torch.Tensor] = None) -> None:
+    _dev(xb16, torch.int16, tuple(xb16.shape), "xb16")
+    check(_lib.load().ivhd_enc_train_step(enc, xb16.data_ptr(), xb16.shape[0], plan, float(c), float(eps),
+                                          float(lr), float(loss_scale),
+                                          None if loss_out is None else loss_out.data_ptr()))
+
+
+def ivhd_enc_train_epoch(enc, x16: torch.Tensor, nn_idx: torch.Tensor, rn: int, seed: int, epoch: int,
+                         batch: int, c: float, eps: float, lr: float) -> float:
+    M, nn = nn_idx.shape
+    _dev(x16, torch.int16, tuple(x16.shape), "x16")
+    _dev(nn_idx, torch.int32, (M, nn), "nn_idx")
+    loss = ctypes.c_double()
+    check(_lib.load().ivhd_enc_train_epoch(enc, x16.data_ptr(), M, nn_idx.data_ptr(), nn, rn,
+                                           seed & (2**64 - 1), epoch, batch, float(c), float(eps), float(lr),
+                                           ctypes.byref(loss)))
+    return loss.value
+
+
+def ivhd_enc_destroy(enc) -> None:
+    check(_lib.load().ivhd_enc_destroy(enc))
+
+
+__all__ += ["ivhd_f32_to_bf16", "ivhd_gemm_bf16", "ivhd_enc_create", "ivhd_enc_num_params",
+            "ivhd_enc_get_params", "ivhd_enc_set_params", "ivhd_enc_embed", "ivhd_enc_train_step",
+            "ivhd_enc_train_epoch", "ivhd_enc_destroy"]

@@ -14,7 +14,7 @@
 
 using namespace ivhd;
 
-namespace {
+namespace ivhd {
 
 thread_local std::string g_err;
 
@@ -33,11 +33,11 @@ int hip_fail(hipError_t e, const char *what) {
               hipGetErrorString(e));
 }
 
-#define HIPCHK(expr)                                \
-  do {                                              \
-    hipError_t _e = (expr);                         \
-    if (_e != hipSuccess) return hip_fail(_e, #expr); \
-  } while (0)
+void clear_error() { g_err.clear(); }
+
+}  // namespace ivhd
+
+namespace {
 
 // contexts handed out and not yet destroyed: a stale or foreign pointer is
 // reported as IVHD_ESTATE instead of being dereferenced
@@ -78,20 +78,6 @@ struct ivhd_ctx {
 };
 
 namespace {
-
-template <typename T>
-int dev_alloc(T **p, size_t count, const char *what) {
-  *p = nullptr;
-  if (count == 0) count = 1;
-  hipError_t e = hipMalloc((void **)p, count * sizeof(T));
-  if (e != hipSuccess) {
-    *p = nullptr;
-    (void)hipGetLastError();
-    return fail(e == hipErrorOutOfMemory ? IVHD_ENOMEM : IVHD_EDEVICE,
-                "allocating %s (%zu bytes): %s", what, count * sizeof(T), hipGetErrorString(e));
-  }
-  return IVHD_OK;
-}
 
 void free_ctx(ivhd_ctx *c) {
   if (!c) return;
@@ -247,13 +233,13 @@ int build_nn_csc(ivhd_ctx *c) {
 
 extern "C" {
 
-const char *ivhd_last_error(void) { return g_err.c_str(); }
+const char *ivhd_last_error(void) { return ivhd::g_err.c_str(); }
 
 int ivhd_version(void) { return 100; }
 
 int ivhd_init(ivhd_ctx **out, const ivhd_params *p, const int32_t *d_nn_idx, float *d_y,
               float *d_v, void *stream) {
-  g_err.clear();
+  clear_error();
   if (!out) return fail(IVHD_EINVAL, "out is NULL");
   *out = nullptr;
   int rc = validate(p);
@@ -524,7 +510,7 @@ StepArgs edge_args(const ivhd_edges *e, const float2 *y, float c, float eps, con
 
 int ivhd_edges_create(ivhd_edges **out, int64_t M, const int32_t *d_nn_idx, int32_t nn,
                       const int32_t *d_rn_idx, int32_t rn, void *stream) {
-  g_err.clear();
+  clear_error();
   if (!out) return fail(IVHD_EINVAL, "out is NULL");
   *out = nullptr;
   if (M < 2 || M > (int64_t)INT32_MAX - 1) return fail(IVHD_EINVAL, "M = %lld outside [2, 2^31-2]", (long long)M);
@@ -578,13 +564,13 @@ int ivhd_edges_create(ivhd_edges **out, int64_t M, const int32_t *d_nn_idx, int3
   hipStream_t s = e->stream;
   E_HIP(launch_fill_i32(e->flags, FLAG_SLOTS, 0, s));
   E_HIP(launch_validate_idx(d_nn_idx, M, nn, -1, e->flags, s));
-  if (rn > 0) E_HIP(launch_validate_idx(d_rn_idx, M, rn, 0, e->flags, s));
+  if (rn > 0) E_HIP(launch_validate_idx(d_rn_idx, M, rn, -1, e->flags, s));
   int32_t hflags[FLAG_SLOTS];
   E_HIP(hipMemcpyAsync(hflags, e->flags, sizeof hflags, hipMemcpyDeviceToHost, s));
   E_HIP(hipStreamSynchronize(s));
   if (hflags[FLAG_BAD_INDEX]) {
     free_edges(e);
-    return fail(IVHD_EINVAL, "an nn entry is outside [-1, M), an rn entry outside [0, M), or an entry equals its row");
+    return fail(IVHD_EINVAL, "an nn or rn entry is outside [-1, M) or equals its row");
   }
   E_CHK(build_csc(d_nn_idx, M, nn, e->nn_csc, e->sc, e->flags, s));
   if (rn > 0) E_CHK(build_csc(d_rn_idx, M, rn, e->rn_csc, e->sc, e->flags, s));

@@ -1,0 +1,418 @@
+// Kernels of the parametric encoder (an MLP N-D -> 2-D trained on the IVHD
+// stress): BF16 operands on the gfx950 matrix cores with FP32 accumulation.
+//
+// gemm_bf16: C[M][N] = sum_k opA[m][k] opB[k][n]
+//   opA[m][k] = A[m*lda + k]  (ta = 0)  or  A[k*lda + m]  (ta = 1)
+//   opB[k][n] = B[k*ldb + n]  (tb = 0)  or  B[n*ldb + k]  (tb = 1)
+// Tiles of 128 x 128 per block of 256 threads (4 waves, 64 x 64 each), K in
+// steps of 32 staged in LDS with K contiguous per row, so one lane's MFMA
+// operand (8 consecutive k) is a single 16-byte LDS read.  The instruction
+// is v_mfma_f32_16x16x32_bf16: lane l supplies A[l%16][8(l/16)..+8) and
+// B[8(l/16)..+8)[l%16], and receives D[4(l/16)+r][l%16], r = 0..3.
+// Epilogues: FP32 store (split-K partials: blockIdx.z selects the K range
+// and the output slab), bias + ReLU -> BF16, or (dgrad) multiply by the
+// ReLU derivative read from the forward activation -> BF16.
+//
+// Rounding: every FP32 -> BF16 conversion is round-to-nearest-even.
+#include "enc_internal.h"
+
+namespace ivhd {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int TM = 128, TN = 128, TK = 32;
+constexpr int KP = TK + 8;   // LDS row pitch in bf16 (80 bytes: 16-byte aligned rows)
+constexpr int kGemmThreads = 256;
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+struct alignas(16) U16x8 {
+  uint16_t v[8];
+};
+
+// stage one operand tile: rows r0..r0+127 of op (row index = m or n), k0..k0+31;
+// op[row][k] = T ? P[k*ld + row] : P[row*ld + k]; out of range -> 0
+template <bool T>
+__device__ __forceinline__ void stage(uint16_t *__restrict__ lds, const uint16_t *__restrict__ P, int64_t ld,
+                                      int64_t rows, int64_t r0, int64_t k0, int64_t kend, bool vec_ok) {
+  const int tid = threadIdx.x;
+  if (!T) {
+    // 128 rows x 4 chunks of 8 k: 512 chunks, two per thread
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int id = tid + kGemmThreads * c;
+      const int r = id >> 2, kc = (id & 3) * 8;
+      const int64_t row = r0 + r, k = k0 + kc;
+      U16x8 v;
+      if (row < rows && vec_ok && k + 8 <= kend) {
+        v = *reinterpret_cast<const U16x8 *>(P + row * ld + k);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v.v[j] = (row < rows && k + j < kend) ? P[row * ld + k + j] : (uint16_t)0;
+      }
+      *reinterpret_cast<U16x8 *>(lds + r * KP + kc) = v;
+    }
+  } else {
+    // k-major source: 32 k x 16 chunks of 8 rows, two per thread, scattered into LDS
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int id = tid + kGemmThreads * c;
+      const int kk = id >> 4, rc = (id & 15) * 8;
+      const int64_t k = k0 + kk, row = r0 + rc;
+      U16x8 v;
+      if (k < kend && vec_ok && row + 8 <= rows) {
+        v = *reinterpret_cast<const U16x8 *>(P + k * ld + row);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v.v[j] = (k < kend && row + j < rows) ? P[k * ld + row + j] : (uint16_t)0;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) lds[(rc + j) * KP + kk] = v.v[j];
+    }
+  }
+}
+
+template <bool TA, bool TB, int EPI>
+__global__ void __launch_bounds__(kGemmThreads) gemm_kernel(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[TM * KP];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[TN * KP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t m0 = (int64_t)blockIdx.y * TM, n0 = (int64_t)blockIdx.x * TN;
+  const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
+  const int64_t kend = kbeg + g.kchunk < g.K ? kbeg + g.kchunk : g.K;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+
+  floatx4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  for (int64_t k0 = kbeg; k0 < kend; k0 += TK) {
+    __syncthreads();
+    stage<TA>(As, g.A, g.lda, g.M, m0, k0, kend, g.vec_a);
+    stage<TB>(Bs, g.B, g.ldb, g.N, n0, k0, kend, g.vec_b);
+    __syncthreads();
+    const int kq = (lane >> 4) * 8;
+    bf16x8 a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      a[i] = *reinterpret_cast<const bf16x8 *>(As + (wm + 16 * i + (lane & 15)) * KP + kq);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      b[j] = *reinterpret_cast<const bf16x8 *>(Bs + (wn + 16 * j + (lane & 15)) * KP + kq);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+
+  // epilogue
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t n = n0 + wn + 16 * j + (lane & 15);
+      if (n >= g.N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+        if (m >= g.M) continue;
+        float x = acc[i][j][r];
+        if (EPI == GEMM_EPI_F32) {
+          float *C = static_cast<float *>(g.C) + (int64_t)blockIdx.z * g.M * g.ldc;
+          C[m * g.ldc + n] = x;
+        } else if (EPI == GEMM_EPI_BIAS_RELU_BF16) {
+          x += g.bias ? g.bias[n] : 0.f;
+          x = fmaxf(x, 0.f);
+          static_cast<uint16_t *>(g.C)[m * g.ldc + n] = f2bf(x);
+        } else {   // GEMM_EPI_RELU_MASK_BF16
+          const float h = bf2f(g.mask[m * g.ldm + n]);
+          static_cast<uint16_t *>(g.C)[m * g.ldc + n] = f2bf(h > 0.f ? x : 0.f);
+        }
+      }
+    }
+  }
+}
+
+// sum of `splits` FP32 slabs [M][ldc] in slab order -> out (FP32, ld = ldo)
+__global__ void splitk_reduce_kernel(const float *__restrict__ part, int splits, int64_t M, int64_t N,
+                                     int64_t ldp, float *__restrict__ out, int64_t ldo) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * N) return;
+  const int64_t m = e / N, n = e % N;
+  float s = 0.f;
+  for (int z = 0; z < splits; ++z) s += part[(int64_t)z * M * ldp + m * ldp + n];
+  out[m * ldo + n] = s;
+}
+
+template <bool TA, bool TB>
+hipError_t launch_gemm_t(const GemmArgs &g, int epi, dim3 grid, hipStream_t s) {
+  switch (epi) {
+    case GEMM_EPI_F32: gemm_kernel<TA, TB, GEMM_EPI_F32><<<grid, kGemmThreads, 0, s>>>(g); break;
+    case GEMM_EPI_BIAS_RELU_BF16:
+      gemm_kernel<TA, TB, GEMM_EPI_BIAS_RELU_BF16><<<grid, kGemmThreads, 0, s>>>(g);
+      break;
+    default: gemm_kernel<TA, TB, GEMM_EPI_RELU_MASK_BF16><<<grid, kGemmThreads, 0, s>>>(g); break;
+  }
+  return hipGetLastError();
+}
+
+// ---- small kernels around the GEMMs -------------------------------------
+
+__global__ void f32_to_bf16_kernel(const float *__restrict__ x, int64_t n, uint16_t *__restrict__ y) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) y[e] = f2bf(x[e]);
+}
+
+// out[r][:] = X[rows[r]][:] (BF16 rows of width N)
+__global__ void gather_rows_kernel(const uint16_t *__restrict__ X, int64_t N, const int32_t *__restrict__ rows,
+                                   int64_t R, uint16_t *__restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= R * N) return;
+  const int64_t r = e / N, k = e % N;
+  out[e] = X[(int64_t)rows[r] * N + k];
+}
+
+// Z[r][o] = b3[o] + sum_k H[r][k] W3[o][k], o < 2 (one wavefront per row)
+__global__ void __launch_bounds__(256) head_forward_kernel(const uint16_t *__restrict__ H, int64_t R, int K,
+                                                           const uint16_t *__restrict__ W3,
+                                                           const float *__restrict__ b3, float *__restrict__ Z) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= R) return;
+  float s0 = 0.f, s1 = 0.f;
+  for (int k = lane; k < K; k += 64) {
+    const float h = bf2f(H[r * K + k]);
+    s0 += h * bf2f(W3[k]);
+    s1 += h * bf2f(W3[K + k]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    s0 += __shfl_xor(s0, o, 64);
+    s1 += __shfl_xor(s1, o, 64);
+  }
+  if (lane == 0) {
+    Z[2 * r] = s0 + b3[0];
+    Z[2 * r + 1] = s1 + b3[1];
+  }
+}
+
+// dH[r][k] = (dZ[r][0] W3[0][k] + dZ[r][1] W3[1][k]) * [H[r][k] > 0]  -> BF16
+__global__ void head_dgrad_kernel(const float *__restrict__ dZ, const uint16_t *__restrict__ W3,
+                                  const uint16_t *__restrict__ H, int64_t R, int K, uint16_t *__restrict__ dH) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= R * K) return;
+  const int64_t r = e / K;
+  const int k = (int)(e % K);
+  const float g = dZ[2 * r] * bf2f(W3[k]) + dZ[2 * r + 1] * bf2f(W3[K + k]);
+  dH[e] = f2bf(bf2f(H[e]) > 0.f ? g : 0.f);
+}
+
+// column sums over row chunks: part[c][j] = sum_{r in chunk c} f(r, j) for
+//   mode 0: BF16 matrix X[R][J]           (bias gradients of the hidden layers)
+//   mode 1: dZ (FP32 [R][2]) x H (BF16 [R][K]): j = o*K + k -> dZ[r][o] H[r][k]  (dW3)
+//   mode 2: FP32 matrix [R][J]            (bias gradient of the head)
+__global__ void colsum_kernel(int mode, const void *__restrict__ Xp, const float *__restrict__ dZ,
+                              int64_t R, int64_t J, int64_t K, int64_t rows_per_chunk,
+                              float *__restrict__ part) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= J) return;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per_chunk;
+  const int64_t r1 = r0 + rows_per_chunk < R ? r0 + rows_per_chunk : R;
+  float s = 0.f;
+  if (mode == 0) {
+    const uint16_t *X = static_cast<const uint16_t *>(Xp);
+    for (int64_t r = r0; r < r1; ++r) s += bf2f(X[r * J + j]);
+  } else if (mode == 1) {
+    const uint16_t *H = static_cast<const uint16_t *>(Xp);
+    const int64_t o = j / K, k = j % K;
+    for (int64_t r = r0; r < r1; ++r) s += dZ[2 * r + o] * bf2f(H[r * K + k]);
+  } else {
+    const float *X = static_cast<const float *>(Xp);
+    for (int64_t r = r0; r < r1; ++r) s += X[r * J + j];
+  }
+  part[(int64_t)blockIdx.y * J + j] = s;
+}
+
+__global__ void chunk_reduce_kernel(const float *__restrict__ part, int chunks, int64_t J, float *__restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= J) return;
+  float s = 0.f;
+  for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * J + j];
+  out[j] = s;
+}
+
+// Adam with bias correction 1/(1 - beta^t); refreshes the BF16 copy
+__global__ void adam_kernel(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
+                            float *__restrict__ v, uint16_t *__restrict__ w16, int64_t n, float lr, float b1,
+                            float b2, float eps, float c1, float c2, float gscale) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const float gr = g[e] * gscale;
+  const float mm = b1 * m[e] + (1.f - b1) * gr;
+  const float vv = b2 * v[e] + (1.f - b2) * gr * gr;
+  m[e] = mm;
+  v[e] = vv;
+  const float wn = w[e] - lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+  w[e] = wn;
+  w16[e] = f2bf(wn);
+}
+
+// Glorot-uniform weights U(-s, s), s = sqrt(6 / (fan_in + fan_out)), from a
+// SplitMix64 counter stream; biases zero
+__global__ void glorot_kernel(float *__restrict__ w, int64_t n, int fan_in, int fan_out, uint64_t seed,
+                              uint64_t offset) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  uint64_t z = seed ^ (offset + (uint64_t)e) * 0x9e3779b97f4a7c15ull;
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  z ^= z >> 31;
+  const float u = (float)(z >> 40) * (1.0f / 16777216.0f);   // [0, 1)
+  const float s = sqrtf(6.0f / (float)(fan_in + fan_out));
+  w[e] = (2.f * u - 1.f) * s;
+}
+
+__global__ void scale_dz_kernel(float *__restrict__ dz, int64_t n, const float *__restrict__ s) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) dz[e] *= *s;
+}
+
+}  // namespace
+
+hipError_t launch_gemm_bf16(const GemmArgs &g0, int ta, int tb, int epi, int splits, hipStream_t s) {
+  GemmArgs g = g0;
+  if (splits < 1) splits = 1;
+  g.kchunk = ((g.K + splits - 1) / splits + TK - 1) / TK * TK;
+  if (g.kchunk < TK) g.kchunk = TK;
+  splits = (int)((g.K + g.kchunk - 1) / g.kchunk);
+  if (splits < 1) splits = 1;
+  dim3 grid((unsigned)((g.N + TN - 1) / TN), (unsigned)((g.M + TM - 1) / TM), (unsigned)splits);
+  if (!ta && !tb) return launch_gemm_t<false, false>(g, epi, grid, s);
+  if (!ta && tb) return launch_gemm_t<false, true>(g, epi, grid, s);
+  if (ta && !tb) return launch_gemm_t<true, false>(g, epi, grid, s);
+  return launch_gemm_t<true, true>(g, epi, grid, s);
+}
+
+int gemm_splits_used(int64_t K, int splits) {
+  if (splits < 1) splits = 1;
+  int64_t kchunk = ((K + splits - 1) / splits + TK - 1) / TK * TK;
+  if (kchunk < TK) kchunk = TK;
+  const int64_t used = (K + kchunk - 1) / kchunk;
+  return (int)(used < 1 ? 1 : used);
+}
+
+hipError_t launch_splitk_reduce(const float *part, int splits, int64_t M, int64_t N, int64_t ldp, float *out,
+                                int64_t ldo, hipStream_t s) {
+  splitk_reduce_kernel<<<grid_for(M * N), kBlock, 0, s>>>(part, splits, M, N, ldp, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_f32_to_bf16(const float *x, int64_t n, uint16_t *y, hipStream_t s) {
+  f32_to_bf16_kernel<<<grid_for(n), kBlock, 0, s>>>(x, n, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(const uint16_t *X, int64_t N, const int32_t *rows, int64_t R, uint16_t *out,
+                              hipStream_t s) {
+  gather_rows_kernel<<<grid_for(R * N), kBlock, 0, s>>>(X, N, rows, R, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_head_forward(const uint16_t *H, int64_t R, int K, const uint16_t *W3, const float *b3, float *Z,
+                               hipStream_t s) {
+  head_forward_kernel<<<grid_for(R, 4), 256, 0, s>>>(H, R, K, W3, b3, Z);
+  return hipGetLastError();
+}
+
+hipError_t launch_head_dgrad(const float *dZ, const uint16_t *W3, const uint16_t *H, int64_t R, int K,
+                             uint16_t *dH, hipStream_t s) {
+  head_dgrad_kernel<<<grid_for(R * K), kBlock, 0, s>>>(dZ, W3, H, R, K, dH);
+  return hipGetLastError();
+}
+
+hipError_t launch_colsum(int mode, const void *X, const float *dZ, int64_t R, int64_t J, int64_t K,
+                         float *part, int chunks, float *out, hipStream_t s) {
+  const int64_t rpc = (R + chunks - 1) / chunks;
+  dim3 grid(grid_for(J), (unsigned)chunks);
+  colsum_kernel<<<grid, kBlock, 0, s>>>(mode, X, dZ, R, J, K, rpc < 1 ? 1 : rpc, part);
+  chunk_reduce_kernel<<<grid_for(J), kBlock, 0, s>>>(part, chunks, J, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float *w, const float *g, float *m, float *v, uint16_t *w16, int64_t n, float lr, float b1,
+                       float b2, float eps, int64_t t, float gscale, hipStream_t s) {
+  const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+  adam_kernel<<<grid_for(n), kBlock, 0, s>>>(w, g, m, v, w16, n, lr, b1, b2, eps, c1, c2, gscale);
+  return hipGetLastError();
+}
+
+hipError_t launch_glorot(float *w, int64_t n, int fan_in, int fan_out, uint64_t seed, uint64_t offset,
+                         hipStream_t s) {
+  glorot_kernel<<<grid_for(n), kBlock, 0, s>>>(w, n, fan_in, fan_out, seed, offset);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_dz(float *dz, int64_t n, const float *scale, hipStream_t s) {
+  scale_dz_kernel<<<grid_for(n), kBlock, 0, s>>>(dz, n, scale);
+  return hipGetLastError();
+}
+
+}  // namespace ivhd
+
+namespace ivhd {
+namespace {
+
+// rows of one training batch: B sources s_b = (a (off + b) + c0) mod M, then
+// their nn targets (an absent slot repeats the source, which adds nothing to
+// the stress or its gradient), then their rn targets
+__global__ void batch_rows_kernel(const int32_t *__restrict__ nn_idx, int nn, const int32_t *__restrict__ rn_idx,
+                                  int rn, int64_t M, int64_t B, uint64_t a, uint64_t c0, int64_t off,
+                                  int32_t *__restrict__ rows) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const int64_t src = (int64_t)((a * (uint64_t)(off + b) + c0) % (uint64_t)M);
+  rows[b] = (int32_t)src;
+  for (int q = 0; q < nn; ++q) {
+    const int32_t j = nn_idx[src * nn + q];
+    rows[B + b * nn + q] = j >= 0 ? j : (int32_t)src;
+  }
+  for (int q = 0; q < rn; ++q) rows[B + B * nn + b * rn + q] = rn_idx[src * rn + q];
+}
+
+// the fixed local edge lists of a batch: source b's nn edges point at rows
+// B + b*nn + q, its rn edges at rows B + B*nn + b*rn + q; other rows have none
+__global__ void batch_plan_kernel(int64_t B, int nn, int rn, int32_t *__restrict__ lnn, int32_t *__restrict__ lrn) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t R = B * (1 + nn + rn);
+  if (r >= R) return;
+  for (int q = 0; q < nn; ++q) lnn[r * nn + q] = r < B ? (int32_t)(B + r * nn + q) : -1;
+  for (int q = 0; q < rn; ++q) lrn[r * rn + q] = r < B ? (int32_t)(B + B * nn + r * rn + q) : -1;
+}
+
+}  // namespace
+
+hipError_t launch_batch_rows(const int32_t *nn_idx, int nn, const int32_t *rn_idx, int rn, int64_t M, int64_t B,
+                             uint64_t a, uint64_t c0, int64_t off, int32_t *rows, hipStream_t s) {
+  batch_rows_kernel<<<grid_for(B), kBlock, 0, s>>>(nn_idx, nn, rn_idx, rn, M, B, a, c0, off, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_plan(int64_t B, int nn, int rn, int32_t *lnn, int32_t *lrn, hipStream_t s) {
+  batch_plan_kernel<<<grid_for(B * (1 + nn + rn)), kBlock, 0, s>>>(B, nn, rn, lnn, lrn);
+  return hipGetLastError();
+}
+
+}  // namespace ivhd

@@ -1,0 +1,414 @@
+// Host side of the parametric encoder ABI (include/ivhd.h, "parametric
+// encoder"): an MLP n_in -> h1 -> h2 -> 2 with ReLU, BF16 weights and
+// activations, FP32 accumulation and FP32 master weights, trained with Adam
+// on the IVHD stress of its own batches' edges.
+//
+// One training step on a batch of R rows X_b (BF16):
+//   H1 = relu(X_b W1^T + b1)  H2 = relu(H1 W2^T + b2)  Z = H2 W3^T + b3 (FP32)
+//   loss = s E_batch(Z)       (the stress over the batch's local edge lists)
+//   dZ   = grad E_batch(Z)    (the deterministic gather kernel of the loop)
+//   dH2  = (dZ W3) . [H2 > 0]             dW3 = dZ^T H2      db3 = sum dZ
+//   dH1  = (dH2 W2) . [H1 > 0]            dW2 = dH2^T H1     db2 = sum dH2
+//                                         dW1 = dH1^T X_b    db1 = sum dH1
+//   Adam on all parameters with the gradients scaled by s, then BF16 copies.
+#include <cmath>
+#include <mutex>
+#include <new>
+#include <unordered_set>
+
+#include "enc_internal.h"
+
+struct ivhd_enc {
+  int32_t n_in = 0, h1 = 0, h2 = 0;
+  hipStream_t stream = nullptr;
+  int64_t n_params = 0;
+  int64_t oW1 = 0, ob1 = 0, oW2 = 0, ob2 = 0, oW3 = 0, ob3 = 0;
+  float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+  uint16_t *w16 = nullptr;
+  int64_t t = 0;
+  int64_t r_cap = 0;
+  uint16_t *xb = nullptr, *a1 = nullptr, *a2 = nullptr, *d1 = nullptr, *d2 = nullptr;
+  float *z = nullptr, *dz = nullptr;
+  float *ws = nullptr;
+  int64_t ws_elems = 0;
+  int splits = 16;
+  int chunks = 64;
+  // epoch training state
+  int32_t *rows = nullptr;
+  int32_t *lnn = nullptr, *lrn = nullptr;
+  ivhd_edges *plan = nullptr;
+  int64_t plan_B = 0;
+  int32_t plan_nn = 0, plan_rn = 0;
+  int32_t *rn_all = nullptr;
+  int64_t rn_all_elems = 0;
+  int64_t *d_epoch = nullptr;
+  double *d_losses = nullptr;
+  int64_t losses_cap = 0;
+};
+
+using namespace ivhd;
+
+namespace {
+
+std::mutex g_enc_mu;
+std::unordered_set<const ivhd_enc *> g_enc_live;
+
+bool enc_live(const ivhd_enc *e) {
+  if (!e) return false;
+  std::lock_guard<std::mutex> lk(g_enc_mu);
+  return g_enc_live.count(e) != 0;
+}
+
+void free_enc(ivhd_enc *e) {
+  if (!e) return;
+  if (e->plan) (void)ivhd_edges_destroy(e->plan);
+  void *bufs[] = {e->w, e->g, e->m, e->v, e->w16, e->xb, e->a1, e->a2, e->d1, e->d2, e->z, e->dz, e->ws,
+                  e->rows, e->lnn, e->lrn, e->rn_all, e->d_epoch, e->d_losses};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+  delete e;
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+GemmArgs gemm(const uint16_t *A, const uint16_t *B, int64_t M, int64_t N, int64_t K, int64_t lda, int64_t ldb,
+              void *C, int64_t ldc) {
+  GemmArgs g{};
+  g.A = A;
+  g.B = B;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.lda = lda;
+  g.ldb = ldb;
+  g.C = C;
+  g.ldc = ldc;
+  g.vec_a = lda % 8 == 0 && aligned16(A);
+  g.vec_b = ldb % 8 == 0 && aligned16(B);
+  return g;
+}
+
+// forward of R rows (R <= r_cap) from BF16 input X (row pitch n_in) into z
+int forward_rows(ivhd_enc *e, const uint16_t *X, int64_t R, float *z) {
+  hipStream_t s = e->stream;
+  GemmArgs g1 = gemm(X, e->w16 + e->oW1, R, e->h1, e->n_in, e->n_in, e->n_in, e->a1, e->h1);
+  g1.bias = e->w + e->ob1;
+  HIPCHK(launch_gemm_bf16(g1, 0, 1, GEMM_EPI_BIAS_RELU_BF16, 1, s));
+  GemmArgs g2 = gemm(e->a1, e->w16 + e->oW2, R, e->h2, e->h1, e->h1, e->h1, e->a2, e->h2);
+  g2.bias = e->w + e->ob2;
+  HIPCHK(launch_gemm_bf16(g2, 0, 1, GEMM_EPI_BIAS_RELU_BF16, 1, s));
+  HIPCHK(launch_head_forward(e->a2, R, e->h2, e->w16 + e->oW3, e->w + e->ob3, z, s));
+  return IVHD_OK;
+}
+
+// weight gradient dW[M][N] = A^T B over R rows, split over K = R, into g
+int wgrad(ivhd_enc *e, const uint16_t *A, int64_t M, const uint16_t *B, int64_t N, int64_t R, float *out) {
+  hipStream_t s = e->stream;
+  const int splits = gemm_splits_used(R, e->splits);
+  GemmArgs gg = gemm(A, B, M, N, R, M, N, e->ws, N);
+  HIPCHK(launch_gemm_bf16(gg, 1, 0, GEMM_EPI_F32, e->splits, s));
+  HIPCHK(launch_splitk_reduce(e->ws, splits, M, N, N, out, N, s));
+  return IVHD_OK;
+}
+
+// one step on the batch already in e->xb (R rows) with local edge plan `plan`
+int train_step_rows(ivhd_enc *e, int64_t R, ivhd_edges *plan, float c, float eps, float lr, float scale,
+                    double *d_loss) {
+  hipStream_t s = e->stream;
+  int rc = forward_rows(e, e->xb, R, e->z);
+  if (rc) return rc;
+  if (d_loss && (rc = ivhd_edges_stress(plan, e->z, c, d_loss))) return rc;
+  if ((rc = ivhd_edges_grad(plan, e->z, c, eps, nullptr, e->dz))) return rc;
+  // head
+  HIPCHK(launch_head_dgrad(e->dz, e->w16 + e->oW3, e->a2, R, e->h2, e->d2, s));
+  HIPCHK(launch_colsum(1, e->a2, e->dz, R, 2 * (int64_t)e->h2, e->h2, e->ws, e->chunks, e->g + e->oW3, s));
+  HIPCHK(launch_colsum(2, e->dz, nullptr, R, 2, 2, e->ws, e->chunks, e->g + e->ob3, s));
+  // layer 2
+  GemmArgs gd = gemm(e->d2, e->w16 + e->oW2, R, e->h1, e->h2, e->h2, e->h1, e->d1, e->h1);
+  gd.mask = e->a1;
+  gd.ldm = e->h1;
+  HIPCHK(launch_gemm_bf16(gd, 0, 0, GEMM_EPI_RELU_MASK_BF16, 1, s));
+  if ((rc = wgrad(e, e->d2, e->h2, e->a1, e->h1, R, e->g + e->oW2))) return rc;
+  HIPCHK(launch_colsum(0, e->d2, nullptr, R, e->h2, e->h2, e->ws, e->chunks, e->g + e->ob2, s));
+  // layer 1
+  if ((rc = wgrad(e, e->d1, e->h1, e->xb, e->n_in, R, e->g + e->oW1))) return rc;
+  HIPCHK(launch_colsum(0, e->d1, nullptr, R, e->h1, e->h1, e->ws, e->chunks, e->g + e->ob1, s));
+  // Adam
+  e->t += 1;
+  HIPCHK(launch_adam(e->w, e->g, e->m, e->v, e->w16, e->n_params, lr, 0.9f, 0.999f, 1e-8f, e->t, scale, s));
+  return IVHD_OK;
+}
+
+uint64_t mix64(uint64_t x) {
+  uint64_t z = x + 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+uint64_t gcd64(uint64_t a, uint64_t b) {
+  while (b) {
+    uint64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ivhd_enc_create(ivhd_enc **out, int32_t n_in, int32_t h1, int32_t h2, uint64_t seed, int64_t max_rows,
+                    void *stream) {
+  clear_error();
+  if (!out) return fail(IVHD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_in < 1 || h1 < 1 || h2 < 1 || n_in > 65536 || h1 > 65536 || h2 > 65536)
+    return fail(IVHD_EINVAL, "layer widths (%d, %d, %d) outside [1, 65536]", n_in, h1, h2);
+  if (h1 % 8 || h2 % 8) return fail(IVHD_EINVAL, "hidden widths (%d, %d) must be multiples of 8", h1, h2);
+  if (max_rows < 1 || max_rows > (int64_t)1 << 26)
+    return fail(IVHD_EINVAL, "max_rows = %lld outside [1, 2^26]", (long long)max_rows);
+  ivhd_enc *e = new (std::nothrow) ivhd_enc();
+  if (!e) return fail(IVHD_ENOMEM, "host allocation of the encoder failed");
+  e->n_in = n_in;
+  e->h1 = h1;
+  e->h2 = h2;
+  e->stream = (hipStream_t)stream;
+  e->oW1 = 0;
+  e->ob1 = e->oW1 + (int64_t)h1 * n_in;
+  e->oW2 = e->ob1 + h1;
+  e->ob2 = e->oW2 + (int64_t)h2 * h1;
+  e->oW3 = e->ob2 + h2;
+  e->ob3 = e->oW3 + 2 * (int64_t)h2;
+  e->n_params = e->ob3 + 2;
+  e->r_cap = max_rows;
+  const int64_t wmax = (int64_t)h1 * n_in > (int64_t)h2 * h1 ? (int64_t)h1 * n_in : (int64_t)h2 * h1;
+  e->ws_elems = wmax * e->splits;
+  const int64_t colsum_ws = (int64_t)e->chunks * (2 * (int64_t)h2 > (h1 > h2 ? h1 : h2) ? 2 * (int64_t)h2 : (h1 > h2 ? h1 : h2));
+  if (colsum_ws > e->ws_elems) e->ws_elems = colsum_ws;
+  int rc;
+#define ENC_CHK(expr) \
+  do {                \
+    rc = (expr);      \
+    if (rc) {         \
+      free_enc(e);    \
+      return rc;      \
+    }                 \
+  } while (0)
+#define ENC_HIP(expr)                 \
+  do {                                \
+    hipError_t _e = (expr);           \
+    if (_e != hipSuccess) {           \
+      rc = hip_fail(_e, #expr);       \
+      free_enc(e);                    \
+      return rc;                      \
+    }                                 \
+  } while (0)
+  const int64_t np = e->n_params;
+  ENC_CHK(dev_alloc(&e->w, np, "encoder weights"));
+  ENC_CHK(dev_alloc(&e->g, np, "encoder gradients"));
+  ENC_CHK(dev_alloc(&e->m, np, "Adam first moments"));
+  ENC_CHK(dev_alloc(&e->v, np, "Adam second moments"));
+  ENC_CHK(dev_alloc(&e->w16, np, "BF16 weights"));
+  ENC_CHK(dev_alloc(&e->xb, max_rows * n_in, "batch input"));
+  ENC_CHK(dev_alloc(&e->a1, max_rows * h1, "layer-1 activations"));
+  ENC_CHK(dev_alloc(&e->a2, max_rows * h2, "layer-2 activations"));
+  ENC_CHK(dev_alloc(&e->d1, max_rows * h1, "layer-1 gradients"));
+  ENC_CHK(dev_alloc(&e->d2, max_rows * h2, "layer-2 gradients"));
+  ENC_CHK(dev_alloc(&e->z, max_rows * 2, "embedding"));
+  ENC_CHK(dev_alloc(&e->dz, max_rows * 2, "embedding gradient"));
+  ENC_CHK(dev_alloc(&e->ws, e->ws_elems, "encoder workspace"));
+  ENC_CHK(dev_alloc(&e->d_epoch, 1, "epoch counter"));
+  hipStream_t s = e->stream;
+  ENC_HIP(launch_fill_i32((int32_t *)e->w, np, 0, s));
+  ENC_HIP(launch_fill_i32((int32_t *)e->m, np, 0, s));
+  ENC_HIP(launch_fill_i32((int32_t *)e->v, np, 0, s));
+  ENC_HIP(launch_fill_i32((int32_t *)e->g, np, 0, s));
+  ENC_HIP(launch_glorot(e->w + e->oW1, (int64_t)h1 * n_in, n_in, h1, seed, 1, s));
+  ENC_HIP(launch_glorot(e->w + e->oW2, (int64_t)h2 * h1, h1, h2, seed, 2ull << 40, s));
+  ENC_HIP(launch_glorot(e->w + e->oW3, 2 * (int64_t)h2, h2, 2, seed, 3ull << 40, s));
+  ENC_HIP(launch_f32_to_bf16(e->w, np, e->w16, s));
+  ENC_HIP(hipStreamSynchronize(s));
+#undef ENC_CHK
+#undef ENC_HIP
+  {
+    std::lock_guard<std::mutex> lk(g_enc_mu);
+    g_enc_live.insert(e);
+  }
+  *out = e;
+  return IVHD_OK;
+}
+
+int ivhd_enc_num_params(const ivhd_enc *e, int64_t *h_n) {
+  if (!enc_live(e)) return fail(IVHD_ESTATE, "invalid encoder");
+  if (!h_n) return fail(IVHD_EINVAL, "h_n is NULL");
+  *h_n = e->n_params;
+  return IVHD_OK;
+}
+
+int ivhd_enc_get_params(ivhd_enc *e, float *d_params, float *d_grads) {
+  if (!enc_live(e)) return fail(IVHD_ESTATE, "invalid encoder");
+  const size_t bytes = (size_t)e->n_params * sizeof(float);
+  if (d_params) HIPCHK(hipMemcpyAsync(d_params, e->w, bytes, hipMemcpyDeviceToDevice, e->stream));
+  if (d_grads) HIPCHK(hipMemcpyAsync(d_grads, e->g, bytes, hipMemcpyDeviceToDevice, e->stream));
+  return IVHD_OK;
+}
+
+int ivhd_enc_set_params(ivhd_enc *e, const float *d_params) {
+  if (!enc_live(e)) return fail(IVHD_ESTATE, "invalid encoder");
+  if (!d_params) return fail(IVHD_EINVAL, "d_params is NULL");
+  HIPCHK(hipMemcpyAsync(e->w, d_params, (size_t)e->n_params * sizeof(float), hipMemcpyDeviceToDevice, e->stream));
+  HIPCHK(launch_f32_to_bf16(e->w, e->n_params, e->w16, e->stream));
+  HIPCHK(launch_fill_i32((int32_t *)e->m, e->n_params, 0, e->stream));
+  HIPCHK(launch_fill_i32((int32_t *)e->v, e->n_params, 0, e->stream));
+  e->t = 0;
+  return IVHD_OK;
+}
+
+int ivhd_enc_embed(ivhd_enc *e, const uint16_t *d_x16, int64_t rows, float *d_z) {
+  if (!enc_live(e)) return fail(IVHD_ESTATE, "invalid encoder");
+  if (rows < 0) return fail(IVHD_EINVAL, "rows = %lld < 0", (long long)rows);
+  if (rows > 0 && (!d_x16 || !d_z)) return fail(IVHD_EINVAL, "d_x16 and d_z must not be NULL");
+  for (int64_t r0 = 0; r0 < rows; r0 += e->r_cap) {
+    const int64_t R = rows - r0 < e->r_cap ? rows - r0 : e->r_cap;
+    int rc = forward_rows(e, d_x16 + r0 * e->n_in, R, d_z + 2 * r0);
+    if (rc) return rc;
+  }
+  return IVHD_OK;
+}
+
+int ivhd_enc_train_step(ivhd_enc *e, const uint16_t *d_xb16, int64_t R, ivhd_edges *plan, float c, float eps,
+                        float lr, float loss_scale, double *d_loss) {
+  if (!enc_live(e)) return fail(IVHD_ESTATE, "invalid encoder");
+  if (R < 1 || R > e->r_cap) return fail(IVHD_EINVAL, "R = %lld outside [1, max_rows]", (long long)R);
+  if (!d_xb16 || !plan) return fail(IVHD_EINVAL, "d_xb16 and plan must not be NULL");
+  if (!(lr > 0.f) || !std::isfinite(lr)) return fail(IVHD_EINVAL, "lr = %g must be > 0", (double)lr);
+  HIPCHK(hipMemcpyAsync(e->xb, d_xb16, (size_t)R * e->n_in * sizeof(uint16_t), hipMemcpyDeviceToDevice,
+                        e->stream));
+  return train_step_rows(e, R, plan, c, eps, lr, loss_scale, d_loss);
+}
+
+int ivhd_enc_train_epoch(ivhd_enc *e, const uint16_t *d_x16, int64_t M, const int32_t *d_nn_idx, int32_t nn,
+                         int32_t rn, uint64_t seed, int64_t epoch, int64_t batch, float c, float eps, float lr,
+                         double *h_loss) {
+  if (!enc_live(e)) return fail(IVHD_ESTATE, "invalid encoder");
+  if (!d_x16 || !d_nn_idx) return fail(IVHD_EINVAL, "d_x16 and d_nn_idx must not be NULL");
+  if (M < 2 || M > (int64_t)INT32_MAX - 1) return fail(IVHD_EINVAL, "M = %lld outside [2, 2^31-2]", (long long)M);
+  if (nn < 1 || nn > 64 || rn < 0 || rn > 64 || nn + rn > M - 1)
+    return fail(IVHD_EINVAL, "nn = %d, rn = %d invalid for M = %lld", nn, rn, (long long)M);
+  if (batch < 1 || batch * (1 + nn + rn) > e->r_cap)
+    return fail(IVHD_EINVAL, "batch = %lld: batch * (1 + nn + rn) must be in [1, max_rows]", (long long)batch);
+  if (epoch < 0) return fail(IVHD_EINVAL, "epoch = %lld < 0", (long long)epoch);
+  hipStream_t s = e->stream;
+  const int64_t R = batch * (1 + nn + rn);
+  int rc;
+  // local edge lists of a batch: fixed structure, built once per (batch, nn, rn)
+  if (!e->plan || e->plan_B != batch || e->plan_nn != nn || e->plan_rn != rn) {
+    if (e->plan) {
+      (void)ivhd_edges_destroy(e->plan);
+      e->plan = nullptr;
+    }
+    if (e->lnn) (void)hipFree(e->lnn);
+    if (e->lrn) (void)hipFree(e->lrn);
+    if (e->rows) (void)hipFree(e->rows);
+    e->lnn = e->lrn = e->rows = nullptr;
+    if ((rc = dev_alloc(&e->lnn, R * nn, "batch nn lists"))) return rc;
+    if (rn > 0 && (rc = dev_alloc(&e->lrn, R * rn, "batch rn lists"))) return rc;
+    if ((rc = dev_alloc(&e->rows, R, "batch rows"))) return rc;
+    HIPCHK(launch_batch_plan(batch, nn, rn, e->lnn, e->lrn, s));
+    if ((rc = ivhd_edges_create(&e->plan, R, e->lnn, nn, e->lrn, rn, s))) return rc;
+    e->plan_B = batch;
+    e->plan_nn = nn;
+    e->plan_rn = rn;
+  }
+  if (rn > 0 && e->rn_all_elems < M * rn) {
+    if (e->rn_all) (void)hipFree(e->rn_all);
+    e->rn_all = nullptr;
+    e->rn_all_elems = 0;
+    if ((rc = dev_alloc(&e->rn_all, M * rn, "epoch random neighbours"))) return rc;
+    e->rn_all_elems = M * rn;
+  }
+  const int64_t steps = (M + batch - 1) / batch;
+  if (e->losses_cap < steps) {
+    if (e->d_losses) (void)hipFree(e->d_losses);
+    e->d_losses = nullptr;
+    e->losses_cap = 0;
+    if ((rc = dev_alloc(&e->d_losses, steps, "step losses"))) return rc;
+    e->losses_cap = steps;
+  }
+  // the epoch's random neighbours (same draw as the loop's, epoch = training epoch)
+  if (rn > 0) {
+    HIPCHK(hipMemcpyAsync(e->d_epoch, &epoch, sizeof epoch, hipMemcpyHostToDevice, s));
+    HIPCHK(launch_rn_sample(d_nn_idx, M, nn, rn, seed, e->d_epoch, e->rn_all, nullptr, s));
+    HIPCHK(hipStreamSynchronize(s));   // epoch lives on the host stack
+  }
+  // visiting order: s_b = (a b + c0) mod M with gcd(a, M) = 1, a bijection
+  uint64_t a = mix64(seed ^ mix64(0x5eedULL + (uint64_t)epoch)) % (uint64_t)M;
+  if (a == 0) a = 1;
+  while (gcd64(a, (uint64_t)M) != 1) a = a + 1 == (uint64_t)M ? 1 : a + 1;
+  const uint64_t c0 = mix64(seed + 7919ull * (uint64_t)epoch) % (uint64_t)M;
+  const float scale = 1.f / (float)batch;
+  for (int64_t st = 0; st < steps; ++st) {
+    HIPCHK(launch_batch_rows(d_nn_idx, nn, e->rn_all, rn, M, batch, a, c0, st * batch, e->rows, s));
+    HIPCHK(launch_gather_rows(d_x16, e->n_in, e->rows, R, e->xb, s));
+    if ((rc = train_step_rows(e, R, e->plan, c, eps, lr, scale, e->d_losses + st))) return rc;
+  }
+  if (h_loss) {
+    double *tmp = new (std::nothrow) double[steps];
+    if (!tmp) return fail(IVHD_ENOMEM, "host loss buffer");
+    hipError_t err = hipMemcpyAsync(tmp, e->d_losses, steps * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    double sum = 0.0;
+    for (int64_t st = 0; st < steps; ++st) sum += tmp[st];
+    delete[] tmp;
+    if (err != hipSuccess) return hip_fail(err, "loss copy");
+    *h_loss = sum * scale / (double)steps;
+  }
+  return IVHD_OK;
+}
+
+int ivhd_enc_destroy(ivhd_enc *e) {
+  if (!e) return IVHD_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_enc_mu);
+    if (!g_enc_live.erase(e)) return fail(IVHD_ESTATE, "invalid encoder");
+  }
+  hipError_t err = hipStreamSynchronize(e->stream);
+  free_enc(e);
+  if (err != hipSuccess) return hip_fail(err, "hipStreamSynchronize");
+  return IVHD_OK;
+}
+
+int ivhd_f32_to_bf16(const float *d_x, int64_t n, uint16_t *d_y, void *stream) {
+  if (n < 0) return fail(IVHD_EINVAL, "n < 0");
+  if (n > 0 && (!d_x || !d_y)) return fail(IVHD_EINVAL, "d_x and d_y must not be NULL");
+  if (n == 0) return IVHD_OK;
+  HIPCHK(launch_f32_to_bf16(d_x, n, d_y, (hipStream_t)stream));
+  return IVHD_OK;
+}
+
+int ivhd_gemm_bf16(const uint16_t *d_a, const uint16_t *d_b, int64_t M, int64_t N, int64_t K, int64_t lda,
+                   int64_t ldb, int32_t trans_a, int32_t trans_b, int32_t epilogue, const float *d_bias,
+                   const uint16_t *d_mask, int64_t ldm, void *d_c, int64_t ldc, int32_t splits, float *d_work,
+                   void *stream) {
+  if (!d_a || !d_b || !d_c) return fail(IVHD_EINVAL, "d_a, d_b and d_c must not be NULL");
+  if (M < 1 || N < 1 || K < 1) return fail(IVHD_EINVAL, "M, N, K must be >= 1");
+  if (epilogue < 0 || epilogue > 2) return fail(IVHD_EINVAL, "epilogue = %d unknown", epilogue);
+  if (lda < (trans_a ? M : K) || ldb < (trans_b ? K : N) || ldc < N)
+    return fail(IVHD_EINVAL, "leading dimension too small");
+  if (epilogue == 2 && (!d_mask || ldm < N)) return fail(IVHD_EINVAL, "epilogue 2 needs d_mask with ldm >= N");
+  if (splits < 1) splits = 1;
+  const int used = gemm_splits_used(K, splits);
+  if (used > 1 && (epilogue != 0 || !d_work)) return fail(IVHD_EINVAL, "split-K needs epilogue 0 and d_work");
+  hipStream_t s = (hipStream_t)stream;
+  GemmArgs g = gemm(d_a, d_b, M, N, K, lda, ldb, used > 1 ? (void *)d_work : d_c, used > 1 ? N : ldc);
+  g.bias = d_bias;
+  g.mask = d_mask;
+  g.ldm = ldm;
+  HIPCHK(launch_gemm_bf16(g, trans_a ? 1 : 0, trans_b ? 1 : 0, epilogue, splits, s));
+  if (used > 1) HIPCHK(launch_splitk_reduce(d_work, used, M, N, N, (float *)d_c, ldc, s));
+  return IVHD_OK;
+}
+
+}  // extern "C"

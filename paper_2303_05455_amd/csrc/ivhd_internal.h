@@ -20,6 +20,31 @@ constexpr int kHeavyPerBlock = kBlock / 64;
 // device flag slots
 enum { FLAG_BAD_INDEX = 0, FLAG_NONFINITE = 1, FLAG_BIG_COUNT = 2, FLAG_SLOTS = 4 };
 
+// error reporting shared by the host translation units (message is thread-local)
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+void clear_error();
+
+#define HIPCHK(expr)                                  \
+  do {                                                \
+    hipError_t _e = (expr);                           \
+    if (_e != hipSuccess) return ::ivhd::hip_fail(_e, #expr); \
+  } while (0)
+
+template <typename T>
+int dev_alloc(T **p, size_t count, const char *what) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(e == hipErrorOutOfMemory ? IVHD_ENOMEM : IVHD_EDEVICE, "allocating %s (%zu bytes): %s", what,
+                count * sizeof(T), hipGetErrorString(e));
+  }
+  return IVHD_OK;
+}
+
 inline unsigned grid_for(int64_t n, int block = kBlock) {
   int64_t g = (n + block - 1) / block;
   return (unsigned)(g < 1 ? 1 : g);

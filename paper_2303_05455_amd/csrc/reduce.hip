@@ -28,7 +28,9 @@ stress_partial_kernel(const float2 *__restrict__ y, int64_t M, const int32_t *__
       e += dx * dx + dy * dy;
     }
     for (int q = 0; q < rn; ++q) {
-      const float2 yk = y[rn_idx[i * rn + q]];
+      const int32_t k = rn_idx[i * rn + q];
+      if (k < 0) continue;
+      const float2 yk = y[k];
       const double dx = (double)yi.x - (double)yk.x, dy = (double)yi.y - (double)yk.y;
       const double d = sqrt(dx * dx + dy * dy);
       e += c * (1.0 - d) * (1.0 - d);

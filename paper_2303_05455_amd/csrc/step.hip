@@ -78,8 +78,11 @@ __device__ __forceinline__ float2 light_force(const StepArgs &A, int64_t i, floa
     }
   }
   for (int q = 0; q < A.rn; ++q) {
-    const float2 t = rn_term(yi, y[A.rn_idx[i * A.rn + q]], A.c, A.eps);
-    fx += t.x; fy += t.y;
+    const int32_t k = A.rn_idx[i * A.rn + q];
+    if (k >= 0) {
+      const float2 t = rn_term(yi, y[k], A.c, A.eps);
+      fx += t.x; fy += t.y;
+    }
   }
   gather_segment<false>(y, A.nn_src, ns, ne, yi, A.c, A.eps, fx, fy);
   if (A.rn > 0) gather_segment<true>(y, A.rn_src, A.rn_ptr[i], A.rn_ptr[i + 1], yi, A.c, A.eps, fx, fy);
@@ -102,7 +105,8 @@ __device__ __forceinline__ float2 heavy_force(const StepArgs &A, int64_t i, floa
       const int32_t j = A.nn_idx[i * A.nn + e];
       t = j >= 0 ? nn_term(yi, y[j]) : make_float2(0.f, 0.f);
     } else if (e < n_out) {
-      t = rn_term(yi, y[A.rn_idx[i * A.rn + (e - A.nn)]], A.c, A.eps);
+      const int32_t k = A.rn_idx[i * A.rn + (e - A.nn)];
+      t = k >= 0 ? rn_term(yi, y[k], A.c, A.eps) : make_float2(0.f, 0.f);
     } else if (e < n_out + n_in_nn) {
       t = nn_term(yi, y[A.nn_src[ns + (e - n_out)]]);
     } else {

@@ -117,7 +117,7 @@ def test_bad_random_neighbour_index_is_rejected(m):
     pkg, ag = m
     nn_idx, rn_idx, Y = _case(500, 2, 1, 7)
     bad = rn_idx.copy()
-    bad[10, 0] = -1
+    bad[10, 0] = 500
     with pytest.raises(pkg.IvhdError):
         ag.StressEdges(torch.from_numpy(nn_idx).cuda(), torch.from_numpy(bad).cuda())
 

@@ -1,0 +1,125 @@
+"""The BF16 MFMA encoder kernels against the FP64 reference.
+
+GEMMs: on identical BF16 operands, |gpu - ref| <= 1e-5 * sum_k |a_k b_k| per
+element (FP32 accumulation) for FP32 outputs, plus one BF16 rounding step
+(2^-8 relative) for BF16 outputs.  A training step: gradients and updated
+parameters against oracle/mlp.py with BF16 rounding emulated at the same
+points, norm-wise within 1e-3.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2303_05455_amd as m
+    from paper_2303_05455_amd import api, autograd, parametric
+    return m, api, autograd, parametric
+
+
+def _bits(x):
+    return torch.from_numpy(mlp.bf16_bits(x).copy()).cuda()
+
+
+def _norm_rel(x, ref):
+    return float(np.linalg.norm(np.asarray(x, np.float64) - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+@pytest.mark.parametrize("M,N,K,ta,tb,epi,splits", [
+    (257, 130, 100, 0, 1, 0, 1), (128, 128, 32, 0, 0, 0, 1), (300, 77, 513, 1, 0, 0, 4),
+    (64, 200, 1000, 1, 1, 0, 3), (1000, 512, 784, 0, 1, 1, 1), (999, 512, 512, 0, 0, 2, 1),
+    (512, 784, 4096, 1, 0, 0, 16), (5, 3, 7, 0, 1, 0, 1),
+])
+def test_gemm_matches_fp64_on_identical_bf16_operands(pkg, M, N, K, ta, tb, epi, splits):
+    m, api, _, _ = pkg
+    rng = np.random.default_rng(M * 7 + N + K)
+    A = mlp.bf16_round(rng.normal(size=(K, M) if ta else (M, K)))
+    B = mlp.bf16_round(rng.normal(size=(N, K) if tb else (K, N)))
+    opA = A.T if ta else A
+    opB = B.T if tb else B
+    ref = opA @ opB
+    bound = np.abs(opA) @ np.abs(opB)
+    bias = rng.normal(size=N).astype(np.float32)
+    mask = mlp.bf16_round(rng.normal(size=(M, N)))
+    out = api.ivhd_gemm_bf16(_bits(A), _bits(B), M, N, K, lda=A.shape[1], ldb=B.shape[1], trans_a=bool(ta),
+                             trans_b=bool(tb), epilogue=epi,
+                             bias=torch.from_numpy(bias).cuda() if epi == 1 else None,
+                             mask=_bits(mask) if epi == 2 else None, ldm=N, splits=splits)
+    torch.cuda.synchronize()
+    if epi == 0:
+        got = out.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(got - ref) <= 1e-5 * bound + 1e-30)
+    else:
+        got = mlp.from_bf16_bits(out.cpu().numpy())
+        want = np.maximum(ref + bias, 0) if epi == 1 else np.where(mask > 0, ref, 0.0)
+        tol = 1e-5 * (bound + np.abs(bias) if epi == 1 else bound) + 2.0 ** -8 * np.abs(want) + 1e-30
+        assert np.all(np.abs(got - want) <= tol)
+
+
+def _setup(pkg, n_in, h1, h2, B, nn, rn, seed):
+    m, api, ag, par = pkg
+    rng = np.random.default_rng(seed)
+    R = B * (1 + nn + rn)
+    X = mlp.bf16_round(np.maximum(rng.normal(1.0, 1.0, size=(R, n_in)), 0))
+    L = mlp.layout(n_in, h1, h2)
+    p = np.zeros(L["n"])
+    for name, (o, n), fan in (("W1", L["W1"], (n_in, h1)), ("W2", L["W2"], (h1, h2)), ("W3", L["W3"], (h2, 2))):
+        s = np.sqrt(6.0 / sum(fan))
+        p[o:o + n] = rng.uniform(-s, s, n)
+    p = p.astype(np.float32).astype(np.float64)
+    lnn, lrn = mlp.batch_edges(B, nn, rn)
+    return X, p, lnn, lrn, R
+
+
+@pytest.mark.parametrize("n_in,h1,h2,B,nn,rn", [(40, 32, 24, 50, 2, 1), (784, 512, 512, 256, 5, 1)])
+def test_training_step_matches_the_reference(pkg, n_in, h1, h2, B, nn, rn):
+    m, api, ag, par = pkg
+    X, p, lnn, lrn, R = _setup(pkg, n_in, h1, h2, B, nn, rn, 11)
+    c, eps, lr, scale = 0.1, 1e-12, 1e-3, 1.0 / B
+    enc = par.ParametricIVHD(n_in, (h1, h2), batch=B, nn=nn, rn=rn, max_rows=R)
+    enc.set_params(torch.from_numpy(p.astype(np.float32)).cuda())
+    plan = ag.StressEdges(torch.from_numpy(lnn).cuda(), torch.from_numpy(lrn).cuda(), c=c)
+    loss = torch.zeros((), dtype=torch.float64, device="cuda")
+    api.ivhd_enc_train_step(enc.handle, _bits(X), plan.handle, c, eps, lr, scale, loss)
+    torch.cuda.synchronize()
+    _, _, _, g_ref, E_ref = mlp.train_step(p, np.zeros_like(p), np.zeros_like(p), 1, X, lnn, lrn, n_in, h1, h2,
+                                            c=np.float32(c), eps=np.float32(eps), lr=lr, scale=scale)
+    assert loss.item() == pytest.approx(E_ref, rel=1e-4)
+    g_gpu = enc.grads().cpu().numpy().astype(np.float64)
+    assert _norm_rel(g_gpu, g_ref) <= 1e-3
+    # the Adam step itself, on the GPU's own gradients (a sign flip of a
+    # near-zero gradient moves a weight by 2 lr, so it is checked apart)
+    p1_from_gpu_grads, _, _ = mlp.adam(p, g_gpu * scale, np.zeros_like(p), np.zeros_like(p), 1, lr)
+    np.testing.assert_allclose(enc.params().cpu().numpy(), p1_from_gpu_grads, rtol=1e-5, atol=1e-7)
+    # forward alone
+    Z = enc.embed(_bits(X[:B]))
+    Z_ref, _ = mlp.forward(enc.params().cpu().numpy().astype(np.float64), X[:B], n_in, h1, h2)
+    assert _norm_rel(Z.cpu().numpy(), Z_ref) <= 1e-3
+    enc.close()
+    plan.close()
+
+
+def test_training_lowers_the_batch_stress_and_separates_clusters(pkg):
+    # small mixture: 6,000 points in 64-D, 6 clusters; a few epochs of training
+    m, api, ag, par = pkg
+    import synth
+    rng = synth.rng_for(77)
+    X, labels = synth.gaussian_mixture(6000, 64, 6, centre_var=16.0, sigma=1.0, rng=rng)
+    dX = torch.from_numpy(X).cuda()
+    nn_idx = m.ivhd_knn_build(dX, 5)
+    enc = par.ParametricIVHD(64, (64, 64), batch=256, nn=5, rn=1, lr=3e-3, seed=1)
+    x16 = par.ParametricIVHD.to_bf16(dX)
+    enc.fit(x16, nn_idx, epochs=8)
+    assert enc.losses[-1] < 0.7 * enc.losses[0]
+    Z = enc.embed(x16).cpu().numpy()
+    assert np.all(np.isfinite(Z))
+    assert oracle.cf_k(Z, labels, 10) > 0.9
+    enc.close()
