@@ -58,6 +58,12 @@ typedef enum ivhd_mode {
                               pass; summation order varies run to run        */
 } ivhd_mode;
 
+/* ivhd_params.flags */
+#define IVHD_FLAG_REORDER 1   /* keep the vertices internally grouped by connected
+                                 component of the nn graph (a locality order; the
+                                 results are the same up to floating-point summation
+                                 order, and the caller always sees its own order)  */
+
 typedef struct ivhd_params {
     int64_t  M;       /* vertices; 2 <= M <= 2^31 - 2                        */
     int32_t  nn;      /* nn slots per vertex, 1..64                          */
@@ -70,6 +76,8 @@ typedef struct ivhd_params {
     int32_t  rn_resample_every; /* R: draw new random neighbours at every
                                    iteration n with n % R == 0; 0 = draw once */
     int32_t  mode;    /* ivhd_mode                                            */
+    int32_t  flags;   /* IVHD_FLAG_* bits                                     */
+    int32_t  reserved;/* must be 0                                            */
 } ivhd_params;
 
 typedef struct ivhd_ctx ivhd_ctx;   /* opaque */
@@ -87,20 +95,36 @@ typedef struct ivhd_ctx ivhd_ctx;   /* opaque */
 /* ivhd_init: create a context for one graph and one layout.
  *   d_nn_idx  int32 [M][nn], read at init and at every random-neighbour draw;
  *             must stay valid and unchanged for the context's lifetime.
- *   d_y, d_v  float32 [M][2]; the context advances them in place (ivhd_step);
- *             they must stay valid for the context's lifetime.  d_v is
- *             normally zeros.
+ *   d_y, d_v  float32 [M][2], the initial positions and velocities (d_v is
+ *             normally zeros).  The context copies them into its own buffers
+ *             and writes the state back into them at the end of every
+ *             ivhd_step; they must stay valid for the context's lifetime.
+ *             Changes the caller makes to them are not read back (see
+ *             ivhd_set_state).
  *   stream    hipStream_t all later calls enqueue on.
- * Draws the random neighbours of epoch 0 and builds the transposed edge
- * lists.  Synchronises `stream`.  Returns IVHD_EINVAL (and no context) when
- * an nn entry is outside [-1, M) or equals its own row.                      */
+ * Draws the random neighbours of epoch 0, builds the internal vertex order
+ * (IVHD_FLAG_REORDER) and the transposed edge lists.  Synchronises `stream`.
+ * Returns IVHD_EINVAL (and no context) when an nn entry is outside [-1, M)
+ * or equals its own row.                                                    */
 int ivhd_init(ivhd_ctx **out, const ivhd_params *p, const int32_t *d_nn_idx,
               float *d_y, float *d_v, void *stream);
 
 /* ivhd_step: n_iters >= 0 iterations of the loop; asynchronous.  Y and V are
- * left in the caller's buffers.  Iterations are replayed from captured HIP
- * graphs when possible (one graph per random-neighbour epoch).             */
+ * written back to the caller's buffers (in the caller's order) at the end.
+ * Iterations are replayed from captured HIP graphs when possible (one graph
+ * per random-neighbour epoch).                                              */
 int ivhd_step(ivhd_ctx *ctx, int64_t n_iters);
+
+/* ivhd_set_state: load positions and velocities (float32 [M][2] each, the
+ * caller's order) into the context, e.g. to resume from a checkpoint.
+ * Asynchronous.                                                             */
+int ivhd_set_state(ivhd_ctx *ctx, const float *d_y, const float *d_v);
+
+/* ivhd_set_iteration: set the iteration counter to n and redraw the random
+ * neighbours held before iteration n (epoch (n-1)/R, epoch 0 when n = 0 or
+ * R = 0).  With ivhd_set_state this resumes a run exactly: a checkpoint is
+ * (Y, V, n) and the parameters.  Synchronises the stream.                   */
+int ivhd_set_iteration(ivhd_ctx *ctx, int64_t n);
 
 /* ivhd_stress: E(Y) accumulated in FP64 from the FP32 positions, with a
  * fixed-order (deterministic) reduction.  d_y = NULL uses the context's Y;
@@ -119,9 +143,14 @@ int ivhd_get_rn(ivhd_ctx *ctx, int32_t *d_rn_out);
  * mode gathers over: which = 0 for the nn edges, 1 for the current epoch's
  * rn edges.  d_ptr int32 [M+1] (offsets), d_src int32 [M*nn] or [M*rn]
  * (sources of the edges into each vertex, ascending; only the first
- * d_ptr[M] entries are written).  IVHD_EINVAL in atomic mode for which = 1
- * (that mode keeps no rn in-edge lists).                                    */
+ * d_ptr[M] entries are written).  Vertices are numbered in the internal
+ * order (ivhd_get_order).  IVHD_EINVAL in atomic mode for which = 1 (that
+ * mode keeps no rn in-edge lists).                                          */
 int ivhd_get_in_edges(ivhd_ctx *ctx, int32_t which, int32_t *d_ptr, int32_t *d_src);
+
+/* ivhd_get_order: d_perm int32 [M]: the caller's id of internal vertex p
+ * (the identity without IVHD_FLAG_REORDER).                                 */
+int ivhd_get_order(ivhd_ctx *ctx, int32_t *d_perm);
 
 /* ivhd_get_iteration: the number of iterations done so far.                */
 int ivhd_get_iteration(const ivhd_ctx *ctx, int64_t *h_n);

@@ -25,6 +25,7 @@ class ivhd_params(ctypes.Structure):
         ("M", i64), ("nn", i32), ("rn", i32),
         ("a", f32), ("b", f32), ("c", f32), ("eps", f32),
         ("seed", u64), ("rn_resample_every", i32), ("mode", i32),
+        ("flags", i32), ("reserved", i32),
     ]
 
 
@@ -36,6 +37,9 @@ SIGNATURES = {
     "ivhd_grad": (i32, [vp, vp, vp]),
     "ivhd_get_rn": (i32, [vp, vp]),
     "ivhd_get_in_edges": (i32, [vp, i32, vp, vp]),
+    "ivhd_get_order": (i32, [vp, vp]),
+    "ivhd_set_state": (i32, [vp, vp, vp]),
+    "ivhd_set_iteration": (i32, [vp, i64]),
     "ivhd_get_iteration": (i32, [vp, ctypes.POINTER(i64)]),
     "ivhd_set_graphs": (i32, [vp, i32]),
     "ivhd_destroy": (i32, [vp]),

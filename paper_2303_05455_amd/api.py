@@ -19,7 +19,8 @@ MODES = {"det": 0, "atomic": 1}
 
 __all__ = [
     "IvhdError", "Context", "make_params", "ivhd_init", "ivhd_step", "ivhd_stress", "ivhd_grad",
-    "ivhd_get_rn", "ivhd_get_in_edges", "ivhd_get_iteration", "ivhd_set_graphs", "ivhd_destroy", "ivhd_last_error",
+    "ivhd_get_rn", "ivhd_get_in_edges", "ivhd_get_order", "ivhd_set_state", "ivhd_set_iteration",
+    "ivhd_get_iteration", "ivhd_set_graphs", "ivhd_destroy", "ivhd_last_error",
     "ivhd_version", "ivhd_knn_build", "ivhd_knn_query", "ivhd_edges_create", "ivhd_edges_stress",
     "ivhd_edges_grad", "ivhd_edges_destroy", "ivhd_grad_edges",
 ]
@@ -44,10 +45,15 @@ def _dev(t: torch.Tensor, dtype, shape, name: str) -> int:
     return t.data_ptr()
 
 
+FLAG_REORDER = 1
+
+
 def make_params(M: int, nn: int, rn: int, *, a: float, b: float, c: float, eps: float = 1e-12,
-                seed: int = 0, rn_resample_every: int = 0, mode: str = "det") -> ivhd_params:
+                seed: int = 0, rn_resample_every: int = 0, mode: str = "det",
+                reorder: bool = True) -> ivhd_params:
     return ivhd_params(M=M, nn=nn, rn=rn, a=a, b=b, c=c, eps=eps, seed=seed & (2**64 - 1),
-                       rn_resample_every=rn_resample_every, mode=MODES[mode])
+                       rn_resample_every=rn_resample_every, mode=MODES[mode],
+                       flags=FLAG_REORDER if reorder else 0, reserved=0)
 
 
 def ivhd_init(params: ivhd_params, nn_idx: torch.Tensor, y: torch.Tensor, v: torch.Tensor,
@@ -94,6 +100,22 @@ def ivhd_get_in_edges(ctx, which: int, ptr_out: torch.Tensor, src_out: torch.Ten
     _dev(src_out, torch.int32, tuple(src_out.shape), "src_out")
     check(_lib.load().ivhd_get_in_edges(ctx, int(which), ptr_out.data_ptr(), src_out.data_ptr()))
     return ptr_out, src_out
+
+
+def ivhd_get_order(ctx, out: torch.Tensor) -> torch.Tensor:
+    _dev(out, torch.int32, tuple(out.shape), "out")
+    check(_lib.load().ivhd_get_order(ctx, out.data_ptr()))
+    return out
+
+
+def ivhd_set_state(ctx, y: torch.Tensor, v: torch.Tensor) -> None:
+    _dev(y, torch.float32, tuple(y.shape), "y")
+    _dev(v, torch.float32, tuple(y.shape), "v")
+    check(_lib.load().ivhd_set_state(ctx, y.data_ptr(), v.data_ptr()))
+
+
+def ivhd_set_iteration(ctx, n: int) -> None:
+    check(_lib.load().ivhd_set_iteration(ctx, int(n)))
 
 
 def ivhd_get_iteration(ctx) -> int:
@@ -209,13 +231,13 @@ class Context:
 
     def __init__(self, nn_idx: torch.Tensor, y: torch.Tensor, v: Optional[torch.Tensor] = None, *,
                  rn: int = 1, a: float = 0.9, b: float = 0.01, c: float = 0.1, eps: float = 1e-12,
-                 seed: int = 0, rn_resample_every: int = 0, mode: str = "det",
+                 seed: int = 0, rn_resample_every: int = 0, mode: str = "det", reorder: bool = True,
                  stream: Optional[torch.cuda.Stream] = None):
         M, nn = nn_idx.shape
         if v is None:
             v = torch.zeros_like(y)
         self.params = make_params(M, nn, rn, a=a, b=b, c=c, eps=eps, seed=seed,
-                                  rn_resample_every=rn_resample_every, mode=mode)
+                                  rn_resample_every=rn_resample_every, mode=mode, reorder=reorder)
         self.nn_idx, self.y, self.v = nn_idx, y, v
         self.M, self.nn, self.rn = M, nn, rn
         self._h = None
@@ -243,8 +265,19 @@ class Context:
         out = torch.empty((self.M, self.rn), dtype=torch.int32, device=self.y.device)
         return ivhd_get_rn(self.handle, out)
 
+    def order(self) -> torch.Tensor:
+        """perm [M]: the caller's id of each internal vertex."""
+        out = torch.empty(self.M, dtype=torch.int32, device=self.y.device)
+        return ivhd_get_order(self.handle, out)
+
+    def set_state(self, y: torch.Tensor, v: torch.Tensor) -> None:
+        ivhd_set_state(self.handle, y.contiguous(), v.contiguous())
+
+    def set_iteration(self, n: int) -> None:
+        ivhd_set_iteration(self.handle, n)
+
     def in_edges(self, which: str = "nn"):
-        """(ptr [M+1], src) of the transposed nn or rn edge lists, on the host."""
+        """(ptr [M+1], src) of the transposed nn or rn edge lists (internal order), on the host."""
         k = self.nn if which == "nn" else self.rn
         ptr = torch.empty(self.M + 1, dtype=torch.int32, device=self.y.device)
         src = torch.empty(max(1, self.M * k), dtype=torch.int32, device=self.y.device)

@@ -99,8 +99,10 @@ __global__ void __launch_bounds__(kGemmThreads) gemm_kernel(GemmArgs g) {
 
   for (int64_t k0 = kbeg; k0 < kend; k0 += TK) {
     __syncthreads();
+    // A rows are m: opA[m][k] is P[row*ld + k] unless transposed.  B rows are
+    // n: opB[k][n] is P[row*ld + k] exactly when B is given transposed.
     stage<TA>(As, g.A, g.lda, g.M, m0, k0, kend, g.vec_a);
-    stage<TB>(Bs, g.B, g.ldb, g.N, n0, k0, kend, g.vec_b);
+    stage<!TB>(Bs, g.B, g.ldb, g.N, n0, k0, kend, g.vec_b);
     __syncthreads();
     const int kq = (lane >> 4) * 8;
     bf16x8 a[4], b[4];

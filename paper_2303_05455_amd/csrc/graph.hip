@@ -50,29 +50,103 @@ __global__ void epoch_begin_kernel(int64_t *epoch, int32_t *cnt, int64_t M, int3
   if (cnt && e <= M) cnt[e] = 0;
 }
 
+// perm / inv (both NULL or both set): the draw is defined on the caller's
+// vertex ids; thread p serves internal vertex p = inv[i], i = perm[p], and
+// stores the internal id inv[j] of each draw j
 __global__ void rn_sample_kernel(const int32_t *__restrict__ nn_idx, int64_t M, int nn, int rn,
                                  uint64_t seed, const int64_t *__restrict__ epoch_p,
+                                 const int32_t *__restrict__ perm, const int32_t *__restrict__ inv,
                                  int32_t *__restrict__ rn_idx, int32_t *__restrict__ cnt) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= M) return;
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= M) return;
+  const int64_t i = perm ? (int64_t)perm[p] : p;
   const uint64_t e = (uint64_t)(*epoch_p);
   const uint64_t range = (uint64_t)(M - 1);
   for (int r = 0; r < rn; ++r) {
-    int64_t pick = -1;
+    int32_t pick = -1;
     for (int t = 0; t < 256; ++t) {
       uint64_t ctr = ((e * (uint64_t)M + (uint64_t)i) * (uint64_t)rn + (uint64_t)r) * 256u + (uint64_t)t;
       uint64_t h = splitmix64(seed ^ splitmix64(ctr));
       int64_t j = (int64_t)(h % range);
       if (j >= i) j += 1;
+      const int32_t js = inv ? inv[j] : (int32_t)j;
       bool clash = false;
       for (int q = 0; q < nn; ++q) clash |= (nn_idx[i * nn + q] == j);
-      for (int q = 0; q < r; ++q) clash |= (rn_idx[i * rn + q] == j);
-      pick = j;
+      for (int q = 0; q < r; ++q) clash |= (rn_idx[p * rn + q] == js);
+      pick = js;
       if (!clash) break;
     }
-    rn_idx[i * rn + r] = (int32_t)pick;
+    rn_idx[p * rn + r] = pick;
     if (cnt) atomicAdd(&cnt[pick], 1);
   }
+}
+
+// connected components of the undirected nn graph: parent pointers that only
+// decrease, hooked across every edge and shortened by pointer jumping; at the
+// fixed point every vertex points at the smallest id of its component
+__global__ void cc_init_kernel(int32_t *parent, int64_t M) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < M) parent[i] = (int32_t)i;
+}
+
+__global__ void cc_hook_kernel(const int32_t *__restrict__ nn_idx, int64_t M, int nn, int32_t *parent,
+                               int32_t *changed) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * nn) return;
+  const int32_t j = nn_idx[e];
+  if (j < 0) return;
+  const int32_t pi = parent[e / nn], pj = parent[j];
+  if (pi == pj) return;
+  const int32_t lo = pi < pj ? pi : pj, hi = pi < pj ? pj : pi;
+  atomicMin(&parent[hi], lo);
+  *changed = 1;
+}
+
+__global__ void cc_shortcut_kernel(int32_t *parent, int64_t M) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  int32_t p = parent[i];
+  int32_t gp = parent[p];
+  while (p != gp) {
+    p = gp;
+    gp = parent[p];
+  }
+  parent[i] = p;
+}
+
+__global__ void inverse_perm_kernel(const int32_t *__restrict__ perm, int64_t M, int32_t *__restrict__ inv) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < M) inv[perm[p]] = (int32_t)p;
+}
+
+// out[p][q] = inv[idx[perm[p]][q]] (absent slots stay -1)
+__global__ void map_lists_kernel(const int32_t *__restrict__ idx, int64_t M, int k, const int32_t *__restrict__ perm,
+                                 const int32_t *__restrict__ inv, int32_t *__restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * k) return;
+  const int64_t p = e / k;
+  const int q = (int)(e % k);
+  const int32_t j = idx[(int64_t)perm[p] * k + q];
+  out[e] = j < 0 ? -1 : inv[j];
+}
+
+// out[i][q] = perm[lists[inv[i]][q]] (back to the caller's ids and order)
+__global__ void unmap_lists_kernel(const int32_t *__restrict__ lists, int64_t M, int k,
+                                   const int32_t *__restrict__ perm, const int32_t *__restrict__ inv,
+                                   int32_t *__restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * k) return;
+  const int64_t i = e / k;
+  const int q = (int)(e % k);
+  const int32_t v = lists[(int64_t)inv[i] * k + q];
+  out[e] = v < 0 ? -1 : perm[v];
+}
+
+// dst[p] = src[idx[p]] for float2 rows
+__global__ void gather_f2_kernel(const float2 *__restrict__ src, const int32_t *__restrict__ idx, int64_t M,
+                                 float2 *__restrict__ dst) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < M) dst[p] = src[idx ? (int64_t)idx[p] : p];
 }
 
 __global__ void count_kernel(const int32_t *__restrict__ idx, int64_t M, int k, int32_t *cnt) {
@@ -245,9 +319,46 @@ hipError_t launch_epoch_begin(int64_t *epoch, int32_t *cnt, int64_t M, int32_t *
 }
 
 hipError_t launch_rn_sample(const int32_t *nn_idx, int64_t M, int nn, int rn, uint64_t seed,
-                            const int64_t *epoch, int32_t *rn_idx, int32_t *cnt, hipStream_t s) {
+                            const int64_t *epoch, const int32_t *perm, const int32_t *inv, int32_t *rn_idx,
+                            int32_t *cnt, hipStream_t s) {
   if (rn == 0) return hipSuccess;
-  rn_sample_kernel<<<grid_for(M), kBlock, 0, s>>>(nn_idx, M, nn, rn, seed, epoch, rn_idx, cnt);
+  rn_sample_kernel<<<grid_for(M), kBlock, 0, s>>>(nn_idx, M, nn, rn, seed, epoch, perm, inv, rn_idx, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_cc_init(int32_t *parent, int64_t M, hipStream_t s) {
+  cc_init_kernel<<<grid_for(M), kBlock, 0, s>>>(parent, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_cc_round(const int32_t *nn_idx, int64_t M, int nn, int32_t *parent, int32_t *changed,
+                           hipStream_t s) {
+  cc_hook_kernel<<<grid_for(M * nn), kBlock, 0, s>>>(nn_idx, M, nn, parent, changed);
+  cc_shortcut_kernel<<<grid_for(M), kBlock, 0, s>>>(parent, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_inverse_perm(const int32_t *perm, int64_t M, int32_t *inv, hipStream_t s) {
+  inverse_perm_kernel<<<grid_for(M), kBlock, 0, s>>>(perm, M, inv);
+  return hipGetLastError();
+}
+
+hipError_t launch_map_lists(const int32_t *idx, int64_t M, int k, const int32_t *perm, const int32_t *inv,
+                            int32_t *out, hipStream_t s) {
+  if (k == 0) return hipSuccess;
+  map_lists_kernel<<<grid_for(M * k), kBlock, 0, s>>>(idx, M, k, perm, inv, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_unmap_lists(const int32_t *lists, int64_t M, int k, const int32_t *perm, const int32_t *inv,
+                              int32_t *out, hipStream_t s) {
+  if (k == 0) return hipSuccess;
+  unmap_lists_kernel<<<grid_for(M * k), kBlock, 0, s>>>(lists, M, k, perm, inv, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_f2(const float2 *src, const int32_t *idx, int64_t M, float2 *dst, hipStream_t s) {
+  gather_f2_kernel<<<grid_for(M), kBlock, 0, s>>>(src, idx, M, dst);
   return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@ constexpr int kSmallSegment = 32;    // in-edge segments up to this size are sor
 constexpr int kBigSortBlocks = 256;  // blocks that share the list of large segments
 constexpr int kHeavyDegree = 24;     // nn in-degree above which a vertex gets a whole wavefront
 constexpr int kHeavyPerBlock = kBlock / 64;
+constexpr int kXcds = 8;             // MI355X: 8 XCDs, workgroups dealt round-robin
 
 // device flag slots
 enum { FLAG_BAD_INDEX = 0, FLAG_NONFINITE = 1, FLAG_BIG_COUNT = 2, FLAG_SLOTS = 4 };
@@ -71,9 +72,21 @@ hipError_t launch_validate_idx(const int32_t *idx, int64_t M, int k, int32_t lo,
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t value, hipStream_t s);
 // Begins a random-neighbour epoch: epoch += 1; when cnt != NULL zeroes cnt[0..M] and flags[FLAG_BIG_COUNT].
 hipError_t launch_epoch_begin(int64_t *epoch, int32_t *cnt, int64_t M, int32_t *flags, hipStream_t s);
-// rn draw for epoch *epoch; when cnt != NULL also counts in-degrees into cnt.
+// rn draw for epoch *epoch (caller ids; with perm/inv stored as internal ids in
+// internal row order); when cnt != NULL also counts in-degrees into cnt.
 hipError_t launch_rn_sample(const int32_t *nn_idx, int64_t M, int nn, int rn, uint64_t seed,
-                            const int64_t *epoch, int32_t *rn_idx, int32_t *cnt, hipStream_t s);
+                            const int64_t *epoch, const int32_t *perm, const int32_t *inv, int32_t *rn_idx,
+                            int32_t *cnt, hipStream_t s);
+// connected components (parent -> smallest id of the component)
+hipError_t launch_cc_init(int32_t *parent, int64_t M, hipStream_t s);
+hipError_t launch_cc_round(const int32_t *nn_idx, int64_t M, int nn, int32_t *parent, int32_t *changed,
+                           hipStream_t s);
+hipError_t launch_inverse_perm(const int32_t *perm, int64_t M, int32_t *inv, hipStream_t s);
+hipError_t launch_map_lists(const int32_t *idx, int64_t M, int k, const int32_t *perm, const int32_t *inv,
+                            int32_t *out, hipStream_t s);
+hipError_t launch_unmap_lists(const int32_t *lists, int64_t M, int k, const int32_t *perm, const int32_t *inv,
+                              int32_t *out, hipStream_t s);
+hipError_t launch_gather_f2(const float2 *src, const int32_t *idx, int64_t M, float2 *dst, hipStream_t s);
 // in-degree count of an [M][k] index list (entries < 0 skipped); cnt must be zero.
 hipError_t launch_count(const int32_t *idx, int64_t M, int k, int32_t *cnt, hipStream_t s);
 // From counts cnt[0..M-1]: ptr = exclusive scan (ptr[M] = total), cnt = cursor copy.
@@ -97,17 +110,31 @@ struct StepArgs {
   const float *gscale;    // gradient kernels: output scaled by *gscale (NULL = 1)
   const int32_t *heavy;   // vertices whose nn in-degree exceeds kHeavyDegree
   int32_t n_heavy;
-  int32_t heavy_blocks;   // leading blocks of a launch that serve the heavy vertices
+  int32_t heavy_blocks;   // leading blocks of a launch that serve the heavy vertices (multiple of kXcds)
+  int32_t light_tiles;    // tiles of kBlock consecutive vertices
+  int32_t tiles_per_xcd;  // consecutive tiles given to each XCD
   int64_t M;
   int nn, rn;
   float a, b, c, eps;
 };
+// launch shape of the deterministic kernel: heavy blocks first (rounded to a
+// multiple of kXcds so the round-robin phase is kept), then the light tiles,
+// XCD x taking tiles [x * tiles_per_xcd, (x + 1) * tiles_per_xcd)
+inline void set_launch_shape(StepArgs &a) {
+  const int32_t hb = (a.n_heavy + kHeavyPerBlock - 1) / kHeavyPerBlock;
+  a.heavy_blocks = (hb + kXcds - 1) / kXcds * kXcds;
+  a.light_tiles = (int32_t)((a.M + kBlock - 1) / kBlock);
+  a.tiles_per_xcd = (a.light_tiles + kXcds - 1) / kXcds;
+}
 hipError_t launch_step_det(const StepArgs &a, hipStream_t s);
 hipError_t launch_step_atomic(const StepArgs &a, hipStream_t s);   // two kernels
 // grad E = -2 f at positions a.y into out (det gather; or atomic scatter via fbuf)
 hipError_t launch_grad_det(const StepArgs &a, float2 *out, hipStream_t s);
 hipError_t launch_grad_atomic(const StepArgs &a, float2 *out, hipStream_t s);
 
+// transposed lists of an [M][k] index list into g; the heavy list (synchronises s)
+int build_csc(const int32_t *idx, int64_t M, int k, Csc &g, CscScratch &sc, int32_t *flags, hipStream_t s);
+int build_heavy(const Csc &nn_csc, int64_t M, int32_t *heavy, int32_t *flags, int32_t *n_heavy, hipStream_t s);
 // list the vertices with nn in-degree > kHeavyDegree (order arbitrary); *count must be zero
 hipError_t launch_heavy_list(const int32_t *nn_ptr, int64_t M, int32_t *list, int32_t *count,
                              hipStream_t s);

@@ -1,0 +1,259 @@
+// Host side of the stateless parts of the C ABI: edge plans (the stress and
+// its gradient for caller-given edge lists) and the exact kNN builder.
+#include <cmath>
+#include <mutex>
+#include <new>
+#include <unordered_set>
+
+#include "ivhd_internal.h"
+
+using namespace ivhd;
+
+namespace ivhd {
+
+// transposed lists of an [M][k] index list into g (sources ascending per target)
+int build_csc(const int32_t *idx, int64_t M, int k, Csc &g, CscScratch &sc, int32_t *flags,
+              hipStream_t s) {
+  HIPCHK(launch_fill_i32(sc.cnt, M + 1, 0, s));
+  HIPCHK(launch_fill_i32(flags + FLAG_BIG_COUNT, 1, 0, s));
+  HIPCHK(launch_count(idx, M, k, sc.cnt, s));
+  HIPCHK(launch_scan(sc.cnt, M, sc.part, g.ptr, s));
+  HIPCHK(launch_scatter_sort(idx, M, k, g.ptr, sc.cnt, sc.tmp, sc.big, flags, g.src, s));
+  return IVHD_OK;
+}
+
+// the vertices of nn in-degree above kHeavyDegree; synchronises s to read the count
+int build_heavy(const Csc &nn_csc, int64_t M, int32_t *heavy, int32_t *flags, int32_t *n_heavy,
+                hipStream_t s) {
+  HIPCHK(launch_fill_i32(flags + FLAG_BIG_COUNT, 1, 0, s));
+  HIPCHK(launch_heavy_list(nn_csc.ptr, M, heavy, flags + FLAG_BIG_COUNT, s));
+  HIPCHK(hipMemcpyAsync(n_heavy, flags + FLAG_BIG_COUNT, sizeof *n_heavy, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return IVHD_OK;
+}
+
+}  // namespace ivhd
+
+extern "C" {
+
+// ---- edge plans: the stress and its gradient for caller-given edge lists ----
+
+struct ivhd_edges {
+  int64_t M = 0;
+  int32_t nn = 0, rn = 0;
+  const int32_t *nn_idx = nullptr, *rn_idx = nullptr;
+  hipStream_t stream = nullptr;
+  Csc nn_csc, rn_csc;
+  CscScratch sc;
+  int32_t *heavy = nullptr;
+  int32_t n_heavy = 0;
+  int32_t *flags = nullptr;
+  double *partials = nullptr;
+  int nparts = 0;
+};
+
+namespace {
+std::mutex g_edges_mu;
+std::unordered_set<const ivhd_edges *> g_edges_live;
+
+bool edges_live(const ivhd_edges *e) {
+  if (!e) return false;
+  std::lock_guard<std::mutex> lk(g_edges_mu);
+  return g_edges_live.count(e) != 0;
+}
+
+void free_edges(ivhd_edges *e) {
+  if (!e) return;
+  void *bufs[] = {e->nn_csc.ptr, e->nn_csc.src, e->rn_csc.ptr, e->rn_csc.src, e->sc.cnt,
+                  e->sc.tmp, e->sc.part, e->sc.big, e->heavy, e->flags, e->partials};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+  delete e;
+}
+
+StepArgs edge_args(const ivhd_edges *e, const float2 *y, float c, float eps, const float *gscale) {
+  StepArgs a{};
+  a.y = y;
+  a.nn_idx = e->nn_idx;
+  a.rn_idx = e->rn_idx;
+  a.nn_ptr = e->nn_csc.ptr;
+  a.nn_src = e->nn_csc.src;
+  a.rn_ptr = e->rn_csc.ptr;
+  a.rn_src = e->rn_csc.src;
+  a.flags = e->flags;
+  a.gscale = gscale;
+  a.heavy = e->heavy;
+  a.n_heavy = e->n_heavy;
+  a.M = e->M;
+  a.nn = e->nn;
+  a.rn = e->rn;
+  a.c = c;
+  a.eps = eps;
+  set_launch_shape(a);
+  return a;
+}
+}  // namespace
+
+int ivhd_edges_create(ivhd_edges **out, int64_t M, const int32_t *d_nn_idx, int32_t nn,
+                      const int32_t *d_rn_idx, int32_t rn, void *stream) {
+  clear_error();
+  if (!out) return fail(IVHD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (M < 2 || M > (int64_t)INT32_MAX - 1) return fail(IVHD_EINVAL, "M = %lld outside [2, 2^31-2]", (long long)M);
+  if (nn < 1 || nn > 64) return fail(IVHD_EINVAL, "nn = %d outside [1, 64]", nn);
+  if (rn < 0 || rn > 64) return fail(IVHD_EINVAL, "rn = %d outside [0, 64]", rn);
+  if (M * (int64_t)(nn > rn ? nn : rn) > (int64_t)INT32_MAX)
+    return fail(IVHD_EINVAL, "M * max(nn, rn) exceeds 2^31-1 edges");
+  if (!d_nn_idx) return fail(IVHD_EINVAL, "d_nn_idx is NULL");
+  if (rn > 0 && !d_rn_idx) return fail(IVHD_EINVAL, "d_rn_idx is NULL while rn > 0");
+  ivhd_edges *e = new (std::nothrow) ivhd_edges();
+  if (!e) return fail(IVHD_ENOMEM, "host allocation of the edge plan failed");
+  e->M = M;
+  e->nn = nn;
+  e->rn = rn;
+  e->nn_idx = d_nn_idx;
+  e->rn_idx = rn > 0 ? d_rn_idx : nullptr;
+  e->stream = (hipStream_t)stream;
+  const int64_t nb = (M + kScanChunk - 1) / kScanChunk;
+  int rc;
+#define E_CHK(expr)  \
+  do {               \
+    rc = (expr);     \
+    if (rc) {        \
+      free_edges(e); \
+      return rc;     \
+    }                \
+  } while (0)
+#define E_HIP(expr)                     \
+  do {                                  \
+    hipError_t _e = (expr);             \
+    if (_e != hipSuccess) {             \
+      rc = hip_fail(_e, #expr);         \
+      free_edges(e);                    \
+      return rc;                        \
+    }                                   \
+  } while (0)
+  E_CHK(dev_alloc(&e->nn_csc.ptr, M + 1, "nn in-edge offsets"));
+  E_CHK(dev_alloc(&e->nn_csc.src, M * nn, "nn in-edge sources"));
+  if (rn > 0) {
+    E_CHK(dev_alloc(&e->rn_csc.ptr, M + 1, "rn in-edge offsets"));
+    E_CHK(dev_alloc(&e->rn_csc.src, M * rn, "rn in-edge sources"));
+  }
+  E_CHK(dev_alloc(&e->sc.cnt, M + 1, "CSC counts"));
+  E_CHK(dev_alloc(&e->sc.tmp, M * (nn > rn ? nn : rn), "CSC scatter buffer"));
+  E_CHK(dev_alloc(&e->sc.part, nb + 1, "scan partials"));
+  E_CHK(dev_alloc(&e->sc.big, M, "large-segment list"));
+  E_CHK(dev_alloc(&e->heavy, M, "heavy-vertex list"));
+  E_CHK(dev_alloc(&e->flags, FLAG_SLOTS, "device flags"));
+  e->nparts = stress_partials(M);
+  E_CHK(dev_alloc(&e->partials, e->nparts, "stress partials"));
+  hipStream_t s = e->stream;
+  E_HIP(launch_fill_i32(e->flags, FLAG_SLOTS, 0, s));
+  E_HIP(launch_validate_idx(d_nn_idx, M, nn, -1, e->flags, s));
+  if (rn > 0) E_HIP(launch_validate_idx(d_rn_idx, M, rn, -1, e->flags, s));
+  int32_t hflags[FLAG_SLOTS];
+  E_HIP(hipMemcpyAsync(hflags, e->flags, sizeof hflags, hipMemcpyDeviceToHost, s));
+  E_HIP(hipStreamSynchronize(s));
+  if (hflags[FLAG_BAD_INDEX]) {
+    free_edges(e);
+    return fail(IVHD_EINVAL, "an nn or rn entry is outside [-1, M) or equals its row");
+  }
+  E_CHK(build_csc(d_nn_idx, M, nn, e->nn_csc, e->sc, e->flags, s));
+  if (rn > 0) E_CHK(build_csc(d_rn_idx, M, rn, e->rn_csc, e->sc, e->flags, s));
+  E_CHK(build_heavy(e->nn_csc, M, e->heavy, e->flags, &e->n_heavy, s));
+#undef E_CHK
+#undef E_HIP
+  {
+    std::lock_guard<std::mutex> lk(g_edges_mu);
+    g_edges_live.insert(e);
+  }
+  *out = e;
+  return IVHD_OK;
+}
+
+int ivhd_edges_stress(ivhd_edges *e, const float *d_y, float c, double *d_E) {
+  if (!edges_live(e)) return fail(IVHD_ESTATE, "invalid edge plan");
+  if (!d_y || !d_E) return fail(IVHD_EINVAL, "d_y and d_E must not be NULL");
+  if (!std::isfinite(c) || c < 0.f) return fail(IVHD_EINVAL, "c = %g must be finite and >= 0", (double)c);
+  HIPCHK(launch_stress((const float2 *)d_y, e->M, e->nn_idx, e->nn, e->rn_idx, e->rn, (double)c,
+                       e->partials, e->nparts, d_E, e->stream));
+  return IVHD_OK;
+}
+
+int ivhd_edges_grad(ivhd_edges *e, const float *d_y, float c, float eps, const float *d_scale,
+                    float *d_grad) {
+  if (!edges_live(e)) return fail(IVHD_ESTATE, "invalid edge plan");
+  if (!d_y || !d_grad) return fail(IVHD_EINVAL, "d_y and d_grad must not be NULL");
+  if (d_y == d_grad) return fail(IVHD_EINVAL, "d_y and d_grad alias");
+  if (!std::isfinite(c) || c < 0.f) return fail(IVHD_EINVAL, "c = %g must be finite and >= 0", (double)c);
+  if (!std::isfinite(eps) || eps < 0.f) return fail(IVHD_EINVAL, "eps = %g must be >= 0", (double)eps);
+  HIPCHK(launch_grad_det(edge_args(e, (const float2 *)d_y, c, eps, d_scale), (float2 *)d_grad, e->stream));
+  return IVHD_OK;
+}
+
+int ivhd_edges_destroy(ivhd_edges *e) {
+  if (!e) return IVHD_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_edges_mu);
+    if (!g_edges_live.erase(e)) return fail(IVHD_ESTATE, "invalid edge plan");
+  }
+  hipError_t err = hipStreamSynchronize(e->stream);
+  free_edges(e);
+  if (err != hipSuccess) return hip_fail(err, "hipStreamSynchronize");
+  return IVHD_OK;
+}
+
+int ivhd_grad_edges(const float *d_y, int64_t M, const int32_t *d_nn_idx, int32_t nn,
+                    const int32_t *d_rn_idx, int32_t rn, float c, float eps, float *d_grad,
+                    double *h_E, void *stream) {
+  ivhd_edges *e = nullptr;
+  int rc = ivhd_edges_create(&e, M, d_nn_idx, nn, d_rn_idx, rn, stream);
+  if (rc) return rc;
+  rc = ivhd_edges_grad(e, d_y, c, eps, nullptr, d_grad);
+  if (!rc && h_E) {
+    double *d_E = nullptr;
+    rc = dev_alloc(&d_E, 1, "stress result");
+    if (!rc) rc = ivhd_edges_stress(e, d_y, c, d_E);
+    if (!rc) {
+      hipError_t err = hipMemcpyAsync(h_E, d_E, sizeof(double), hipMemcpyDeviceToHost, e->stream);
+      if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
+      if (err != hipSuccess) rc = hip_fail(err, "stress copy");
+    }
+    if (d_E) (void)hipFree(d_E);
+  }
+  int rc2 = ivhd_edges_destroy(e);
+  return rc ? rc : rc2;
+}
+
+static int knn_common(const float *d_x, int64_t M, int32_t N, const float *d_q, int64_t Q,
+                      int self_mode, const int32_t *d_self, int32_t k, int32_t *d_idx,
+                      float *d_dist, void *stream) {
+  if (!d_x || !d_q || !d_idx) return fail(IVHD_EINVAL, "d_x, d_q and d_idx must not be NULL");
+  if (M < 2 || M > (int64_t)INT32_MAX - 1) return fail(IVHD_EINVAL, "M = %lld outside [2, 2^31-2]", (long long)M);
+  if (N < 1) return fail(IVHD_EINVAL, "N = %d must be >= 1", N);
+  if (Q < 0) return fail(IVHD_EINVAL, "Q = %lld < 0", (long long)Q);
+  const int64_t kmax = M - 1 < knn_max_k() ? M - 1 : knn_max_k();
+  if (k < 1 || k > kmax) return fail(IVHD_EINVAL, "k = %d outside [1, %lld]", k, (long long)kmax);
+  if (Q == 0) return IVHD_OK;
+  hipStream_t s = (hipStream_t)stream;
+  float *norms = nullptr;
+  int rc = dev_alloc(&norms, (size_t)M, "row norms");
+  if (rc) return rc;
+  hipError_t e = launch_row_norms(d_x, M, N, norms, s);
+  if (e == hipSuccess) e = launch_knn(d_x, M, N, d_q, Q, self_mode, d_self, norms, k, d_idx, d_dist, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(norms);
+  if (e != hipSuccess) return hip_fail(e, "knn");
+  return IVHD_OK;
+}
+
+int ivhd_knn_build(const float *d_x, int64_t M, int32_t N, int32_t k, int32_t *d_idx, void *stream) {
+  return knn_common(d_x, M, N, d_x, M, 1, nullptr, k, d_idx, nullptr, stream);
+}
+
+int ivhd_knn_query(const float *d_x, int64_t M, int32_t N, const float *d_q, int64_t Q,
+                   const int32_t *d_self, int32_t k, int32_t *d_idx, float *d_dist, void *stream) {
+  return knn_common(d_x, M, N, d_q, Q, d_self ? 2 : 0, d_self, k, d_idx, d_dist, stream);
+}
+
+}  // extern "C"

@@ -152,7 +152,13 @@ __global__ void __launch_bounds__(kBlock) det_kernel(StepArgs A, float2 *out) {
     }
     return;
   }
-  const int64_t i = (int64_t)(blockIdx.x - A.heavy_blocks) * kBlock + threadIdx.x;
+  // XCD-aware tiles: blocks are dealt to the XCDs round-robin, so block b runs
+  // on XCD b % kXcds; each XCD is given one contiguous range of tiles, keeping
+  // the positions its vertices gather from in its own L2
+  const int32_t lb = (int32_t)blockIdx.x - A.heavy_blocks;
+  const int32_t tile = (lb % kXcds) * A.tiles_per_xcd + lb / kXcds;
+  if (tile >= A.light_tiles) return;
+  const int64_t i = (int64_t)tile * kBlock + threadIdx.x;
   if (i >= A.M) return;
   const int32_t ns = A.nn_ptr[i], ne = A.nn_ptr[i + 1];
   if (ne - ns > kHeavyDegree) return;   // served by a heavy wavefront
@@ -217,7 +223,7 @@ __global__ void __launch_bounds__(kBlock) atomic_grad_out_kernel(float2 *fbuf, i
   out[i] = make_float2(g * f.x, g * f.y);
 }
 
-unsigned det_grid(const StepArgs &a) { return (unsigned)a.heavy_blocks + grid_for(a.M); }
+unsigned det_grid(const StepArgs &a) { return (unsigned)(a.heavy_blocks + kXcds * a.tiles_per_xcd); }
 
 }  // namespace
 

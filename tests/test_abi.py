@@ -41,14 +41,15 @@ def test_binding_covers_every_declared_symbol():
 
 def test_struct_layout_matches_header():
     from paper_2303_05455_amd._lib import ivhd_params
-    assert ctypes.sizeof(ivhd_params) == 48
+    assert ctypes.sizeof(ivhd_params) == 56
     assert ivhd_params.seed.offset == 32 and ivhd_params.mode.offset == 44
+    assert ivhd_params.flags.offset == 48
 
 
 def _params(**kw):
     from paper_2303_05455_amd._lib import ivhd_params
     base = dict(M=100, nn=2, rn=1, a=0.9, b=0.01, c=0.1, eps=1e-12, seed=0,
-                rn_resample_every=0, mode=0)
+                rn_resample_every=0, mode=0, flags=1, reserved=0)
     base.update(kw)
     return ivhd_params(**base)
 
@@ -62,7 +63,8 @@ FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
     (dict(a=1.5), "a ="), (dict(a=float("nan")), "a ="), (dict(b=0.0), "b ="),
     (dict(b=float("inf")), "b ="), (dict(c=0.0), "c ="), (dict(c=1.0), "c ="),
     (dict(eps=-1.0), "eps ="), (dict(rn_resample_every=-3), "rn_resample_every"),
-    (dict(mode=7), "mode ="), (dict(M=2**30, nn=4), "2^31-1 edges"),
+    (dict(mode=7), "mode ="), (dict(M=2**30, nn=4), "2^31-1 edges"), (dict(flags=6), "flags ="),
+    (dict(reserved=3), "reserved ="),
 ])
 def test_init_rejects_bad_parameters(lib, kw, frag):
     h = ctypes.c_void_p(123)
@@ -97,6 +99,9 @@ def test_calls_on_a_missing_or_foreign_context_report_state(lib):
         assert lib.ivhd_get_rn(ctx, FAKE) == -4
         assert lib.ivhd_get_iteration(ctx, ctypes.byref(n)) == -4
         assert lib.ivhd_set_graphs(ctx, 1) == -4
+        assert lib.ivhd_set_iteration(ctx, 0) == -4
+        assert lib.ivhd_set_state(ctx, FAKE, FAKE) == -4
+        assert lib.ivhd_get_order(ctx, FAKE) == -4
     assert lib.ivhd_destroy(None) == 0
     assert lib.ivhd_destroy(bogus) == -4
     assert "invalid context" in lib.ivhd_last_error().decode()

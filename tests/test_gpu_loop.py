@@ -77,12 +77,12 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("mode", ["det", "atomic"])
+@pytest.mark.parametrize("mode,reorder", [("det", True), ("det", False), ("atomic", True)])
 @pytest.mark.parametrize("M,nn,rn,seed,extra", CASES)
-def test_single_step_matches_oracle(ivhd, mode, M, nn, rn, seed, extra):
+def test_single_step_matches_oracle(ivhd, mode, reorder, M, nn, rn, seed, extra):
     a, b, c, eps = f32(0.9), f32(0.01), f32(0.1), f32(1e-12)
     nn_idx, Y, V = _case(M, nn, rn, seed, **extra)
-    ctx = _ctx(ivhd, nn_idx, Y, V, rn=rn, a=a, b=b, c=c, eps=eps, seed=seed, mode=mode)
+    ctx = _ctx(ivhd, nn_idx, Y, V, rn=rn, a=a, b=b, c=c, eps=eps, seed=seed, mode=mode, reorder=reorder)
     rn_idx = ctx.rn_edges().cpu().numpy()
     assert np.array_equal(rn_idx, oracle.rn_sample(nn_idx, rn, seed, 0))
     f_ref = oracle.force(Y, nn_idx, rn_idx, c, eps)
@@ -151,20 +151,77 @@ def test_resample_schedule_matches_oracle_draws(ivhd, mode):
     ctx.close()
 
 
+def _components(nn_idx, M):
+    """Component label (smallest id) of each vertex of the undirected nn graph."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    src = np.repeat(np.arange(M), nn_idx.shape[1])
+    dst = nn_idx.ravel()
+    keep = dst >= 0
+    A = sp.coo_matrix((np.ones(keep.sum()), (src[keep], dst[keep])), shape=(M, M))
+    _, lab = connected_components(A, directed=False)
+    first = np.full(lab.max() + 1, M)
+    np.minimum.at(first, lab, np.arange(M))
+    return first[lab]
+
+
+def _internal(lists, perm, inv):
+    out = lists[perm]
+    return np.where(out >= 0, inv[np.maximum(out, 0)], -1).astype(np.int32)
+
+
+@pytest.mark.parametrize("reorder", [True, False])
 @pytest.mark.parametrize("M,nn,rn,seed,extra", CASES)
-def test_in_edge_lists_are_the_exact_transpose(ivhd, M, nn, rn, seed, extra):
+def test_in_edge_lists_are_the_exact_transpose(ivhd, M, nn, rn, seed, extra, reorder):
     nn_idx, Y, V = _case(M, nn, rn, seed, **extra)
-    ctx = _ctx(ivhd, nn_idx, Y, V, rn=rn, seed=seed, rn_resample_every=3)
+    ctx = _ctx(ivhd, nn_idx, Y, V, rn=rn, seed=seed, rn_resample_every=3, reorder=reorder)
+    perm = ctx.order().cpu().numpy()
+    if reorder:
+        # vertices grouped by connected component (smallest id first), ids ascending inside
+        comp = _components(nn_idx, M)
+        assert np.array_equal(perm, np.lexsort((np.arange(M), comp)))
+    else:
+        assert np.array_equal(perm, np.arange(M))
+    inv = np.empty(M, np.int64)
+    inv[perm] = np.arange(M)
     for step in range(3):
         ptr, src = ctx.in_edges("nn")
-        want_ptr, want_src = _transpose(nn_idx, M)
+        want_ptr, want_src = _transpose(_internal(nn_idx, perm, inv), M)
         assert np.array_equal(ptr, want_ptr) and np.array_equal(src, want_src)
         if rn:
             ptr, src = ctx.in_edges("rn")
-            want_ptr, want_src = _transpose(ctx.rn_edges().cpu().numpy(), M)
+            want_ptr, want_src = _transpose(_internal(ctx.rn_edges().cpu().numpy(), perm, inv), M)
             assert np.array_equal(ptr, want_ptr) and np.array_equal(src, want_src)
         ctx.step(3)
     ctx.close()
+
+
+def test_checkpoint_and_resume_is_bitwise(ivhd):
+    nn_idx, Y, V = _case(5000, 3, 1, 14, hub=0.6)
+    kw = dict(rn=1, b=5e-4, seed=21, rn_resample_every=6)
+    ref = _ctx(ivhd, nn_idx, Y.copy(), V.copy(), **kw)
+    ref.step(30)
+    torch.cuda.synchronize()
+    want_y, want_v = ref.y.cpu().numpy().copy(), ref.v.cpu().numpy().copy()
+    ref.close()
+    first = _ctx(ivhd, nn_idx, Y.copy(), V.copy(), **kw)
+    first.step(17)
+    torch.cuda.synchronize()
+    ck_y, ck_v, ck_n = first.y.cpu().numpy().copy(), first.v.cpu().numpy().copy(), first.iteration
+    first.close()
+    resumed = _ctx(ivhd, nn_idx, ck_y, ck_v, **kw)
+    resumed.set_iteration(ck_n)
+    resumed.step(13)
+    torch.cuda.synchronize()
+    assert np.array_equal(resumed.y.cpu().numpy(), want_y)
+    assert np.array_equal(resumed.v.cpu().numpy(), want_v)
+    # set_state loads a layout into a running context
+    resumed.set_state(torch.from_numpy(ck_y).cuda(), torch.from_numpy(ck_v).cuda())
+    resumed.set_iteration(ck_n)
+    resumed.step(13)
+    torch.cuda.synchronize()
+    assert np.array_equal(resumed.y.cpu().numpy(), want_y)
+    resumed.close()
 
 
 def test_two_contexts_give_bitwise_equal_gradients_and_steps(ivhd):
