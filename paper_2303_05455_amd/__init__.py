@@ -8,14 +8,5 @@ for gfx950 behind a C ABI (include/ivhd.h).
 The HIP library (``libivhd.so``) is built in place by
 ``python -m paper_2303_05455_amd.build``; nothing here falls back to the CPU.
 """
-from .api import (Context, IvhdError, ivhd_destroy, ivhd_get_in_edges, ivhd_get_iteration,
-                  ivhd_get_rn, ivhd_grad, ivhd_init, ivhd_knn_build, ivhd_knn_query,
-                  ivhd_last_error, ivhd_set_graphs, ivhd_step, ivhd_stress, ivhd_version,
-                  make_params)
-
-__all__ = [
-    "Context", "IvhdError", "ivhd_destroy", "ivhd_get_in_edges", "ivhd_get_iteration",
-    "ivhd_knn_build", "ivhd_knn_query", "ivhd_get_rn", "ivhd_grad",
-    "ivhd_init", "ivhd_last_error", "ivhd_set_graphs", "ivhd_step", "ivhd_stress", "ivhd_version",
-    "make_params",
-]
+from .api import *  # noqa: F401,F403  (the C ABI under its own names, plus Context)
+from .api import __all__  # noqa: F401
