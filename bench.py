@@ -12,10 +12,17 @@ The JSON line also carries
   roofline      the deterministic step kernel's algorithmic bytes per launch
                 (32 M + 8 M (nn + rn)) over its average launch time, measured
                 with HIP events around back-to-back launches, against 8 TB/s;
-                `traffic` = HBM bytes per launch from rocprofv3 counters when
-                profiles/ holds figures taken on the current kernel source
+                `traffic` = HBM-side bytes per launch from rocprofv3 counters
+                when profiles/ holds figures taken on the current kernel source
   cpu_baseline  the FP64 oracle (plain C, one thread) timed on a bounded
-                sample of the same workload shape (rank 0, N = 1 only)
+                sample of the same workload shape (N = 1 only)
+
+Other workloads (one JSON line each, not the headline):
+  --config C2   the loop at the MNIST shape (70,000 x 784, nn = 5)
+  --config C4   the differentiable stress: forward (FP64 stress) and backward
+                (gradient kernel) at 1,000,000 points, nn = 5, rn = 1
+  --config C5   the parametric encoder: training throughput, embedding of the
+                held-out points, and their kNN preservation beside plain IVHD
 """
 from __future__ import annotations
 
@@ -33,8 +40,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
 STEP_SOURCE = os.path.join(ROOT, "paper_2303_05455_amd", "csrc", "step.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_det_C3_traffic.md")
+METRIC = "edge-updates/sec (M·(nn+rn)·iters/s) at M=1.4M + achieved HBM GB/s"
 
 
 def log(msg):
@@ -46,7 +55,7 @@ def source_digest(path=STEP_SOURCE) -> str:
 
 
 def stored_traffic():
-    """HBM bytes per launch of the det step kernel from the committed
+    """HBM-side bytes per launch of the det step kernel from the committed
     rocprofv3 counter summary, if it was taken on the current source."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -63,6 +72,11 @@ def alg_bytes(M, nn, rn):
     (32 B per vertex) plus, per edge, its index and its reaction delivered to
     the other end (8 B per edge)."""
     return 32 * M + 8 * M * (nn + rn)
+
+
+def events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
 def cpu_baseline(cfg, iters, seed=0):
@@ -102,51 +116,36 @@ def calibrate_copy(mib: int):
     print(json.dumps({"calibration_copy_bytes": n * 4, "launches": 3}))
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="C3")
-    ap.add_argument("--mode", default="both", choices=["det", "atomic", "both"])
-    ap.add_argument("--cpu-iters", type=int, default=200)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-graphs", action="store_true")
-    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB")
-    args = ap.parse_args()
-
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
-              file=sys.stderr)
-        sys.exit(2)
-
+def build_graph(cfg, dev):
     import torch
-    if args.calibrate_copy:
-        calibrate_copy(args.calibrate_copy)
-        return
-
     import synth
-    from paper_2303_05455_amd import Context, ivhd_knn_build
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
-    cfg = synth.CONFIGS[args.config]
-    M, nn, rn, R, T = cfg.M, cfg.nn, cfg.rn, cfg.R, cfg.T
-
+    from paper_2303_05455_amd import ivhd_knn_build
     t0 = time.perf_counter()
     X, labels, Y0 = synth.make_inputs(cfg)
-    log(f"inputs {cfg.name}: M={M} N={cfg.N} ({time.perf_counter() - t0:.1f} s)")
+    log(f"inputs {cfg.name}: M={cfg.M} N={cfg.N} ({time.perf_counter() - t0:.1f} s)")
     dX = torch.from_numpy(X).to(dev)
     del X
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    nn_idx = ivhd_knn_build(dX, nn)
+    nn_idx = ivhd_knn_build(dX, cfg.nn)
     torch.cuda.synchronize()
     knn_s = time.perf_counter() - t0
+    indeg = torch.bincount(nn_idx.view(-1).long()[nn_idx.view(-1) >= 0], minlength=cfg.M)
+    log(f"kNN graph (exact, nn={cfg.nn}) built in {knn_s:.2f} s; max nn in-degree {int(indeg.max())}")
+    return dX, labels, Y0, nn_idx, knn_s, int(indeg.max())
+
+
+def run_loop(args, cfg):
+    import torch
+    from paper_2303_05455_amd import Context
+    dev = torch.device("cuda:0")
+    M, nn, rn, R, T = cfg.M, cfg.nn, cfg.rn, cfg.R, cfg.T
+    dX, labels, Y0, nn_idx, knn_s, max_in = build_graph(cfg, dev)
     del dX
-    indeg = torch.bincount(nn_idx.view(-1).long(), minlength=M)
-    max_deg = int(indeg.max().item()) + nn + 2 * rn + 8
-    log(f"kNN graph (exact, nn={nn}) built in {knn_s:.2f} s; max nn in-degree {int(indeg.max())}")
+    # heavy-ball stability: b * lambda_max < 2 (1 + a), lambda_max <= max degree + 1
+    bound = 2 * (1 + cfg.a) / (max_in + nn + 2 * rn + 2)
+    if cfg.b > bound:
+        log(f"warning: b = {cfg.b} exceeds the stability bound {bound:.2g} of this graph")
 
     d_y0 = torch.from_numpy(Y0).to(dev)
     res = {}
@@ -163,7 +162,7 @@ def main():
         for _ in range(args.warmup):
             ctx.step(T)
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0, e1 = events()
         e0.record()
         for _ in range(args.steps):
             ctx.step(T)
@@ -195,7 +194,7 @@ def main():
         launches = 64 * 20
         ctx.step(128)
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0, e1 = events()
         e0.record()
         ctx.step(launches)
         e1.record()
@@ -203,11 +202,10 @@ def main():
         per_launch = e0.elapsed_time(e1) / 1e3 / launches
         ctx.close()
         achieved = alg_bytes(M, nn, rn) / per_launch / 1e9
-        traffic = stored_traffic()
         roofline = {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-            "kernel": "step_det_kernel", "alg_bytes_per_launch": alg_bytes(M, nn, rn),
+            "frac": achieved / HBM_PEAK_GBPS, "traffic": stored_traffic() if cfg.name == "C3" else None,
+            "kernel": "det_kernel", "alg_bytes_per_launch": alg_bytes(M, nn, rn),
             "us_per_launch": per_launch * 1e6,
         }
         log(f"det step kernel: {per_launch * 1e6:.2f} us/launch, {achieved:.0f} GB/s algorithmic "
@@ -221,8 +219,8 @@ def main():
 
     main_mode = "det" if "det" in res else modes[0]
     r = res[main_mode]
-    out = {
-        "metric": "edge-updates/sec (M·(nn+rn)·iters/s) at M=1.4M + achieved HBM GB/s",
+    return {
+        "metric": METRIC,
         "value": r["value"],
         "unit": "edge-updates/s",
         "n_gpus": 1,
@@ -237,19 +235,201 @@ def main():
         "config": {
             "workload": (f"{cfg.name}: IVHD loop, M={M:,} points N={cfg.N} ({cfg.K}-cluster "
                          f"{'Zipf(' + str(cfg.zipf_s) + ')' if cfg.sizes == 'zipf' else 'equal'} "
-                         f"Gaussian mixture), exact kNN nn={nn}, rn={rn} redrawn every {R} "
-                         f"iterations, {T} iterations per step, {main_mode} reduction"),
+                         f"Gaussian mixture), exact kNN nn={nn}, rn={rn} "
+                         f"{'redrawn every ' + str(R) + ' iterations' if R else 'drawn once'}, "
+                         f"{T} iterations per step, {main_mode} reduction"),
             "M": M, "N": cfg.N, "nn": nn, "rn": rn, "R": R, "T": T, "c": cfg.c, "a": cfg.a,
-            "b": cfg.b, "mode": main_mode, "graphs": not args.no_graphs,
+            "b": cfg.b, "mode": main_mode, "graphs": not args.no_graphs, "reorder": True,
         },
         "gbps_alg": r["gbps_alg"],
         "us_per_iter": r["us_per_iter"],
         "modes": res,
         "knn_build_s": knn_s,
-        "max_degree_bound": max_deg,
+        "max_nn_in_degree": max_in,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+
+
+def run_stress(args, cfg):
+    """Forward (FP64 stress) and backward (gradient) of the differentiable stress."""
+    import torch
+    from paper_2303_05455_amd import Context
+    from paper_2303_05455_amd.autograd import IVHDStress, StressEdges
+    dev = torch.device("cuda:0")
+    M, nn, rn = cfg.M, cfg.nn, cfg.rn
+    dX, labels, Y0, nn_idx, knn_s, max_in = build_graph(cfg, dev)
+    del dX
+    # the random neighbours come from the loop's own draw (epoch 0)
+    ctx = Context(nn_idx, torch.from_numpy(Y0).to(dev), rn=rn, c=cfg.c, seed=cfg.seed)
+    rn_idx = ctx.rn_edges()
+    ctx.close()
+    edges = StressEdges(nn_idx, rn_idx, c=cfg.c)
+    y = torch.from_numpy(Y0).to(dev).requires_grad_(True)
+    E_edges = M * (nn + rn)
+    for _ in range(args.warmup + 1):
+        loss = IVHDStress.apply(y, edges)
+        loss.backward()
+    torch.cuda.synchronize()
+    reps = max(args.steps, 1) * 20
+    e0, e1 = events()
+    e0.record()
+    for _ in range(reps):
+        edges.stress64(y.detach())
+    e1.record()
+    torch.cuda.synchronize()
+    t_fwd = e0.elapsed_time(e1) / 1e3 / reps
+    g = torch.empty_like(y)
+    e0, e1 = events()
+    e0.record()
+    for _ in range(reps):
+        edges.grad(y.detach(), out=g)
+    e1.record()
+    torch.cuda.synchronize()
+    t_bwd = e0.elapsed_time(e1) / 1e3 / reps
+    fwd_bytes = 8 * M + 4 * E_edges + 8
+    bwd_bytes = 16 * M + 8 * E_edges
+    log(f"stress forward {t_fwd * 1e6:.1f} us ({fwd_bytes / t_fwd / 1e9:.0f} GB/s), "
+        f"backward {t_bwd * 1e6:.1f} us ({bwd_bytes / t_bwd / 1e9:.0f} GB/s)")
+    return {
+        "metric": "differentiable IVHD stress: forward+backward edge evaluations/s at M=1M",
+        "value": E_edges / (t_fwd + t_bwd), "unit": "edges/s", "n_gpus": 1, "steps": reps,
+        "warmup": args.warmup, "ms_per_step": (t_fwd + t_bwd) * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 (FP64 stress accumulation)",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: IVHDStress autograd Function, M={M:,} N={cfg.N}, exact kNN "
+                               f"nn={nn}, rn={rn}", "M": M, "nn": nn, "rn": rn},
+        "forward_us": t_fwd * 1e6, "backward_us": t_bwd * 1e6,
+        "forward_gbps_alg": fwd_bytes / t_fwd / 1e9, "backward_gbps_alg": bwd_bytes / t_bwd / 1e9,
+        "knn_build_s": knn_s,
+    }
+
+
+def q_nx_gpu(Xd, Z, rows, k=10):
+    """Q_NX(k) over sampled query rows: exact k-NN sets in N-D and in 2-D (GPU
+    builder, ties by index), averaged agreement."""
+    import torch
+    from paper_2303_05455_amd import ivhd_knn_query
+    r = torch.from_numpy(rows.astype(np.int32)).to(Xd.device)
+    a = ivhd_knn_query(Xd, Xd[r.long()].contiguous(), k, self_idx=r).cpu().numpy()
+    Zc = Z.contiguous()
+    b = ivhd_knn_query(Zc, Zc[r.long()].contiguous(), k, self_idx=r).cpu().numpy()
+    return float(np.mean([len(np.intersect1d(a[i], b[i])) for i in range(len(rows))]) / k)
+
+
+def run_encoder(args, cfg):
+    """Parametric IVHD: train the MLP on the stress of its batches, embed the
+    held-out points, judge them by kNN preservation beside plain IVHD."""
+    import torch
+    import synth
+    from paper_2303_05455_amd import Context, ivhd_knn_build
+    from paper_2303_05455_amd.parametric import ParametricIVHD
+    dev = torch.device("cuda:0")
+    epochs = args.epochs
+    dX, labels, _, nn_idx, knn_s, max_in = build_graph(cfg, dev)
+    x16 = ParametricIVHD.to_bf16(dX)
+    del dX
+    torch.cuda.empty_cache()
+    Xh, lab_h, _ = synth.make_inputs(cfg, heldout=True)
+    dXh = torch.from_numpy(Xh).to(dev)
+    xh16 = ParametricIVHD.to_bf16(dXh)
+    enc = ParametricIVHD(cfg.N, (512, 512), batch=8192, nn=cfg.nn, rn=cfg.rn, c=cfg.c, lr=1e-3, seed=cfg.seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    enc.fit(x16, nn_idx, epochs=epochs)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    steps = epochs * ((cfg.M + 8191) // 8192)
+    rows = 8192 * (1 + cfg.nn + cfg.rn)
+    flop_step = rows * 2 * (3 * cfg.N * 512 + 3 * 512 * 512) - rows * 2 * cfg.N * 512  # no input gradient
+    log(f"trained {epochs} epochs ({steps} steps) in {t_train:.1f} s: "
+        f"{steps / t_train:.1f} steps/s, {flop_step * steps / t_train / 1e12:.0f} TFLOP/s; "
+        f"loss {enc.losses[0]:.4g} -> {enc.losses[-1]:.4g}")
+    Zh = torch.empty((cfg.M_heldout, 2), dtype=torch.float32, device=dev)
+    enc.embed(xh16, Zh)
+    torch.cuda.synchronize()
+    e0, e1 = events()
+    e0.record()
+    enc.embed(xh16, Zh)
+    e1.record()
+    torch.cuda.synchronize()
+    t_embed = e0.elapsed_time(e1) / 1e3
+    rows_q = np.random.default_rng(5).choice(cfg.M_heldout, 2000, replace=False)
+    q_enc = q_nx_gpu(dXh, Zh, rows_q)
+    # plain IVHD on the held-out points (its own kNN graph, 2000 iterations)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nn_h = ivhd_knn_build(dXh, cfg.nn)
+    y = torch.from_numpy(synth.init_positions(cfg.M_heldout, np.random.default_rng(1))).to(dev)
+    ctx = Context(nn_h, y, rn=cfg.rn, a=cfg.a, b=cfg.b, c=cfg.c, seed=1, rn_resample_every=100)
+    ctx.step(2000)
+    torch.cuda.synchronize()
+    t_ivhd = time.perf_counter() - t0
+    q_ivhd = q_nx_gpu(dXh, y, rows_q)
+    ctx.close()
+    # fallback: plain IVHD started from the encoder's layout, 200 iterations
+    y2 = Zh.clone()
+    t0 = time.perf_counter()
+    ctx = Context(nn_h, y2, rn=cfg.rn, a=cfg.a, b=cfg.b, c=cfg.c, seed=1, rn_resample_every=100)
+    ctx.step(200)
+    torch.cuda.synchronize()
+    t_fb = time.perf_counter() - t0
+    q_fb = q_nx_gpu(dXh, y2, rows_q)
+    ctx.close()
+    log(f"held-out {cfg.M_heldout}: encoder Q_NX(10)={q_enc:.4f} in {t_embed * 1e3:.2f} ms; "
+        f"plain IVHD Q_NX(10)={q_ivhd:.4f} in {t_ivhd:.2f} s; IVHD from encoder (200 it) "
+        f"Q_NX(10)={q_fb:.4f}")
+    return {
+        "metric": "parametric IVHD: held-out embedding points/s (MLP 784-512-512-2, BF16 MFMA)",
+        "value": cfg.M_heldout / t_embed, "unit": "points/s", "n_gpus": 1, "steps": steps,
+        "warmup": 0, "ms_per_step": t_train * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16 (FP32 accumulate)", "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: MLP {cfg.N}-512-512-2 trained {epochs} epochs on the stress of "
+                               f"batches of 8192 sources (nn={cfg.nn}, rn={cfg.rn}) over M={cfg.M:,}; "
+                               f"{cfg.M_heldout:,} held-out points embedded",
+                   "M": cfg.M, "N": cfg.N, "epochs": epochs, "batch": 8192},
+        "train_s": t_train, "train_steps_per_s": steps / t_train,
+        "train_tflops": flop_step * steps / t_train / 1e12,
+        "train_mfma_frac": flop_step * steps / t_train / 1e12 / BF16_PEAK_TFLOPS,
+        "loss_first_epoch": enc.losses[0], "loss_last_epoch": enc.losses[-1],
+        "embed_ms": t_embed * 1e3, "q_nx10_encoder": q_enc, "q_nx10_plain_ivhd": q_ivhd,
+        "plain_ivhd_s": t_ivhd, "q_nx10_ivhd_from_encoder_200it": q_fb, "fallback_s": t_fb,
+        "knn_build_s": knn_s,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="C3")
+    ap.add_argument("--mode", default="both", choices=["det", "atomic", "both"])
+    ap.add_argument("--cpu-iters", type=int, default=200)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-graphs", action="store_true")
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    import synth
+    cfg = synth.CONFIGS[args.config]
+    if cfg.name == "C4":
+        out = run_stress(args, cfg)
+    elif cfg.name == "C5":
+        out = run_encoder(args, cfg)
+    else:
+        out = run_loop(args, cfg)
     print(json.dumps(out))
 
 
