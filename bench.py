@@ -301,20 +301,24 @@ def run_stress(args, cfg):
                                f"nn={nn}, rn={rn}", "M": M, "nn": nn, "rn": rn},
         "forward_us": t_fwd * 1e6, "backward_us": t_bwd * 1e6,
         "forward_gbps_alg": fwd_bytes / t_fwd / 1e9, "backward_gbps_alg": bwd_bytes / t_bwd / 1e9,
-        "knn_build_s": knn_s,
+        "knn_build_s": knn_s, "max_nn_in_degree": max_in, "heldout_max_nn_in_degree": max_in_h,
     }
 
 
-def q_nx_gpu(Xd, Z, rows, k=10):
+def q_nx_gpu(Xd, Z, rows, k=10, labels=None):
     """Q_NX(k) over sampled query rows: exact k-NN sets in N-D and in 2-D (GPU
-    builder, ties by index), averaged agreement."""
+    builder, ties by index), averaged agreement; with labels also the
+    neighbour hit cf_k of the 2-D neighbours."""
     import torch
     from paper_2303_05455_amd import ivhd_knn_query
     r = torch.from_numpy(rows.astype(np.int32)).to(Xd.device)
     a = ivhd_knn_query(Xd, Xd[r.long()].contiguous(), k, self_idx=r).cpu().numpy()
     Zc = Z.contiguous()
     b = ivhd_knn_query(Zc, Zc[r.long()].contiguous(), k, self_idx=r).cpu().numpy()
-    return float(np.mean([len(np.intersect1d(a[i], b[i])) for i in range(len(rows))]) / k)
+    q = float(np.mean([len(np.intersect1d(a[i], b[i])) for i in range(len(rows))]) / k)
+    if labels is None:
+        return q
+    return q, float((labels[b] == labels[rows][:, None]).mean())
 
 
 def run_encoder(args, cfg):
@@ -355,17 +359,22 @@ def run_encoder(args, cfg):
     torch.cuda.synchronize()
     t_embed = e0.elapsed_time(e1) / 1e3
     rows_q = np.random.default_rng(5).choice(cfg.M_heldout, 2000, replace=False)
-    q_enc = q_nx_gpu(dXh, Zh, rows_q)
+    q_enc, cf_enc = q_nx_gpu(dXh, Zh, rows_q, labels=lab_h)
     # plain IVHD on the held-out points (its own kNN graph, 2000 iterations)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     nn_h = ivhd_knn_build(dXh, cfg.nn)
+    max_in_h = int(torch.bincount(nn_h.view(-1).long(), minlength=cfg.M_heldout).max())
+    bound_h = 2 * (1 + cfg.a) / (max_in_h + cfg.nn + 2 * cfg.rn + 2)
+    if cfg.b > bound_h:
+        log(f"warning: b = {cfg.b} exceeds the stability bound {bound_h:.2g} of the held-out graph "
+            f"(max nn in-degree {max_in_h})")
     y = torch.from_numpy(synth.init_positions(cfg.M_heldout, np.random.default_rng(1))).to(dev)
     ctx = Context(nn_h, y, rn=cfg.rn, a=cfg.a, b=cfg.b, c=cfg.c, seed=1, rn_resample_every=100)
     ctx.step(2000)
     torch.cuda.synchronize()
     t_ivhd = time.perf_counter() - t0
-    q_ivhd = q_nx_gpu(dXh, y, rows_q)
+    q_ivhd, cf_ivhd = q_nx_gpu(dXh, y, rows_q, labels=lab_h)
     ctx.close()
     # fallback: plain IVHD started from the encoder's layout, 200 iterations
     y2 = Zh.clone()
@@ -374,11 +383,11 @@ def run_encoder(args, cfg):
     ctx.step(200)
     torch.cuda.synchronize()
     t_fb = time.perf_counter() - t0
-    q_fb = q_nx_gpu(dXh, y2, rows_q)
+    q_fb, cf_fb = q_nx_gpu(dXh, y2, rows_q, labels=lab_h)
     ctx.close()
-    log(f"held-out {cfg.M_heldout}: encoder Q_NX(10)={q_enc:.4f} in {t_embed * 1e3:.2f} ms; "
-        f"plain IVHD Q_NX(10)={q_ivhd:.4f} in {t_ivhd:.2f} s; IVHD from encoder (200 it) "
-        f"Q_NX(10)={q_fb:.4f}")
+    log(f"held-out {cfg.M_heldout}: encoder Q_NX(10)={q_enc:.4f} cf_10={cf_enc:.3f} in {t_embed * 1e3:.2f} ms; "
+        f"plain IVHD Q_NX(10)={q_ivhd:.4f} cf_10={cf_ivhd:.3f} in {t_ivhd:.2f} s; IVHD from encoder "
+        f"(200 it) Q_NX(10)={q_fb:.4f} cf_10={cf_fb:.3f}")
     return {
         "metric": "parametric IVHD: held-out embedding points/s (MLP 784-512-512-2, BF16 MFMA)",
         "value": cfg.M_heldout / t_embed, "unit": "points/s", "n_gpus": 1, "steps": steps,
@@ -393,8 +402,10 @@ def run_encoder(args, cfg):
         "train_mfma_frac": flop_step * steps / t_train / 1e12 / BF16_PEAK_TFLOPS,
         "loss_first_epoch": enc.losses[0], "loss_last_epoch": enc.losses[-1],
         "embed_ms": t_embed * 1e3, "q_nx10_encoder": q_enc, "q_nx10_plain_ivhd": q_ivhd,
+        "cf10_encoder": cf_enc, "cf10_plain_ivhd": cf_ivhd, "cf10_ivhd_from_encoder_200it": cf_fb,
+        "q_nx10_random_layout": 10 / (cfg.M_heldout - 1),
         "plain_ivhd_s": t_ivhd, "q_nx10_ivhd_from_encoder_200it": q_fb, "fallback_s": t_fb,
-        "knn_build_s": knn_s,
+        "knn_build_s": knn_s, "max_nn_in_degree": max_in, "heldout_max_nn_in_degree": max_in_h,
     }
 
 
