@@ -220,7 +220,8 @@ int capture(ivhd_ctx *c, bool with_draw, int64_t count, int par, hipGraphExec_t 
 }
 
 // the internal order: vertices grouped by connected component of the nn
-// graph (components by their smallest caller id, members ascending)
+// graph (components by their smallest caller id), inside a component by nn
+// in-degree capped at kHeavyDegree + 1, then by caller id
 int build_order(ivhd_ctx *c) {
   const int64_t M = c->p.M;
   hipStream_t s = c->stream;
@@ -237,10 +238,10 @@ int build_order(ivhd_ctx *c) {
     if (!h) break;
     if (++rounds >= kCcMaxRounds) return fail(IVHD_EDEVICE, "connected components did not converge");
   }
-  Csc by_comp;
-  by_comp.ptr = c->nn_csc.ptr;          // scratch [M+1] until the nn lists are transposed
-  by_comp.src = c->perm;
-  int rc = build_csc(parent, M, 1, by_comp, c->sc, c->flags, s);
+  int32_t *indeg = c->sc.cnt;           // [M+1] scratch until the nn lists are transposed
+  HIPCHK(launch_fill_i32(indeg, M + 1, 0, s));
+  HIPCHK(launch_count(c->nn_user, M, c->p.nn, indeg, s));
+  int rc = sort_vertex_order(parent, indeg, M, c->perm, s);
   if (rc) return rc;
   HIPCHK(launch_inverse_perm(c->perm, M, c->inv, s));
   HIPCHK(launch_map_lists(c->nn_user, M, c->p.nn, c->perm, c->inv, c->nn_own, s));

@@ -96,6 +96,11 @@ hipError_t launch_scatter_sort(const int32_t *idx, int64_t M, int k, const int32
                                int32_t *cursor, int32_t *tmp, int32_t *big, int32_t *flags,
                                int32_t *src_out, hipStream_t s);
 
+// ---- order.hip ----
+// perm = the ids 0..M-1 sorted by (root[i], min(indeg[i], kHeavyDegree + 1), i);
+// synchronises s
+int sort_vertex_order(const int32_t *root, const int32_t *indeg, int64_t M, int32_t *perm, hipStream_t s);
+
 // ---- step.hip ----
 struct StepArgs {
   const float2 *y;        // positions read (Y_n)

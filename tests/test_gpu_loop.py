@@ -177,9 +177,11 @@ def test_in_edge_lists_are_the_exact_transpose(ivhd, M, nn, rn, seed, extra, reo
     ctx = _ctx(ivhd, nn_idx, Y, V, rn=rn, seed=seed, rn_resample_every=3, reorder=reorder)
     perm = ctx.order().cpu().numpy()
     if reorder:
-        # vertices grouped by connected component (smallest id first), ids ascending inside
+        # vertices grouped by connected component (smallest id first), then by
+        # nn in-degree capped at 25, then by id
         comp = _components(nn_idx, M)
-        assert np.array_equal(perm, np.lexsort((np.arange(M), comp)))
+        indeg = np.bincount(nn_idx[nn_idx >= 0].ravel(), minlength=M)
+        assert np.array_equal(perm, np.lexsort((np.arange(M), np.minimum(indeg, 25), comp)))
     else:
         assert np.array_equal(perm, np.arange(M))
     inv = np.empty(M, np.int64)
