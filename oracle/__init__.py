@@ -5,7 +5,9 @@ the CPU-baseline leg of the benchmark, never by the product package.  It
 shares no code with the HIP path; both read their inputs from ``synth``.
 
 * ``ivhd_oracle.c`` (plain C, FP64): stress, force, the random-neighbour
-  draw and the momentum loop, each written as the thesis defines it.
+  draw and the momentum loop, each written as the thesis defines it, with
+  the thesis's variants: Nesterov look-ahead, the l1 distance of the late
+  stage, and the reverse-neighbour edge mask.
 * this module: the ctypes binding of that file, plus numpy FP64 versions of
   the exact kNN graph and of the quality metrics of the thesis's
   "Quality metrics" chapter (trustworthiness / continuity, neighbour hit,
@@ -59,13 +61,19 @@ def _load():
         lib.orc_splitmix64.restype = u64
         lib.orc_rn_sample.argtypes = [i64, i32, vp, i32, u64, i64, vp]
         lib.orc_rn_sample.restype = None
-        lib.orc_force.argtypes = [i64, vp, i32, vp, i32, vp, dbl, dbl, vp]
+        lib.orc_force.argtypes = [i64, vp, i32, vp, i32, vp, dbl, dbl, i32, vp]
         lib.orc_force.restype = None
-        lib.orc_stress.argtypes = [i64, vp, i32, vp, i32, vp, dbl]
+        lib.orc_stress.argtypes = [i64, vp, i32, vp, i32, vp, dbl, i32]
         lib.orc_stress.restype = dbl
+        lib.orc_rnn_mask.argtypes = [i64, i32, vp, i32, vp, vp]
+        lib.orc_rnn_mask.restype = None
         lib.orc_run.argtypes = [i64, vp, vp, i32, vp, i32, vp, dbl, dbl, dbl, dbl, u64,
-                                i64, i64, i64, vp]
+                                i64, i64, i64, i32, i32, vp, vp]
         lib.orc_run.restype = None
+        lib.orc_run_adaptive.argtypes = [i64, vp, vp, i32, vp, i32, vp, dbl, vp, dbl, dbl, u64,
+                                         i64, i64, i64, dbl, dbl, dbl, i32, vp, vp, vp, vp,
+                                         vp, vp]
+        lib.orc_run_adaptive.restype = i64
         _lib = lib
         return lib
 
@@ -102,28 +110,43 @@ def rn_sample(nn_idx, rn: int, seed: int, epoch: int) -> np.ndarray:
     return out
 
 
-def force(Y, nn_idx, rn_idx, c: float, eps: float = 1e-12) -> np.ndarray:
-    """f = -1/2 grad E in FP64, float64 [M, 2]."""
+METRICS = {"l2": 0, "l1": 1}
+
+
+def force(Y, nn_idx, rn_idx, c: float, eps: float = 1e-12, metric: str = "l2") -> np.ndarray:
+    """f = -1/2 grad E in FP64, float64 [M, 2]; metric "l2" (Euclidean d) or
+    "l1" (d = |dx| + |dy|, the late-stage variant)."""
     nn_idx, rn_idx = _graph(nn_idx, rn_idx)
     Y = np.ascontiguousarray(Y, dtype=np.float64)
     M = Y.shape[0]
     f = np.empty((M, 2), dtype=np.float64)
     _load().orc_force(M, _ptr(Y), nn_idx.shape[1], _ptr(nn_idx), rn_idx.shape[1], _ptr(rn_idx),
-                      c, eps, _ptr(f))
+                      c, eps, METRICS[metric], _ptr(f))
     return f
 
 
-def grad(Y, nn_idx, rn_idx, c: float, eps: float = 1e-12) -> np.ndarray:
+def grad(Y, nn_idx, rn_idx, c: float, eps: float = 1e-12, metric: str = "l2") -> np.ndarray:
     """grad E = -2 f in FP64."""
-    return -2.0 * force(Y, nn_idx, rn_idx, c, eps)
+    return -2.0 * force(Y, nn_idx, rn_idx, c, eps, metric)
 
 
-def stress(Y, nn_idx, rn_idx, c: float) -> float:
-    """E(Y) in FP64 (Eq. ivhd_cost_function)."""
+def stress(Y, nn_idx, rn_idx, c: float, metric: str = "l2") -> float:
+    """E(Y) in FP64 (Eq. ivhd_cost_function, with the Euclidean or the l1 distance)."""
     nn_idx, rn_idx = _graph(nn_idx, rn_idx)
     Y = np.ascontiguousarray(Y, dtype=np.float64)
     return float(_load().orc_stress(Y.shape[0], _ptr(Y), nn_idx.shape[1], _ptr(nn_idx),
-                                    rn_idx.shape[1], _ptr(rn_idx), c))
+                                    rn_idx.shape[1], _ptr(rn_idx), c, METRICS[metric]))
+
+
+def rnn_mask(nn_idx, helper) -> np.ndarray:
+    """Reverse-neighbour pruning: nn edge i -> j kept (else -1) when i is
+    among the helper neighbours of j.  helper: int32 [M, kh]."""
+    nn_idx, _ = _graph(nn_idx)
+    helper = np.ascontiguousarray(helper, dtype=np.int32)
+    M, nn = nn_idx.shape
+    out = np.empty_like(nn_idx)
+    _load().orc_rnn_mask(M, nn, _ptr(nn_idx), helper.shape[1], _ptr(helper), _ptr(out))
+    return out
 
 
 def step(Y, V, f, a: float, b: float):
@@ -133,8 +156,10 @@ def step(Y, V, f, a: float, b: float):
 
 
 def run(Y0, V0, nn_idx, *, rn: int, a: float, b: float, c: float, eps: float = 1e-12,
-        seed: int = 0, R: int = 0, n0: int = 0, T: int = 1):
-    """T iterations of the loop from (Y0, V0) at iteration n0.
+        seed: int = 0, R: int = 0, n0: int = 0, T: int = 1, nesterov: bool = False,
+        metric: str = "l2"):
+    """T iterations of the loop from (Y0, V0) at iteration n0 (with
+    ``nesterov`` the force is taken at Y + a V).
 
     Returns (Y, V, rn_idx) in FP64; rn_idx is the last epoch's draw.
     """
@@ -144,9 +169,37 @@ def run(Y0, V0, nn_idx, *, rn: int, a: float, b: float, c: float, eps: float = 1
     V = np.array(V0, dtype=np.float64, order="C", copy=True)
     rn_idx = np.zeros((M, rn), dtype=np.int32)
     f = np.empty((M, 2), dtype=np.float64)
+    Yh = np.empty((M, 2), dtype=np.float64)
     _load().orc_run(M, _ptr(Y), _ptr(V), nn, _ptr(nn_idx), rn, _ptr(rn_idx), a, b, c, eps,
-                    seed & 0xFFFFFFFFFFFFFFFF, R, n0, T, _ptr(f))
+                    seed & 0xFFFFFFFFFFFFFFFF, R, n0, T, int(nesterov), METRICS[metric],
+                    _ptr(f), _ptr(Yh))
     return Y, V, rn_idx
+
+
+def run_adaptive(Y0, V0, nn_idx, *, rn: int, a: float, b: float, c: float, tau: float,
+                 g1: float, g2: float, eps: float = 1e-12, seed: int = 0, R: int = 0,
+                 n0: int = 0, T: int = 1, metric: str = "l2"):
+    """T iterations with the self-adaptive b (see ivhd_oracle.c).
+
+    Returns (Y, V, rn_idx, b, trace) with trace a dict of per-step arrays
+    dT (kinetic energy change of the tentative step), b (the b it used) and
+    kept (1 = step taken, 0 = rejected).
+    """
+    nn_idx, _ = _graph(nn_idx)
+    M, nn = nn_idx.shape
+    Y = np.array(Y0, dtype=np.float64, order="C", copy=True)
+    V = np.array(V0, dtype=np.float64, order="C", copy=True)
+    rn_idx = np.zeros((M, rn), dtype=np.int32)
+    scratch = [np.empty((M, 2), dtype=np.float64) for _ in range(3)]
+    dT = np.empty(T)
+    bs = np.empty(T)
+    kept = np.empty(T, dtype=np.int32)
+    bb = ctypes.c_double(b)
+    _load().orc_run_adaptive(M, _ptr(Y), _ptr(V), nn, _ptr(nn_idx), rn, _ptr(rn_idx), a,
+                             ctypes.byref(bb), c, eps, seed & 0xFFFFFFFFFFFFFFFF, R, n0, T, tau,
+                             g1, g2, METRICS[metric], _ptr(dT), _ptr(bs), _ptr(kept),
+                             *[_ptr(x) for x in scratch])
+    return Y, V, rn_idx, bb.value, {"dT": dT, "b": bs, "kept": kept}
 
 
 # ---------------------------------------------------------------------------

@@ -24,6 +24,22 @@
  *   step     V <- a V + b f ;  Y <- Y + V, all vertices from the same Y_n
  *            (Eq. ivhd_force_1 / ivhd_position_update; Eq.
  *             force_directed_update of Sec. "Force directed").
+ *            Nesterov variant (Sec. "Optimization methods", Nesterov): the
+ *            force is taken at the look-ahead layout Y + a V.
+ *   metric   d is the Euclidean distance; the late-stage variant of Sec.
+ *            "L1 norm in late stages of embedding" uses d = |dx| + |dy| in
+ *            the same stress, and its force is again -1/2 grad E, with the
+ *            subgradient sign(0) = 0 where a coordinate difference vanishes:
+ *            nn edge: F = -d (sign dx, sign dy)
+ *            rn edge: F = +c (1 - d) (sign dx, sign dy)
+ *   adapt    self-adaptive b of Sec. "Force directed": each step is first
+ *            taken tentatively; with dT = sum_i |V'_i|^2 - |V_i|^2 (the change
+ *            of kinetic energy), |dT| > tau rejects the step (Y and V stay)
+ *            and scales b by g1 > 1 when dT < -tau or by g2 < 1 when
+ *            dT > tau; otherwise the step is kept and b stays.
+ *   mask     reverse-neighbour pruning of Sec. "Reverse neighbors
+ *            mechanism": an nn edge i -> j is kept only when i is also
+ *            among the kh nearest neighbours of j in a wider helper graph.
  *   rn       per vertex, rn distinct random non-neighbours other than
  *            itself, drawn ad hoc (Sec. "Improving classical MDS"; the
  *            practical rules of Sec. "Force directed": a connected
@@ -80,9 +96,13 @@ void orc_rn_sample(int64_t M, int32_t nn, const int32_t *nn_idx, int32_t rn,
     }
 }
 
-/* f = -1/2 grad E, edge by edge; f must hold 2*M doubles (overwritten). */
+static double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
+
+/* f = -1/2 grad E, edge by edge; f must hold 2*M doubles (overwritten).
+ * metric 0: Euclidean distance, 1: l1 distance.                        */
 void orc_force(int64_t M, const double *Y, int32_t nn, const int32_t *nn_idx,
-               int32_t rn, const int32_t *rn_idx, double c, double eps, double *f)
+               int32_t rn, const int32_t *rn_idx, double c, double eps, int32_t metric,
+               double *f)
 {
     for (int64_t i = 0; i < 2 * M; ++i) f[i] = 0.0;
     for (int64_t i = 0; i < M; ++i) {
@@ -91,7 +111,15 @@ void orc_force(int64_t M, const double *Y, int32_t nn, const int32_t *nn_idx,
             if (j < 0) continue;                      /* absent neighbour */
             double dx = Y[2 * i] - Y[2 * j];
             double dy = Y[2 * i + 1] - Y[2 * j + 1];
-            double Fx = -dx, Fy = -dy;
+            double Fx, Fy;
+            if (metric == 0) {                        /* -1/2 d/dy_i of d^2 */
+                Fx = -dx;
+                Fy = -dy;
+            } else {
+                double d = fabs(dx) + fabs(dy);
+                Fx = -d * sgn(dx);
+                Fy = -d * sgn(dy);
+            }
             f[2 * i] += Fx;  f[2 * i + 1] += Fy;
             f[2 * j] -= Fx;  f[2 * j + 1] -= Fy;
         }
@@ -100,9 +128,17 @@ void orc_force(int64_t M, const double *Y, int32_t nn, const int32_t *nn_idx,
             if (k < 0) continue;                      /* absent slot */
             double dx = Y[2 * i] - Y[2 * k];
             double dy = Y[2 * i + 1] - Y[2 * k + 1];
-            double d = sqrt(dx * dx + dy * dy);
-            double s = c * (1.0 - d) / (d > eps ? d : eps);
-            double Fx = s * dx, Fy = s * dy;
+            double Fx, Fy;
+            if (metric == 0) {                        /* -1/2 d/dy_i of c (1 - d)^2 */
+                double d = sqrt(dx * dx + dy * dy);
+                double s = c * (1.0 - d) / (d > eps ? d : eps);
+                Fx = s * dx;
+                Fy = s * dy;
+            } else {
+                double d = fabs(dx) + fabs(dy);
+                Fx = c * (1.0 - d) * sgn(dx);
+                Fy = c * (1.0 - d) * sgn(dy);
+            }
             f[2 * i] += Fx;  f[2 * i + 1] += Fy;
             f[2 * k] -= Fx;  f[2 * k + 1] -= Fy;
         }
@@ -110,7 +146,7 @@ void orc_force(int64_t M, const double *Y, int32_t nn, const int32_t *nn_idx,
 }
 
 double orc_stress(int64_t M, const double *Y, int32_t nn, const int32_t *nn_idx,
-                  int32_t rn, const int32_t *rn_idx, double c)
+                  int32_t rn, const int32_t *rn_idx, double c, int32_t metric)
 {
     double E = 0.0;
     for (int64_t i = 0; i < M; ++i) {
@@ -119,35 +155,104 @@ double orc_stress(int64_t M, const double *Y, int32_t nn, const int32_t *nn_idx,
             if (j < 0) continue;
             double dx = Y[2 * i] - Y[2 * j];
             double dy = Y[2 * i + 1] - Y[2 * j + 1];
-            E += dx * dx + dy * dy;                   /* d_ij^2 */
+            double d = metric == 0 ? sqrt(dx * dx + dy * dy) : fabs(dx) + fabs(dy);
+            E += metric == 0 ? dx * dx + dy * dy : d * d;   /* d_ij^2 */
         }
         for (int32_t q = 0; q < rn; ++q) {
             int64_t k = rn_idx[i * rn + q];
             if (k < 0) continue;
             double dx = Y[2 * i] - Y[2 * k];
             double dy = Y[2 * i + 1] - Y[2 * k + 1];
-            double d = sqrt(dx * dx + dy * dy);
+            double d = metric == 0 ? sqrt(dx * dx + dy * dy) : fabs(dx) + fabs(dy);
             E += c * (1.0 - d) * (1.0 - d);           /* c (1 - d_ik)^2 */
         }
     }
     return E;
 }
 
+/* Reverse-neighbour mask: out[i][q] = nn_idx[i][q] when that j >= 0 lists
+ * i among its first kh helper neighbours, else -1.                      */
+void orc_rnn_mask(int64_t M, int32_t nn, const int32_t *nn_idx, int32_t kh,
+                  const int32_t *helper, int32_t *out)
+{
+    for (int64_t i = 0; i < M; ++i) {
+        for (int32_t q = 0; q < nn; ++q) {
+            int64_t j = nn_idx[i * nn + q];
+            int keep = 0;
+            if (j >= 0)
+                for (int32_t r = 0; r < kh; ++r)
+                    if (helper[j * kh + r] == i) keep = 1;
+            out[i * nn + q] = keep ? (int32_t)j : -1;
+        }
+    }
+}
+
 /* T iterations starting at iteration n0.  Y, V: 2*M doubles, updated in
- * place.  rn_idx: M*rn ints, in/out.  f: 2*M doubles of scratch.
+ * place.  rn_idx: M*rn ints, in/out.  f, Yh: 2*M doubles of scratch.
  * The random neighbours of epoch e = (R > 0 ? n / R : 0) are drawn at the
- * first iteration of the call and whenever n is a multiple of R.         */
+ * first iteration of the call and whenever n is a multiple of R.
+ * nesterov != 0: the force of each step is taken at Yh = Y + a V.       */
 void orc_run(int64_t M, double *Y, double *V, int32_t nn, const int32_t *nn_idx,
              int32_t rn, int32_t *rn_idx, double a, double b, double c, double eps,
-             uint64_t seed, int64_t R, int64_t n0, int64_t T, double *f)
+             uint64_t seed, int64_t R, int64_t n0, int64_t T, int32_t nesterov,
+             int32_t metric, double *f, double *Yh)
 {
     for (int64_t n = n0; n < n0 + T; ++n) {
         if (n == n0 || (R > 0 && n % R == 0))
             orc_rn_sample(M, nn, nn_idx, rn, seed, R > 0 ? n / R : 0, rn_idx);
-        orc_force(M, Y, nn, nn_idx, rn, rn_idx, c, eps, f);
+        if (nesterov) {
+            for (int64_t i = 0; i < 2 * M; ++i) Yh[i] = Y[i] + a * V[i];
+            orc_force(M, Yh, nn, nn_idx, rn, rn_idx, c, eps, metric, f);
+        } else {
+            orc_force(M, Y, nn, nn_idx, rn, rn_idx, c, eps, metric, f);
+        }
         for (int64_t i = 0; i < 2 * M; ++i) {
             V[i] = a * V[i] + b * f[i];
             Y[i] = Y[i] + V[i];
         }
     }
+}
+
+/* T iterations of the plain loop with the self-adaptive b, from iteration
+ * n0.  *b is read and updated.  Per step k (0-based) it records the kinetic
+ * energy change dT[k], the b used bs[k] and acc[k] = 1 (kept) or 0
+ * (rejected); any of them may be NULL.  Vt, Yt, f: 2*M doubles of scratch.
+ * Returns the number of kept steps.                                      */
+int64_t orc_run_adaptive(int64_t M, double *Y, double *V, int32_t nn, const int32_t *nn_idx,
+                         int32_t rn, int32_t *rn_idx, double a, double *b, double c,
+                         double eps, uint64_t seed, int64_t R, int64_t n0, int64_t T,
+                         double tau, double g1, double g2, int32_t metric, double *dT,
+                         double *bs, int32_t *acc, double *f, double *Yt, double *Vt)
+{
+    int64_t kept = 0;
+    for (int64_t n = n0; n < n0 + T; ++n) {
+        if (n == n0 || (R > 0 && n % R == 0))
+            orc_rn_sample(M, nn, nn_idx, rn, seed, R > 0 ? n / R : 0, rn_idx);
+        orc_force(M, Y, nn, nn_idx, rn, rn_idx, c, eps, metric, f);
+        double d = 0.0;
+        for (int64_t i = 0; i < M; ++i) {
+            double vx = a * V[2 * i] + *b * f[2 * i];
+            double vy = a * V[2 * i + 1] + *b * f[2 * i + 1];
+            Vt[2 * i] = vx;
+            Vt[2 * i + 1] = vy;
+            Yt[2 * i] = Y[2 * i] + vx;
+            Yt[2 * i + 1] = Y[2 * i + 1] + vy;
+            d += (vx * vx + vy * vy) - (V[2 * i] * V[2 * i] + V[2 * i + 1] * V[2 * i + 1]);
+        }
+        int64_t k = n - n0;
+        if (bs) bs[k] = *b;
+        if (dT) dT[k] = d;
+        int keep = !(fabs(d) > tau);
+        if (keep) {
+            for (int64_t i = 0; i < 2 * M; ++i) {
+                Y[i] = Yt[i];
+                V[i] = Vt[i];
+            }
+            ++kept;
+        } else {
+            *b *= d < -tau ? g1 : g2;
+        }
+        if (acc) acc[k] = keep;
+    }
+    return kept;
 }
