@@ -65,6 +65,15 @@ typedef enum ivhd_mode {
                                  ties by id (a locality and load-balance order; the
                                  results are the same up to floating-point summation
                                  order, and the caller always sees its own order)  */
+#define IVHD_FLAG_NESTEROV 2  /* Nesterov momentum (Sec. "Optimization methods"): the
+                                 force of each step is taken at the look-ahead layout
+                                 H = Y + a V,  V <- a V + b f(H),  Y <- Y + V.  One
+                                 more (det: two more) [M][2] float buffers.        */
+#define IVHD_FLAG_L1 4        /* the l1 distance d = |dx| + |dy| in the stress and
+                                 its force (Sec. "L1 norm in late stages of
+                                 embedding"); the force is -1/2 grad E with
+                                 sign(0) = 0.  ivhd_stress / ivhd_grad of the
+                                 context use the same distance.                    */
 
 typedef struct ivhd_params {
     int64_t  M;       /* vertices; 2 <= M <= 2^31 - 2                        */
@@ -161,6 +170,26 @@ int ivhd_get_iteration(const ivhd_ctx *ctx, int64_t *h_n);
  * kernel directly.  Results are identical either way.                       */
 int ivhd_set_graphs(ivhd_ctx *ctx, int32_t enable);
 
+/* ivhd_set_adaptive: the self-adaptive b of Sec. "Force directed".  With
+ * enable = 1 every iteration is tentative: V' = a V + b f, Y' = Y + V', and
+ * with dT = sum_i |V'_i|^2 - |V_i|^2 (FP64 sum) the step is kept when dT is
+ * finite and |dT| <= tau; otherwise Y and V stay as they were and b is
+ * scaled by g1 (dT < -tau) or g2 (dT > tau or not finite).  Rejected steps
+ * still count as iterations (they advance the random-neighbour schedule).
+ *   b     the current b (replaces params.b), b > 0
+ *   tau   threshold on |dT|, tau >= 0 (+inf: never reject)
+ *   g1    > 1;  g2 in (0, 1)
+ * Deterministic mode only, not with IVHD_FLAG_NESTEROV (IVHD_EINVAL).
+ * Clears the kept / rejected counters.  enable = 0 returns to the fixed
+ * params.b (the other arguments are ignored).  Synchronises the stream.     */
+int ivhd_set_adaptive(ivhd_ctx *ctx, int32_t enable, float b, double tau, float g1, float g2);
+
+/* ivhd_get_adaptive: the adaptive state after the work queued so far
+ * (synchronises): current b, kept and rejected step counts, and dT of the
+ * last tentative step.  Any output pointer may be NULL.  IVHD_EINVAL if the
+ * adaptive b was never enabled on this context.                             */
+int ivhd_get_adaptive(ivhd_ctx *ctx, float *h_b, int64_t *h_kept, int64_t *h_rejected, double *h_dT);
+
 /* ivhd_destroy: free everything the context owns (not the caller's buffers).
  * Synchronises the stream.  NULL is accepted.                               */
 int ivhd_destroy(ivhd_ctx *ctx);
@@ -214,6 +243,18 @@ int ivhd_grad_edges(const float *d_y, int64_t M, const int32_t *d_nn_idx, int32_
  * and synchronises the stream.                                              */
 int ivhd_knn_build(const float *d_x, int64_t M, int32_t N, int32_t k, int32_t *d_idx,
                    void *stream);
+
+/* ivhd_rnn_mask: the reverse-neighbour pruning of Sec. "Reverse neighbors
+ * mechanism".  An nn edge i -> j is kept when i is also among the kh
+ * nearest neighbours of j in a wider helper graph (the thesis uses
+ * kh = 4 nn), else its slot becomes -1; absent slots stay -1.  The result
+ * is an nn list for a late-stage context.
+ *   d_nn_idx  int32 [M][nn] (entries in [-1, M), no self edges)
+ *   d_helper  int32 [M][kh], e.g. from ivhd_knn_build with k = kh
+ *   d_out     int32 [M][nn]; may be d_nn_idx itself, not d_helper
+ * 1 <= nn <= 64, 1 <= kh <= 256.  Synchronises the stream (validation).     */
+int ivhd_rnn_mask(const int32_t *d_nn_idx, int64_t M, int32_t nn, const int32_t *d_helper, int32_t kh,
+                  int32_t *d_out, void *stream);
 
 /* ivhd_knn_query: the k nearest rows of X to each of Q query rows (used for
  * the quality metrics on a sample of points).

@@ -36,7 +36,8 @@
  *            taken tentatively; with dT = sum_i |V'_i|^2 - |V_i|^2 (the change
  *            of kinetic energy), |dT| > tau rejects the step (Y and V stay)
  *            and scales b by g1 > 1 when dT < -tau or by g2 < 1 when
- *            dT > tau; otherwise the step is kept and b stays.
+ *            dT > tau (or dT is not finite); otherwise the step is kept and
+ *            b stays.
  *   mask     reverse-neighbour pruning of Sec. "Reverse neighbors
  *            mechanism": an nn edge i -> j is kept only when i is also
  *            among the kh nearest neighbours of j in a wider helper graph.
@@ -242,7 +243,7 @@ int64_t orc_run_adaptive(int64_t M, double *Y, double *V, int32_t nn, const int3
         int64_t k = n - n0;
         if (bs) bs[k] = *b;
         if (dT) dT[k] = d;
-        int keep = !(fabs(d) > tau);
+        int keep = isfinite(d) && fabs(d) <= tau;   /* a non-finite dT counts as a rise */
         if (keep) {
             for (int64_t i = 0; i < 2 * M; ++i) {
                 Y[i] = Yt[i];

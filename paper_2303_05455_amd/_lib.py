@@ -42,6 +42,9 @@ SIGNATURES = {
     "ivhd_set_iteration": (i32, [vp, i64]),
     "ivhd_get_iteration": (i32, [vp, ctypes.POINTER(i64)]),
     "ivhd_set_graphs": (i32, [vp, i32]),
+    "ivhd_set_adaptive": (i32, [vp, i32, f32, f64, f32, f32]),
+    "ivhd_get_adaptive": (i32, [vp, vp, vp, vp, vp]),
+    "ivhd_rnn_mask": (i32, [vp, i64, i32, vp, i32, vp, vp]),
     "ivhd_destroy": (i32, [vp]),
     "ivhd_edges_create": (i32, [ctypes.POINTER(vp), i64, vp, i32, vp, i32, vp]),
     "ivhd_edges_stress": (i32, [vp, vp, f32, vp]),

@@ -22,7 +22,8 @@ __all__ = [
     "ivhd_get_rn", "ivhd_get_in_edges", "ivhd_get_order", "ivhd_set_state", "ivhd_set_iteration",
     "ivhd_get_iteration", "ivhd_set_graphs", "ivhd_destroy", "ivhd_last_error",
     "ivhd_version", "ivhd_knn_build", "ivhd_knn_query", "ivhd_edges_create", "ivhd_edges_stress",
-    "ivhd_edges_grad", "ivhd_edges_destroy", "ivhd_grad_edges",
+    "ivhd_edges_grad", "ivhd_edges_destroy", "ivhd_grad_edges", "ivhd_set_adaptive",
+    "ivhd_get_adaptive", "ivhd_rnn_mask",
 ]
 
 
@@ -45,15 +46,17 @@ def _dev(t: torch.Tensor, dtype, shape, name: str) -> int:
     return t.data_ptr()
 
 
-FLAG_REORDER = 1
+FLAG_REORDER, FLAG_NESTEROV, FLAG_L1 = 1, 2, 4
+METRICS = {"l2": 0, "l1": FLAG_L1}
 
 
 def make_params(M: int, nn: int, rn: int, *, a: float, b: float, c: float, eps: float = 1e-12,
                 seed: int = 0, rn_resample_every: int = 0, mode: str = "det",
-                reorder: bool = True) -> ivhd_params:
+                reorder: bool = True, nesterov: bool = False, metric: str = "l2") -> ivhd_params:
+    flags = (FLAG_REORDER if reorder else 0) | (FLAG_NESTEROV if nesterov else 0) | METRICS[metric]
     return ivhd_params(M=M, nn=nn, rn=rn, a=a, b=b, c=c, eps=eps, seed=seed & (2**64 - 1),
-                       rn_resample_every=rn_resample_every, mode=MODES[mode],
-                       flags=FLAG_REORDER if reorder else 0, reserved=0)
+                       rn_resample_every=rn_resample_every, mode=MODES[mode], flags=flags,
+                       reserved=0)
 
 
 def ivhd_init(params: ivhd_params, nn_idx: torch.Tensor, y: torch.Tensor, v: torch.Tensor,
@@ -130,6 +133,34 @@ def ivhd_set_graphs(ctx, enable: bool) -> None:
 
 def ivhd_destroy(ctx) -> None:
     check(_lib.load().ivhd_destroy(ctx))
+
+
+def ivhd_set_adaptive(ctx, enable: bool, b: float = 0.0, tau: float = float("inf"), g1: float = 1.05,
+                      g2: float = 0.5) -> None:
+    check(_lib.load().ivhd_set_adaptive(ctx, 1 if enable else 0, b, tau, g1, g2))
+
+
+def ivhd_get_adaptive(ctx) -> dict:
+    b, dT = ctypes.c_float(), ctypes.c_double()
+    kept, rej = ctypes.c_int64(), ctypes.c_int64()
+    check(_lib.load().ivhd_get_adaptive(ctx, ctypes.byref(b), ctypes.byref(kept), ctypes.byref(rej),
+                                        ctypes.byref(dT)))
+    return {"b": b.value, "kept": kept.value, "rejected": rej.value, "dT": dT.value}
+
+
+def ivhd_rnn_mask(nn_idx: torch.Tensor, helper: torch.Tensor, out: Optional[torch.Tensor] = None,
+                  stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """Reverse-neighbour pruning: int32 [M, nn], edge i -> j kept when i is among helper[j]."""
+    M, nn = nn_idx.shape
+    kh = helper.shape[1]
+    _dev(nn_idx, torch.int32, (M, nn), "nn_idx")
+    _dev(helper, torch.int32, (M, kh), "helper")
+    if out is None:
+        out = torch.empty_like(nn_idx)
+    _dev(out, torch.int32, (M, nn), "out")
+    check(_lib.load().ivhd_rnn_mask(nn_idx.data_ptr(), M, nn, helper.data_ptr(), kh, out.data_ptr(),
+                                    _stream_handle(stream)))
+    return out
 
 
 def ivhd_edges_create(nn_idx: torch.Tensor, rn_idx: Optional[torch.Tensor] = None,
@@ -232,12 +263,14 @@ class Context:
     def __init__(self, nn_idx: torch.Tensor, y: torch.Tensor, v: Optional[torch.Tensor] = None, *,
                  rn: int = 1, a: float = 0.9, b: float = 0.01, c: float = 0.1, eps: float = 1e-12,
                  seed: int = 0, rn_resample_every: int = 0, mode: str = "det", reorder: bool = True,
+                 nesterov: bool = False, metric: str = "l2",
                  stream: Optional[torch.cuda.Stream] = None):
         M, nn = nn_idx.shape
         if v is None:
             v = torch.zeros_like(y)
         self.params = make_params(M, nn, rn, a=a, b=b, c=c, eps=eps, seed=seed,
-                                  rn_resample_every=rn_resample_every, mode=mode, reorder=reorder)
+                                  rn_resample_every=rn_resample_every, mode=mode, reorder=reorder,
+                                  nesterov=nesterov, metric=metric)
         self.nn_idx, self.y, self.v = nn_idx, y, v
         self.M, self.nn, self.rn = M, nn, rn
         self._h = None
@@ -292,6 +325,15 @@ class Context:
 
     def set_graphs(self, enable: bool) -> None:
         ivhd_set_graphs(self.handle, enable)
+
+    def set_adaptive(self, enable: bool = True, *, b: Optional[float] = None, tau: float = float("inf"),
+                     g1: float = 1.05, g2: float = 0.5) -> None:
+        """Self-adaptive b (see include/ivhd.h); b defaults to the context's b."""
+        ivhd_set_adaptive(self.handle, enable, self.params.b if b is None else b, tau, g1, g2)
+
+    def adaptive(self) -> dict:
+        """{"b", "kept", "rejected", "dT"} of the adaptive b."""
+        return ivhd_get_adaptive(self.handle)
 
     def close(self) -> None:
         if self._h is not None:

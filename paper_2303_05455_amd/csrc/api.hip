@@ -67,6 +67,13 @@ struct ivhd_ctx {
   int32_t *nn_own = nullptr;      // nn lists in internal ids (when reordered)
   const int32_t *nn_int = nullptr;   // the lists the kernels read
   float2 *ya = nullptr, *yb = nullptr, *v = nullptr;   // internal state
+  float2 *ha = nullptr, *hb = nullptr;   // Nesterov look-ahead H = Y + a V (det: paired with ya / yb)
+  float2 *vb = nullptr;                  // adaptive b: second velocity buffer (paired with v)
+  AdaptState *adapt = nullptr;           // adaptive b: device state
+  double *ke_part = nullptr;             // adaptive b: per-block kinetic energy changes
+  int adapt_on = 0;
+  double tau = 0.0;
+  float g1 = 1.f, g2 = 1.f;
   float2 *tmp = nullptr;          // [M] scratch (gradients in internal order)
   int parity = 0;                 // det mode: 0 -> Y_n in ya, 1 -> in yb
   Csc nn_csc, rn_csc;
@@ -87,8 +94,12 @@ struct ivhd_ctx {
   hipGraphExec_t g_chunk[2] = {nullptr, nullptr};   // kChunkIters iterations (no draws)
 
   bool det() const { return p.mode == IVHD_MODE_DET; }
+  bool nest() const { return (p.flags & IVHD_FLAG_NESTEROV) != 0; }
+  bool l1() const { return (p.flags & IVHD_FLAG_L1) != 0; }
   float2 *cur() const { return parity ? yb : ya; }
   float2 *other() const { return parity ? ya : yb; }
+  float2 *vcur() const { return adapt_on && parity ? vb : v; }
+  float2 *hcur() const { return det() && parity ? hb : ha; }
 };
 
 namespace {
@@ -102,7 +113,8 @@ void free_ctx(ivhd_ctx *c) {
   }
   void *bufs[] = {c->perm, c->inv, c->nn_own, c->ya, c->yb, c->v, c->tmp, c->nn_csc.ptr, c->nn_csc.src,
                   c->rn_csc.ptr, c->rn_csc.src, c->sc.cnt, c->sc.tmp, c->sc.part, c->sc.big, c->rn_idx,
-                  c->epoch, c->flags, c->fbuf, c->heavy, c->partials, c->d_E};
+                  c->epoch, c->flags, c->fbuf, c->heavy, c->partials, c->d_E, c->ha, c->hb, c->vb,
+                  c->adapt, c->ke_part};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (c->cap) (void)hipStreamDestroy(c->cap);
@@ -134,7 +146,8 @@ int validate(const ivhd_params *p) {
     return fail(IVHD_EINVAL, "rn_resample_every = %d must be >= 0", p->rn_resample_every);
   if (p->mode != IVHD_MODE_DET && p->mode != IVHD_MODE_ATOMIC)
     return fail(IVHD_EINVAL, "mode = %d is neither IVHD_MODE_DET nor IVHD_MODE_ATOMIC", p->mode);
-  if (p->flags & ~IVHD_FLAG_REORDER) return fail(IVHD_EINVAL, "flags = 0x%x has unknown bits", (unsigned)p->flags);
+  if (p->flags & ~(IVHD_FLAG_REORDER | IVHD_FLAG_NESTEROV | IVHD_FLAG_L1))
+    return fail(IVHD_EINVAL, "flags = 0x%x has unknown bits", (unsigned)p->flags);
   if (p->reserved != 0) return fail(IVHD_EINVAL, "reserved = %d must be 0", p->reserved);
   return IVHD_OK;
 }
@@ -142,8 +155,10 @@ int validate(const ivhd_params *p) {
 StepArgs step_args(const ivhd_ctx *c, const float2 *y, float2 *y_out) {
   StepArgs a{};
   a.y = y;
+  a.h = y;
   a.y_out = y_out;
   a.v = c->v;
+  a.l1 = c->l1() ? 1 : 0;
   a.nn_idx = c->nn_int;
   a.rn_idx = c->rn_idx;
   a.nn_ptr = c->nn_csc.ptr;
@@ -183,19 +198,56 @@ int enqueue_draw(ivhd_ctx *c, hipStream_t s) {
   return IVHD_OK;
 }
 
-// `count` iterations starting from parity *par
+// `count` iterations starting from parity *par.  Det mode ping-pongs Y (and
+// H for Nesterov, V for the adaptive b) between the two buffers of a pair;
+// after a rejected adaptive step the commit kernel copies the state across,
+// so the pairing stays static (and capturable).
 int enqueue_steps(ivhd_ctx *c, hipStream_t s, int64_t count, int *par) {
   for (int64_t k = 0; k < count; ++k) {
     if (c->det()) {
       float2 *src = *par ? c->yb : c->ya;
       float2 *dst = *par ? c->ya : c->yb;
-      HIPCHK(launch_step_det(step_args(c, src, dst), s));
+      StepArgs a = step_args(c, src, dst);
+      if (c->nest()) {
+        a.nesterov = 1;
+        a.h = *par ? c->hb : c->ha;
+        a.h_out = *par ? c->ha : c->hb;
+      }
+      if (c->adapt_on) {
+        a.adapt = 1;
+        a.v = *par ? c->vb : c->v;
+        a.v_out = *par ? c->v : c->vb;
+        a.b_dev = &c->adapt->b;
+        a.ke_part = c->ke_part;
+      }
+      HIPCHK(launch_step_det(a, s));
+      if (c->adapt_on) {
+        HIPCHK(launch_adapt_decide(c->ke_part, (int)det_grid(a), c->tau, c->g1, c->g2, c->adapt, s));
+        HIPCHK(launch_adapt_commit(c->adapt, src, a.v, c->p.M, dst, a.v_out, s));
+      }
       *par ^= 1;
     } else {
-      HIPCHK(launch_step_atomic(step_args(c, c->ya, c->ya), s));
+      StepArgs a = step_args(c, c->ya, c->ya);
+      if (c->nest()) {
+        a.nesterov = 1;
+        a.h = c->ha;
+        a.h_out = c->ha;
+      }
+      HIPCHK(launch_step_atomic(a, s));
     }
   }
   return IVHD_OK;
+}
+
+void drop_graphs(ivhd_ctx *c) {
+  for (int k = 0; k < 2; ++k) {
+    hipGraphExec_t *gs[] = {&c->g_epoch[k], &c->g_first[k], &c->g_chunk[k]};
+    for (hipGraphExec_t *g : gs)
+      if (*g) {
+        (void)hipGraphExecDestroy(*g);
+        *g = nullptr;
+      }
+  }
 }
 
 int capture(ivhd_ctx *c, bool with_draw, int64_t count, int par, hipGraphExec_t *out) {
@@ -253,13 +305,14 @@ int load_state(ivhd_ctx *c, const float2 *y, const float2 *v) {
   HIPCHK(launch_gather_f2(y, c->perm, c->p.M, c->ya, c->stream));
   HIPCHK(launch_gather_f2(v, c->perm, c->p.M, c->v, c->stream));
   c->parity = 0;
+  if (c->nest()) HIPCHK(launch_lookahead(c->ya, c->v, c->p.a, c->p.M, c->ha, c->stream));
   return IVHD_OK;
 }
 
 // internal state -> caller's buffers
 int store_state(ivhd_ctx *c) {
   HIPCHK(launch_gather_f2(c->cur(), c->inv, c->p.M, c->y_user, c->stream));
-  HIPCHK(launch_gather_f2(c->v, c->inv, c->p.M, c->v_user, c->stream));
+  HIPCHK(launch_gather_f2(c->vcur(), c->inv, c->p.M, c->v_user, c->stream));
   return IVHD_OK;
 }
 
@@ -281,7 +334,7 @@ extern "C" {
 
 const char *ivhd_last_error(void) { return ivhd::g_err.c_str(); }
 
-int ivhd_version(void) { return 200; }
+int ivhd_version(void) { return 300; }
 
 int ivhd_init(ivhd_ctx **out, const ivhd_params *p, const int32_t *d_nn_idx, float *d_y, float *d_v,
               void *stream) {
@@ -359,6 +412,10 @@ int ivhd_init(ivhd_ctx **out, const ivhd_params *p, const int32_t *d_nn_idx, flo
     }
   }
   if (p->mode == IVHD_MODE_ATOMIC) ALLOC(c->fbuf, M, "force accumulator");
+  if (p->flags & IVHD_FLAG_NESTEROV) {
+    ALLOC(c->ha, M, "look-ahead positions");
+    if (p->mode == IVHD_MODE_DET) ALLOC(c->hb, M, "second look-ahead buffer");
+  }
   if (p->mode == IVHD_MODE_DET) ALLOC(c->heavy, M, "heavy-vertex list");
   c->nparts = stress_partials(M);
   ALLOC(c->partials, c->nparts, "stress partials");
@@ -474,7 +531,8 @@ int ivhd_stress(ivhd_ctx *c, const float *d_y, double *h_E) {
   int rc;
   const float2 *y = internal_positions(c, d_y, &rc);
   if (rc) return rc;
-  HIPCHK(launch_stress(y, c->p.M, c->nn_int, c->p.nn, c->rn_idx, c->p.rn, (double)c->p.c, c->partials,
+  HIPCHK(launch_stress(y, c->p.M, c->nn_int, c->p.nn, c->rn_idx, c->p.rn, (double)c->p.c, c->l1() ? 1 : 0,
+                       c->partials,
                        c->nparts, c->d_E, c->stream));
   double E = 0.0;
   int32_t hflags[FLAG_SLOTS];
@@ -547,6 +605,58 @@ int ivhd_get_iteration(const ivhd_ctx *c, int64_t *h_n) {
   if (!live(c)) return fail(IVHD_ESTATE, "invalid context");
   if (!h_n) return fail(IVHD_EINVAL, "h_n is NULL");
   *h_n = c->n;
+  return IVHD_OK;
+}
+
+int ivhd_set_adaptive(ivhd_ctx *c, int32_t enable, float b, double tau, float g1, float g2) {
+  if (!live(c)) return fail(IVHD_ESTATE, "invalid context");
+  if (!enable) {
+    if (c->adapt_on) {
+      if (c->parity) HIPCHK(hipMemcpyAsync(c->v, c->vb, (size_t)c->p.M * sizeof(float2), hipMemcpyDeviceToDevice,
+                                           c->stream));
+      c->adapt_on = 0;
+      drop_graphs(c);
+    }
+    return IVHD_OK;
+  }
+  if (!c->det()) return fail(IVHD_EINVAL, "the adaptive b needs IVHD_MODE_DET");
+  if (c->nest()) return fail(IVHD_EINVAL, "the adaptive b is not combined with IVHD_FLAG_NESTEROV");
+  if (!std::isfinite(b) || !(b > 0.f)) return fail(IVHD_EINVAL, "b = %g must be > 0", (double)b);
+  if (std::isnan(tau) || tau < 0.0) return fail(IVHD_EINVAL, "tau = %g must be >= 0", tau);
+  if (!std::isfinite(g1) || !(g1 > 1.f)) return fail(IVHD_EINVAL, "g1 = %g must be > 1", (double)g1);
+  if (!std::isfinite(g2) || !(g2 > 0.f) || !(g2 < 1.f)) return fail(IVHD_EINVAL, "g2 = %g outside (0, 1)", (double)g2);
+  const int64_t M = c->p.M;
+  int rc;
+  if (!c->vb && (rc = dev_alloc(&c->vb, M, "second velocity buffer"))) return rc;
+  if (!c->adapt && (rc = dev_alloc(&c->adapt, 1, "adaptive-b state"))) return rc;
+  if (!c->ke_part) {
+    const StepArgs a = step_args(c, c->ya, c->yb);
+    if ((rc = dev_alloc(&c->ke_part, det_grid(a), "kinetic energy partials"))) return rc;
+  }
+  if (!c->adapt_on && c->parity)
+    HIPCHK(hipMemcpyAsync(c->vb, c->v, (size_t)M * sizeof(float2), hipMemcpyDeviceToDevice, c->stream));
+  AdaptState st{};
+  st.b = b;
+  HIPCHK(hipMemcpyAsync(c->adapt, &st, sizeof st, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));   // st lives on this stack frame
+  c->adapt_on = 1;
+  c->tau = tau;
+  c->g1 = g1;
+  c->g2 = g2;
+  drop_graphs(c);
+  return IVHD_OK;
+}
+
+int ivhd_get_adaptive(ivhd_ctx *c, float *h_b, int64_t *h_kept, int64_t *h_rejected, double *h_dT) {
+  if (!live(c)) return fail(IVHD_ESTATE, "invalid context");
+  if (!c->adapt) return fail(IVHD_EINVAL, "the adaptive b was never enabled on this context");
+  AdaptState st{};
+  HIPCHK(hipMemcpyAsync(&st, c->adapt, sizeof st, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (h_b) *h_b = st.b;
+  if (h_kept) *h_kept = st.kept;
+  if (h_rejected) *h_rejected = st.rejected;
+  if (h_dT) *h_dT = st.dT;
   return IVHD_OK;
 }
 

@@ -149,6 +149,20 @@ __global__ void gather_f2_kernel(const float2 *__restrict__ src, const int32_t *
   if (p < M) dst[p] = src[idx ? (int64_t)idx[p] : p];
 }
 
+// reverse-neighbour mask: nn edge i -> j kept when i is among the kh helper
+// neighbours of j, else -1 (absent slots stay absent)
+__global__ void rnn_mask_kernel(const int32_t *nn_idx, int64_t M, int nn, const int32_t *__restrict__ helper,
+                                int kh, int32_t *out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * nn) return;
+  const int32_t i = (int32_t)(e / nn);
+  const int32_t j = nn_idx[e];
+  bool keep = false;
+  if (j >= 0)
+    for (int r = 0; r < kh; ++r) keep |= helper[(int64_t)j * kh + r] == i;
+  out[e] = keep ? j : -1;
+}
+
 __global__ void count_kernel(const int32_t *__restrict__ idx, int64_t M, int k, int32_t *cnt) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= M * k) return;
@@ -359,6 +373,12 @@ hipError_t launch_unmap_lists(const int32_t *lists, int64_t M, int k, const int3
 
 hipError_t launch_gather_f2(const float2 *src, const int32_t *idx, int64_t M, float2 *dst, hipStream_t s) {
   gather_f2_kernel<<<grid_for(M), kBlock, 0, s>>>(src, idx, M, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_rnn_mask(const int32_t *nn_idx, int64_t M, int nn, const int32_t *helper, int kh, int32_t *out,
+                           hipStream_t s) {
+  rnn_mask_kernel<<<grid_for(M * nn), kBlock, 0, s>>>(nn_idx, M, nn, helper, kh, out);
   return hipGetLastError();
 }
 

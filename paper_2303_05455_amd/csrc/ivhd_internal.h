@@ -87,6 +87,9 @@ hipError_t launch_map_lists(const int32_t *idx, int64_t M, int k, const int32_t 
 hipError_t launch_unmap_lists(const int32_t *lists, int64_t M, int k, const int32_t *perm, const int32_t *inv,
                               int32_t *out, hipStream_t s);
 hipError_t launch_gather_f2(const float2 *src, const int32_t *idx, int64_t M, float2 *dst, hipStream_t s);
+// out[i][q] = nn_idx[i][q] when i is among helper[j][0..kh) for j = nn_idx[i][q] >= 0, else -1
+hipError_t launch_rnn_mask(const int32_t *nn_idx, int64_t M, int nn, const int32_t *helper, int kh, int32_t *out,
+                           hipStream_t s);
 // in-degree count of an [M][k] index list (entries < 0 skipped); cnt must be zero.
 hipError_t launch_count(const int32_t *idx, int64_t M, int k, int32_t *cnt, hipStream_t s);
 // From counts cnt[0..M-1]: ptr = exclusive scan (ptr[M] = total), cnt = cursor copy.
@@ -102,10 +105,24 @@ hipError_t launch_scatter_sort(const int32_t *idx, int64_t M, int k, const int32
 int sort_vertex_order(const int32_t *root, const int32_t *indeg, int64_t M, int32_t *perm, hipStream_t s);
 
 // ---- step.hip ----
+// device state of the self-adaptive b
+struct AdaptState {
+  float b;            // current step factor
+  int32_t reject;     // 1: the last tentative step was rejected
+  int64_t kept, rejected;
+  double dT;          // kinetic energy change of the last tentative step
+};
+
 struct StepArgs {
   const float2 *y;        // positions read (Y_n)
+  const float2 *h;        // positions the forces are taken at: y, or H = Y + a V (nesterov)
   float2 *y_out;          // positions written (Y_{n+1}); det mode: != y
-  float2 *v;              // velocities, in place
+  float2 *h_out;          // nesterov: H_{n+1} written here
+  float2 *v;              // velocities, in place (read only with adapt)
+  float2 *v_out;          // adapt: tentative velocities
+  const float *b_dev;     // adapt: b read from device memory
+  double *ke_part;        // adapt: per-block sums of |v'|^2 - |v|^2 [det_grid]
+  int32_t l1, nesterov, adapt;
   const int32_t *nn_idx;  // [M][nn]
   const int32_t *rn_idx;  // [M][rn]
   const int32_t *nn_ptr, *nn_src;   // CSC of nn edges
@@ -131,7 +148,14 @@ inline void set_launch_shape(StepArgs &a) {
   a.light_tiles = (int32_t)((a.M + kBlock - 1) / kBlock);
   a.tiles_per_xcd = (a.light_tiles + kXcds - 1) / kXcds;
 }
+unsigned det_grid(const StepArgs &a);   // blocks of one deterministic launch
 hipError_t launch_step_det(const StepArgs &a, hipStream_t s);
+hipError_t launch_lookahead(const float2 *y, const float2 *v, float a, int64_t M, float2 *h, hipStream_t s);
+hipError_t launch_adapt_decide(const double *part, int nparts, double tau, float g1, float g2, AdaptState *st,
+                               hipStream_t s);
+// when st->reject: y_next = y, v_next = v
+hipError_t launch_adapt_commit(const AdaptState *st, const float2 *y, const float2 *v, int64_t M, float2 *y_next,
+                               float2 *v_next, hipStream_t s);
 hipError_t launch_step_atomic(const StepArgs &a, hipStream_t s);   // two kernels
 // grad E = -2 f at positions a.y into out (det gather; or atomic scatter via fbuf)
 hipError_t launch_grad_det(const StepArgs &a, float2 *out, hipStream_t s);
@@ -146,8 +170,9 @@ hipError_t launch_heavy_list(const int32_t *nn_ptr, int64_t M, int32_t *list, in
 
 // ---- reduce.hip ----
 // FP64 stress: per-block partial sums (fixed tree), then one block in fixed order.
+// metric: 0 Euclidean, 1 l1
 hipError_t launch_stress(const float2 *y, int64_t M, const int32_t *nn_idx, int nn,
-                         const int32_t *rn_idx, int rn, double c, double *partials,
+                         const int32_t *rn_idx, int rn, double c, int metric, double *partials,
                          int nparts, double *out, hipStream_t s);
 int stress_partials(int64_t M);
 

@@ -74,6 +74,7 @@ void free_edges(ivhd_edges *e) {
 StepArgs edge_args(const ivhd_edges *e, const float2 *y, float c, float eps, const float *gscale) {
   StepArgs a{};
   a.y = y;
+  a.h = y;
   a.nn_idx = e->nn_idx;
   a.rn_idx = e->rn_idx;
   a.nn_ptr = e->nn_csc.ptr;
@@ -175,7 +176,7 @@ int ivhd_edges_stress(ivhd_edges *e, const float *d_y, float c, double *d_E) {
   if (!edges_live(e)) return fail(IVHD_ESTATE, "invalid edge plan");
   if (!d_y || !d_E) return fail(IVHD_EINVAL, "d_y and d_E must not be NULL");
   if (!std::isfinite(c) || c < 0.f) return fail(IVHD_EINVAL, "c = %g must be finite and >= 0", (double)c);
-  HIPCHK(launch_stress((const float2 *)d_y, e->M, e->nn_idx, e->nn, e->rn_idx, e->rn, (double)c,
+  HIPCHK(launch_stress((const float2 *)d_y, e->M, e->nn_idx, e->nn, e->rn_idx, e->rn, (double)c, 0,
                        e->partials, e->nparts, d_E, e->stream));
   return IVHD_OK;
 }
@@ -254,6 +255,32 @@ int ivhd_knn_build(const float *d_x, int64_t M, int32_t N, int32_t k, int32_t *d
 int ivhd_knn_query(const float *d_x, int64_t M, int32_t N, const float *d_q, int64_t Q,
                    const int32_t *d_self, int32_t k, int32_t *d_idx, float *d_dist, void *stream) {
   return knn_common(d_x, M, N, d_q, Q, d_self ? 2 : 0, d_self, k, d_idx, d_dist, stream);
+}
+
+int ivhd_rnn_mask(const int32_t *d_nn_idx, int64_t M, int32_t nn, const int32_t *d_helper, int32_t kh,
+                  int32_t *d_out, void *stream) {
+  clear_error();
+  if (M < 2 || M > (int64_t)INT32_MAX - 1) return fail(IVHD_EINVAL, "M = %lld outside [2, 2^31-2]", (long long)M);
+  if (nn < 1 || nn > 64) return fail(IVHD_EINVAL, "nn = %d outside [1, 64]", nn);
+  if (kh < 1 || kh > 256) return fail(IVHD_EINVAL, "kh = %d outside [1, 256]", kh);
+  if (M * (int64_t)(nn > kh ? nn : kh) > (int64_t)INT32_MAX)
+    return fail(IVHD_EINVAL, "M * max(nn, kh) exceeds 2^31-1");
+  if (!d_nn_idx || !d_helper || !d_out) return fail(IVHD_EINVAL, "a list pointer is NULL");
+  if (d_helper == d_out) return fail(IVHD_EINVAL, "d_helper and d_out alias");
+  hipStream_t s = (hipStream_t)stream;
+  int32_t *flags = nullptr;
+  int rc = dev_alloc(&flags, FLAG_SLOTS, "device flags");
+  if (rc) return rc;
+  int32_t hflags[FLAG_SLOTS] = {0};
+  hipError_t e = launch_fill_i32(flags, FLAG_SLOTS, 0, s);
+  if (e == hipSuccess) e = launch_validate_idx(d_nn_idx, M, nn, -1, flags, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(hflags, flags, sizeof hflags, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(flags);
+  if (e != hipSuccess) return hip_fail(e, "validating nn_idx");
+  if (hflags[FLAG_BAD_INDEX]) return fail(IVHD_EINVAL, "nn_idx holds an entry outside [-1, M) or a self edge");
+  HIPCHK(launch_rnn_mask(d_nn_idx, M, nn, d_helper, kh, d_out, s));
+  return IVHD_OK;
 }
 
 }  // extern "C"

@@ -1,5 +1,6 @@
 // FP64 stress of Eq. ivhd_cost_function for reporting:
 //   E = sum_i [ sum_{j in O_nn(i)} d_ij^2 + c * sum_{k in O_rn(i)} (1 - d_ik)^2 ]
+// with d the Euclidean distance, or |dx| + |dy| for the l1 variant.
 // Each thread sums the out-edges of one vertex in double precision (from the
 // FP32 positions, widened before subtracting), each block reduces its 256
 // values in a fixed tree, and a single block adds the block sums in a fixed
@@ -11,6 +12,7 @@ namespace {
 
 constexpr int kStressBlock = 256;
 
+template <bool L1>
 __global__ void __launch_bounds__(kStressBlock)
 stress_partial_kernel(const float2 *__restrict__ y, int64_t M, const int32_t *__restrict__ nn_idx,
                       int nn, const int32_t *__restrict__ rn_idx, int rn, double c,
@@ -25,14 +27,19 @@ stress_partial_kernel(const float2 *__restrict__ y, int64_t M, const int32_t *__
       if (j < 0) continue;
       const float2 yj = y[j];
       const double dx = (double)yi.x - (double)yj.x, dy = (double)yi.y - (double)yj.y;
-      e += dx * dx + dy * dy;
+      if (L1) {
+        const double d = fabs(dx) + fabs(dy);
+        e += d * d;
+      } else {
+        e += dx * dx + dy * dy;
+      }
     }
     for (int q = 0; q < rn; ++q) {
       const int32_t k = rn_idx[i * rn + q];
       if (k < 0) continue;
       const float2 yk = y[k];
       const double dx = (double)yi.x - (double)yk.x, dy = (double)yi.y - (double)yk.y;
-      const double d = sqrt(dx * dx + dy * dy);
+      const double d = L1 ? fabs(dx) + fabs(dy) : sqrt(dx * dx + dy * dy);
       e += c * (1.0 - d) * (1.0 - d);
     }
   }
@@ -64,10 +71,14 @@ stress_final_kernel(const double *__restrict__ partials, int nparts, double *out
 int stress_partials(int64_t M) { return (int)grid_for(M, kStressBlock); }
 
 hipError_t launch_stress(const float2 *y, int64_t M, const int32_t *nn_idx, int nn,
-                         const int32_t *rn_idx, int rn, double c, double *partials, int nparts,
+                         const int32_t *rn_idx, int rn, double c, int metric, double *partials, int nparts,
                          double *out, hipStream_t s) {
-  stress_partial_kernel<<<(unsigned)nparts, kStressBlock, 0, s>>>(y, M, nn_idx, nn, rn_idx, rn, c,
-                                                                   partials);
+  if (metric == 1)
+    stress_partial_kernel<true><<<(unsigned)nparts, kStressBlock, 0, s>>>(y, M, nn_idx, nn, rn_idx, rn, c,
+                                                                         partials);
+  else
+    stress_partial_kernel<false><<<(unsigned)nparts, kStressBlock, 0, s>>>(y, M, nn_idx, nn, rn_idx, rn, c,
+                                                                          partials);
   stress_final_kernel<<<1, kStressBlock, 0, s>>>(partials, nparts, out);
   return hipGetLastError();
 }

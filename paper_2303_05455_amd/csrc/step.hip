@@ -27,17 +27,43 @@
 // Atomic mode: pass 1, one thread per vertex, walks its out-edges, keeps its
 // own share in registers and adds each reaction to the other end with a
 // float atomic; pass 2 applies the update and clears the accumulator.
+//
+// Variants of the thesis, chosen per context and compiled as template
+// parameters so the plain loop carries none of their cost:
+//   L1     the distance is |dx| + |dy| (Sec. "L1 norm in late stages of
+//          embedding"); the force is again -1/2 grad E, with sign(0) = 0:
+//            nn edge: -d (sign dx, sign dy);  rn edge: c (1 - d) (sign dx, sign dy)
+//   NEST   Nesterov look-ahead (Sec. "Optimization methods"): forces are
+//          gathered from H = Y + a V, which each update also writes for the
+//          next iteration (one more position array, no extra gathers)
+//   ADAPT  the self-adaptive b of Sec. "Force directed": the step is
+//          tentative (V is written to a second buffer), b is read from
+//          device memory, and each block leaves the FP64 sum of
+//          |v'|^2 - |v|^2 over its vertices for the accept / reject decision.
 #include "ivhd_internal.h"
 
 namespace ivhd {
 namespace {
 
+__device__ __forceinline__ float sgnf(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
+
+template <bool L1>
 __device__ __forceinline__ float2 nn_term(float2 yi, float2 yo) {
+  if (L1) {
+    const float dx = yi.x - yo.x, dy = yi.y - yo.y;
+    const float d = fabsf(dx) + fabsf(dy);
+    return make_float2(-d * sgnf(dx), -d * sgnf(dy));
+  }
   return make_float2(yo.x - yi.x, yo.y - yi.y);
 }
 
+template <bool L1>
 __device__ __forceinline__ float2 rn_term(float2 yi, float2 yo, float c, float eps) {
   const float dx = yi.x - yo.x, dy = yi.y - yo.y;
+  if (L1) {
+    const float s = c * (1.0f - (fabsf(dx) + fabsf(dy)));
+    return make_float2(s * sgnf(dx), s * sgnf(dy));
+  }
   const float d = sqrtf(dx * dx + dy * dy);
   const float s = c * (1.0f - d) / fmaxf(d, eps);
   return make_float2(s * dx, s * dy);
@@ -45,7 +71,7 @@ __device__ __forceinline__ float2 rn_term(float2 yi, float2 yo, float c, float e
 
 // in-edge segment [s, e) of a light vertex, four gathers in flight at a time;
 // the terms are still added one by one in ascending order
-template <bool RN>
+template <bool RN, bool L1>
 __device__ __forceinline__ void gather_segment(const float2 *__restrict__ y, const int32_t *__restrict__ src,
                                                int32_t s, int32_t e, float2 yi, float c, float eps,
                                                float &fx, float &fy) {
@@ -54,46 +80,49 @@ __device__ __forceinline__ void gather_segment(const float2 *__restrict__ y, con
     const int32_t j0 = src[p], j1 = src[p + 1], j2 = src[p + 2], j3 = src[p + 3];
     const float2 y0 = y[j0], y1 = y[j1], y2 = y[j2], y3 = y[j3];
     float2 t;
-    t = RN ? rn_term(yi, y0, c, eps) : nn_term(yi, y0); fx += t.x; fy += t.y;
-    t = RN ? rn_term(yi, y1, c, eps) : nn_term(yi, y1); fx += t.x; fy += t.y;
-    t = RN ? rn_term(yi, y2, c, eps) : nn_term(yi, y2); fx += t.x; fy += t.y;
-    t = RN ? rn_term(yi, y3, c, eps) : nn_term(yi, y3); fx += t.x; fy += t.y;
+    t = RN ? rn_term<L1>(yi, y0, c, eps) : nn_term<L1>(yi, y0); fx += t.x; fy += t.y;
+    t = RN ? rn_term<L1>(yi, y1, c, eps) : nn_term<L1>(yi, y1); fx += t.x; fy += t.y;
+    t = RN ? rn_term<L1>(yi, y2, c, eps) : nn_term<L1>(yi, y2); fx += t.x; fy += t.y;
+    t = RN ? rn_term<L1>(yi, y3, c, eps) : nn_term<L1>(yi, y3); fx += t.x; fy += t.y;
   }
   for (; p < e; ++p) {
-    const float2 t = RN ? rn_term(yi, y[src[p]], c, eps) : nn_term(yi, y[src[p]]);
+    const float2 t = RN ? rn_term<L1>(yi, y[src[p]], c, eps) : nn_term<L1>(yi, y[src[p]]);
     fx += t.x; fy += t.y;
   }
 }
 
-// force on a light vertex: out-nn, out-rn, in-nn, in-rn, in that order
+// force on a light vertex: out-nn, out-rn, in-nn, in-rn, in that order.
+// Positions are gathered from A.h (Y, or the look-ahead H = Y + a V).
+template <bool L1>
 __device__ __forceinline__ float2 light_force(const StepArgs &A, int64_t i, float2 yi, int32_t ns,
                                               int32_t ne) {
-  const float2 *__restrict__ y = A.y;
+  const float2 *__restrict__ y = A.h;
   float fx = 0.f, fy = 0.f;
   for (int q = 0; q < A.nn; ++q) {
     const int32_t j = A.nn_idx[i * A.nn + q];
     if (j >= 0) {
-      const float2 t = nn_term(yi, y[j]);
+      const float2 t = nn_term<L1>(yi, y[j]);
       fx += t.x; fy += t.y;
     }
   }
   for (int q = 0; q < A.rn; ++q) {
     const int32_t k = A.rn_idx[i * A.rn + q];
     if (k >= 0) {
-      const float2 t = rn_term(yi, y[k], A.c, A.eps);
+      const float2 t = rn_term<L1>(yi, y[k], A.c, A.eps);
       fx += t.x; fy += t.y;
     }
   }
-  gather_segment<false>(y, A.nn_src, ns, ne, yi, A.c, A.eps, fx, fy);
-  if (A.rn > 0) gather_segment<true>(y, A.rn_src, A.rn_ptr[i], A.rn_ptr[i + 1], yi, A.c, A.eps, fx, fy);
+  gather_segment<false, L1>(y, A.nn_src, ns, ne, yi, A.c, A.eps, fx, fy);
+  if (A.rn > 0) gather_segment<true, L1>(y, A.rn_src, A.rn_ptr[i], A.rn_ptr[i + 1], yi, A.c, A.eps, fx, fy);
   return make_float2(fx, fy);
 }
 
 // force on a heavy vertex, computed by a whole wavefront: the vertex's edge
 // list (out-nn | out-rn | in-nn | in-rn) is split over the lanes round-robin,
 // then reduced with a fixed butterfly; every lane returns the total
+template <bool L1>
 __device__ __forceinline__ float2 heavy_force(const StepArgs &A, int64_t i, float2 yi, int lane) {
-  const float2 *__restrict__ y = A.y;
+  const float2 *__restrict__ y = A.h;
   const int32_t ns = A.nn_ptr[i], ne = A.nn_ptr[i + 1];
   const int32_t rs = A.rn > 0 ? A.rn_ptr[i] : 0, re = A.rn > 0 ? A.rn_ptr[i + 1] : 0;
   const int32_t n_out = A.nn + A.rn, n_in_nn = ne - ns;
@@ -103,14 +132,14 @@ __device__ __forceinline__ float2 heavy_force(const StepArgs &A, int64_t i, floa
     float2 t;
     if (e < A.nn) {
       const int32_t j = A.nn_idx[i * A.nn + e];
-      t = j >= 0 ? nn_term(yi, y[j]) : make_float2(0.f, 0.f);
+      t = j >= 0 ? nn_term<L1>(yi, y[j]) : make_float2(0.f, 0.f);
     } else if (e < n_out) {
       const int32_t k = A.rn_idx[i * A.rn + (e - A.nn)];
-      t = k >= 0 ? rn_term(yi, y[k], A.c, A.eps) : make_float2(0.f, 0.f);
+      t = k >= 0 ? rn_term<L1>(yi, y[k], A.c, A.eps) : make_float2(0.f, 0.f);
     } else if (e < n_out + n_in_nn) {
-      t = nn_term(yi, y[A.nn_src[ns + (e - n_out)]]);
+      t = nn_term<L1>(yi, y[A.nn_src[ns + (e - n_out)]]);
     } else {
-      t = rn_term(yi, y[A.rn_src[rs + (e - n_out - n_in_nn)]], A.c, A.eps);
+      t = rn_term<L1>(yi, y[A.rn_src[rs + (e - n_out - n_in_nn)]], A.c, A.eps);
     }
     fx += t.x; fy += t.y;
   }
@@ -122,54 +151,90 @@ __device__ __forceinline__ float2 heavy_force(const StepArgs &A, int64_t i, floa
   return make_float2(fx, fy);
 }
 
-__device__ __forceinline__ void apply_update(const StepArgs &A, int64_t i, float2 yi, float2 f) {
+// v' = a v + b f, y' = y + v'.  hi is the position the force was taken at
+// (y itself unless NEST).  Returns the vertex's |v'|^2 - |v|^2 in FP64 for
+// ADAPT (+inf when the tentative position is not finite, which forces a
+// rejection); the non-finite flag is raised only for steps that are final.
+template <bool NEST, bool ADAPT>
+__device__ __forceinline__ double apply_update(const StepArgs &A, int64_t i, float2 hi, float2 f) {
+  const float2 yi = NEST ? A.y[i] : hi;
   const float2 v0 = A.v[i];
-  const float2 v = make_float2(A.a * v0.x + A.b * f.x, A.a * v0.y + A.b * f.y);
+  const float b = ADAPT ? *A.b_dev : A.b;
+  // explicit fused multiply-adds: every variant rounds the update identically
+  const float2 v = make_float2(fmaf(b, f.x, A.a * v0.x), fmaf(b, f.y, A.a * v0.y));
   const float2 yn = make_float2(yi.x + v.x, yi.y + v.y);
-  A.v[i] = v;
   A.y_out[i] = yn;
-  if (!(isfinite(yn.x) && isfinite(yn.y))) A.flags[FLAG_NONFINITE] = 1;
+  if (ADAPT) {
+    A.v_out[i] = v;
+  } else {
+    A.v[i] = v;
+  }
+  if (NEST) A.h_out[i] = make_float2(fmaf(A.a, v.x, yn.x), fmaf(A.a, v.y, yn.y));
+  const bool finite = isfinite(yn.x) && isfinite(yn.y);
+  if (ADAPT) {
+    if (!finite) return (double)INFINITY;
+    return ((double)v.x * v.x + (double)v.y * v.y) - ((double)v0.x * v0.x + (double)v0.y * v0.y);
+  }
+  if (!finite) A.flags[FLAG_NONFINITE] = 1;
+  return 0.0;
 }
 
-// GRAD = false: one iteration (force + update); GRAD = true: out = s grad E = -2 s f
-// with s = *gscale (1 when NULL)
-template <bool GRAD>
+// fixed-order block sum of one double per thread (256 threads)
+__device__ __forceinline__ void block_sum_store(double x, double *out) {
+  __shared__ double lds[kBlock];
+  lds[threadIdx.x] = x;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = lds[0];
+}
+
+// GRAD = true: out = s grad E = -2 s f with s = *gscale (1 when NULL), at
+// A.h = A.y; otherwise one iteration (force + update).  No thread leaves
+// before the ADAPT block sum.
+template <bool GRAD, bool L1, bool NEST, bool ADAPT>
 __global__ void __launch_bounds__(kBlock) det_kernel(StepArgs A, float2 *out) {
+  double ke = 0.0;
   if ((int32_t)blockIdx.x < A.heavy_blocks) {
     const int lane = threadIdx.x & 63;
     const int32_t h = (int32_t)blockIdx.x * kHeavyPerBlock + (int32_t)(threadIdx.x >> 6);
-    if (h >= A.n_heavy) return;
-    const int64_t i = A.heavy[h];
-    const float2 yi = A.y[i];
-    const float2 f = heavy_force(A, i, yi, lane);
-    if (lane == 0) {
-      if (GRAD) {
-        const float g = -2.f * (A.gscale ? *A.gscale : 1.f);
-        out[i] = make_float2(g * f.x, g * f.y);
-      } else {
-        apply_update(A, i, yi, f);
+    if (h < A.n_heavy) {   // uniform over the wavefront
+      const int64_t i = A.heavy[h];
+      const float2 hi = A.h[i];
+      const float2 f = heavy_force<L1>(A, i, hi, lane);
+      if (lane == 0) {
+        if (GRAD) {
+          const float g = -2.f * (A.gscale ? *A.gscale : 1.f);
+          out[i] = make_float2(g * f.x, g * f.y);
+        } else {
+          ke = apply_update<NEST, ADAPT>(A, i, hi, f);
+        }
       }
     }
-    return;
-  }
-  // XCD-aware tiles: blocks are dealt to the XCDs round-robin, so block b runs
-  // on XCD b % kXcds; each XCD is given one contiguous range of tiles, keeping
-  // the positions its vertices gather from in its own L2
-  const int32_t lb = (int32_t)blockIdx.x - A.heavy_blocks;
-  const int32_t tile = (lb % kXcds) * A.tiles_per_xcd + lb / kXcds;
-  if (tile >= A.light_tiles) return;
-  const int64_t i = (int64_t)tile * kBlock + threadIdx.x;
-  if (i >= A.M) return;
-  const int32_t ns = A.nn_ptr[i], ne = A.nn_ptr[i + 1];
-  if (ne - ns > kHeavyDegree) return;   // served by a heavy wavefront
-  const float2 yi = A.y[i];
-  const float2 f = light_force(A, i, yi, ns, ne);
-  if (GRAD) {
-    const float g = -2.f * (A.gscale ? *A.gscale : 1.f);
-    out[i] = make_float2(g * f.x, g * f.y);
   } else {
-    apply_update(A, i, yi, f);
+    // XCD-aware tiles: blocks are dealt to the XCDs round-robin, so block b
+    // runs on XCD b % kXcds; each XCD is given one contiguous range of tiles,
+    // keeping the positions its vertices gather from in its own L2
+    const int32_t lb = (int32_t)blockIdx.x - A.heavy_blocks;
+    const int32_t tile = (lb % kXcds) * A.tiles_per_xcd + lb / kXcds;
+    const int64_t i = (int64_t)tile * kBlock + threadIdx.x;
+    if (tile < A.light_tiles && i < A.M) {
+      const int32_t ns = A.nn_ptr[i], ne = A.nn_ptr[i + 1];
+      if (ne - ns <= kHeavyDegree) {   // else served by a heavy wavefront
+        const float2 hi = A.h[i];
+        const float2 f = light_force<L1>(A, i, hi, ns, ne);
+        if (GRAD) {
+          const float g = -2.f * (A.gscale ? *A.gscale : 1.f);
+          out[i] = make_float2(g * f.x, g * f.y);
+        } else {
+          ke = apply_update<NEST, ADAPT>(A, i, hi, f);
+        }
+      }
+    }
   }
+  if (ADAPT) block_sum_store(ke, A.ke_part + blockIdx.x);
 }
 
 __global__ void heavy_list_kernel(const int32_t *__restrict__ nn_ptr, int64_t M, int32_t *list,
@@ -179,16 +244,17 @@ __global__ void heavy_list_kernel(const int32_t *__restrict__ nn_ptr, int64_t M,
   if (nn_ptr[i + 1] - nn_ptr[i] > kHeavyDegree) list[atomicAdd(count, 1)] = (int32_t)i;
 }
 
+template <bool L1>
 __global__ void __launch_bounds__(kBlock) scatter_force_kernel(StepArgs A) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.M) return;
-  const float2 *__restrict__ y = A.y;
+  const float2 *__restrict__ y = A.h;
   const float2 yi = y[i];
   float fx = 0.f, fy = 0.f;
   for (int q = 0; q < A.nn; ++q) {
     const int32_t j = A.nn_idx[i * A.nn + q];
     if (j >= 0) {
-      float2 t = nn_term(yi, y[j]);
+      float2 t = nn_term<L1>(yi, y[j]);
       fx += t.x; fy += t.y;
       unsafeAtomicAdd(&A.fbuf[j].x, -t.x);
       unsafeAtomicAdd(&A.fbuf[j].y, -t.y);
@@ -196,7 +262,7 @@ __global__ void __launch_bounds__(kBlock) scatter_force_kernel(StepArgs A) {
   }
   for (int q = 0; q < A.rn; ++q) {
     const int32_t k = A.rn_idx[i * A.rn + q];
-    float2 t = rn_term(yi, y[k], A.c, A.eps);
+    float2 t = rn_term<L1>(yi, y[k], A.c, A.eps);
     fx += t.x; fy += t.y;
     unsafeAtomicAdd(&A.fbuf[k].x, -t.x);
     unsafeAtomicAdd(&A.fbuf[k].y, -t.y);
@@ -205,12 +271,14 @@ __global__ void __launch_bounds__(kBlock) scatter_force_kernel(StepArgs A) {
   unsafeAtomicAdd(&A.fbuf[i].y, fy);
 }
 
+// update after the scatter pass; in place (y_out == y), H rewritten in place
+template <bool NEST>
 __global__ void __launch_bounds__(kBlock) atomic_update_kernel(StepArgs A) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.M) return;
   const float2 f = A.fbuf[i];
   A.fbuf[i] = make_float2(0.f, 0.f);
-  apply_update(A, i, A.y[i], f);
+  (void)apply_update<NEST, false>(A, i, NEST ? make_float2(0.f, 0.f) : A.y[i], f);
 }
 
 __global__ void __launch_bounds__(kBlock) atomic_grad_out_kernel(float2 *fbuf, int64_t M, const float *gscale,
@@ -223,9 +291,73 @@ __global__ void __launch_bounds__(kBlock) atomic_grad_out_kernel(float2 *fbuf, i
   out[i] = make_float2(g * f.x, g * f.y);
 }
 
-unsigned det_grid(const StepArgs &a) { return (unsigned)(a.heavy_blocks + kXcds * a.tiles_per_xcd); }
+// H = Y + a V (the look-ahead positions of the Nesterov variant)
+__global__ void lookahead_kernel(const float2 *__restrict__ y, const float2 *__restrict__ v, float a, int64_t M,
+                                 float2 *__restrict__ h) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const float2 yi = y[i], vi = v[i];
+  h[i] = make_float2(yi.x + a * vi.x, yi.y + a * vi.y);
+}
+
+// accept / reject of a tentative step: dT = the fixed-order sum of the block
+// partials; kept when finite and |dT| <= tau, else b *= (dT < -tau ? g1 : g2)
+__global__ void __launch_bounds__(kBlock) adapt_decide_kernel(const double *__restrict__ part, int nparts,
+                                                              double tau, float g1, float g2, AdaptState *st) {
+  __shared__ double lds[kBlock];
+  double x = 0.0;
+  for (int p = threadIdx.x; p < nparts; p += kBlock) x += part[p];
+  lds[threadIdx.x] = x;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double dT = lds[0];
+    const bool keep = isfinite(dT) && fabs(dT) <= tau;
+    st->dT = dT;
+    st->reject = keep ? 0 : 1;
+    if (keep) {
+      st->kept += 1;
+    } else {
+      st->b = st->b * (dT < -tau ? g1 : g2);
+      st->rejected += 1;
+    }
+  }
+}
+
+// after a rejection the next state is the current one again
+__global__ void adapt_commit_kernel(const AdaptState *__restrict__ st, const float2 *__restrict__ y,
+                                    const float2 *__restrict__ v, int64_t M, float2 *__restrict__ y_next,
+                                    float2 *__restrict__ v_next) {
+  if (!st->reject) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  y_next[i] = y[i];
+  v_next[i] = v[i];
+}
 
 }  // namespace
+
+hipError_t launch_lookahead(const float2 *y, const float2 *v, float a, int64_t M, float2 *h, hipStream_t s) {
+  lookahead_kernel<<<grid_for(M), kBlock, 0, s>>>(y, v, a, M, h);
+  return hipGetLastError();
+}
+
+hipError_t launch_adapt_decide(const double *part, int nparts, double tau, float g1, float g2, AdaptState *st,
+                               hipStream_t s) {
+  adapt_decide_kernel<<<1, kBlock, 0, s>>>(part, nparts, tau, g1, g2, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_adapt_commit(const AdaptState *st, const float2 *y, const float2 *v, int64_t M, float2 *y_next,
+                               float2 *v_next, hipStream_t s) {
+  adapt_commit_kernel<<<grid_for(M), kBlock, 0, s>>>(st, y, v, M, y_next, v_next);
+  return hipGetLastError();
+}
+
+unsigned det_grid(const StepArgs &a) { return (unsigned)(a.heavy_blocks + kXcds * a.tiles_per_xcd); }
 
 hipError_t launch_heavy_list(const int32_t *nn_ptr, int64_t M, int32_t *list, int32_t *count,
                              hipStream_t s) {
@@ -234,23 +366,37 @@ hipError_t launch_heavy_list(const int32_t *nn_ptr, int64_t M, int32_t *list, in
 }
 
 hipError_t launch_step_det(const StepArgs &a, hipStream_t s) {
-  det_kernel<false><<<det_grid(a), kBlock, 0, s>>>(a, nullptr);
+  const unsigned g = det_grid(a);
+  if (a.adapt) {
+    if (a.l1) det_kernel<false, true, false, true><<<g, kBlock, 0, s>>>(a, nullptr);
+    else det_kernel<false, false, false, true><<<g, kBlock, 0, s>>>(a, nullptr);
+  } else if (a.nesterov) {
+    if (a.l1) det_kernel<false, true, true, false><<<g, kBlock, 0, s>>>(a, nullptr);
+    else det_kernel<false, false, true, false><<<g, kBlock, 0, s>>>(a, nullptr);
+  } else {
+    if (a.l1) det_kernel<false, true, false, false><<<g, kBlock, 0, s>>>(a, nullptr);
+    else det_kernel<false, false, false, false><<<g, kBlock, 0, s>>>(a, nullptr);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_step_atomic(const StepArgs &a, hipStream_t s) {
-  scatter_force_kernel<<<grid_for(a.M), kBlock, 0, s>>>(a);
-  atomic_update_kernel<<<grid_for(a.M), kBlock, 0, s>>>(a);
+  if (a.l1) scatter_force_kernel<true><<<grid_for(a.M), kBlock, 0, s>>>(a);
+  else scatter_force_kernel<false><<<grid_for(a.M), kBlock, 0, s>>>(a);
+  if (a.nesterov) atomic_update_kernel<true><<<grid_for(a.M), kBlock, 0, s>>>(a);
+  else atomic_update_kernel<false><<<grid_for(a.M), kBlock, 0, s>>>(a);
   return hipGetLastError();
 }
 
 hipError_t launch_grad_det(const StepArgs &a, float2 *out, hipStream_t s) {
-  det_kernel<true><<<det_grid(a), kBlock, 0, s>>>(a, out);
+  if (a.l1) det_kernel<true, true, false, false><<<det_grid(a), kBlock, 0, s>>>(a, out);
+  else det_kernel<true, false, false, false><<<det_grid(a), kBlock, 0, s>>>(a, out);
   return hipGetLastError();
 }
 
 hipError_t launch_grad_atomic(const StepArgs &a, float2 *out, hipStream_t s) {
-  scatter_force_kernel<<<grid_for(a.M), kBlock, 0, s>>>(a);
+  if (a.l1) scatter_force_kernel<true><<<grid_for(a.M), kBlock, 0, s>>>(a);
+  else scatter_force_kernel<false><<<grid_for(a.M), kBlock, 0, s>>>(a);
   atomic_grad_out_kernel<<<grid_for(a.M), kBlock, 0, s>>>(a.fbuf, a.M, a.gscale, out);
   return hipGetLastError();
 }

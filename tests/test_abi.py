@@ -63,7 +63,7 @@ FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
     (dict(a=1.5), "a ="), (dict(a=float("nan")), "a ="), (dict(b=0.0), "b ="),
     (dict(b=float("inf")), "b ="), (dict(c=0.0), "c ="), (dict(c=1.0), "c ="),
     (dict(eps=-1.0), "eps ="), (dict(rn_resample_every=-3), "rn_resample_every"),
-    (dict(mode=7), "mode ="), (dict(M=2**30, nn=4), "2^31-1 edges"), (dict(flags=6), "flags ="),
+    (dict(mode=7), "mode ="), (dict(M=2**30, nn=4), "2^31-1 edges"), (dict(flags=8), "flags ="),
     (dict(reserved=3), "reserved ="),
 ])
 def test_init_rejects_bad_parameters(lib, kw, frag):
@@ -102,6 +102,8 @@ def test_calls_on_a_missing_or_foreign_context_report_state(lib):
         assert lib.ivhd_set_iteration(ctx, 0) == -4
         assert lib.ivhd_set_state(ctx, FAKE, FAKE) == -4
         assert lib.ivhd_get_order(ctx, FAKE) == -4
+        assert lib.ivhd_set_adaptive(ctx, 1, 0.01, 1.0, 1.1, 0.5) == -4
+        assert lib.ivhd_get_adaptive(ctx, None, None, None, None) == -4
     assert lib.ivhd_destroy(None) == 0
     assert lib.ivhd_destroy(bogus) == -4
     assert "invalid context" in lib.ivhd_last_error().decode()
@@ -109,3 +111,18 @@ def test_calls_on_a_missing_or_foreign_context_report_state(lib):
 
 def test_version(lib):
     assert lib.ivhd_version() >= 100
+
+
+@pytest.mark.parametrize("M,nn,kh,frag", [
+    (1, 2, 8, "M ="), (100, 0, 8, "nn ="), (100, 65, 8, "nn ="), (100, 2, 0, "kh ="),
+    (100, 2, 257, "kh ="), (2**30, 4, 8, "max(nn, kh)"),
+])
+def test_rnn_mask_rejects_bad_sizes(lib, M, nn, kh, frag):
+    assert lib.ivhd_rnn_mask(FAKE, M, nn, FAKE, kh, ctypes.c_void_p(0x2000), None) == -1
+    assert frag in lib.ivhd_last_error().decode()
+
+
+def test_rnn_mask_rejects_null_and_aliased_buffers(lib):
+    assert lib.ivhd_rnn_mask(None, 100, 2, FAKE, 8, FAKE, None) == -1
+    assert lib.ivhd_rnn_mask(FAKE, 100, 2, FAKE, 8, FAKE, None) == -1
+    assert "alias" in lib.ivhd_last_error().decode()

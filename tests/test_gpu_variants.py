@@ -1,0 +1,291 @@
+"""Parity of the loop's variants (through the C ABI) with the FP64 oracle:
+the l1 distance of the late stage, Nesterov look-ahead, the self-adaptive b
+and the reverse-neighbour mask.
+
+Bars: single steps from the same FP32 state agree to 1e-5 norm-wise (the
+infinity norm of the oracle's array is the scale), a few steps to 1e-4; the
+FP64 stress to 1e-10 relative; the mask bit for bit; the adaptive scheme's
+accept / reject sequence exactly, checked only where the oracle's |dT| is
+well clear of tau (the decision is taken from FP64 sums of FP32 velocities
+on the GPU and of FP64 velocities in the oracle).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ivhd():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2303_05455_amd as m
+    return m
+
+
+def _case(M, nn, rn, seed, *, hub=0.0, absent=0.0, star=0, scale=2.0):
+    rng = np.random.default_rng(seed)
+    nn_idx = synth.random_neighbour_graph(M, nn, rng, hub_alpha=hub, absent_frac=absent)
+    if star:
+        nn_idx[1:star + 1, 0] = 0
+    Y = rng.normal(0, scale, size=(M, 2)).astype(np.float32)
+    V = (0.01 * rng.normal(size=(M, 2))).astype(np.float32)
+    return nn_idx, Y, V
+
+
+def f32(x):
+    return float(np.float32(x))
+
+
+def _rel(x, ref):
+    return float(np.max(np.abs(np.asarray(x, np.float64) - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+def _ctx(ivhd, nn_idx, Y, V, **kw):
+    return ivhd.Context(torch.from_numpy(nn_idx).cuda(), torch.from_numpy(Y).cuda(),
+                        torch.from_numpy(V).cuda(), **kw)
+
+
+CASES = [
+    (2000, 2, 1, 0, {}),
+    (5003, 5, 1, 1, dict(absent=0.1)),
+    (4099, 3, 2, 2, dict(hub=0.7)),
+    (3001, 2, 1, 3, dict(star=2500)),
+    (777, 1, 0, 4, {}),
+]
+MODES = [("det", True), ("det", False), ("atomic", True)]
+
+
+# ---- l1 distance -----------------------------------------------------------
+
+@pytest.mark.parametrize("mode,reorder", MODES)
+@pytest.mark.parametrize("M,nn,rn,seed,extra", CASES)
+def test_l1_step_grad_and_stress_match_oracle(ivhd, mode, reorder, M, nn, rn, seed, extra):
+    a, b, c, eps = f32(0.9), f32(0.01), f32(0.1), f32(1e-12)
+    nn_idx, Y, V = _case(M, nn, rn, seed, **extra)
+    ctx = _ctx(ivhd, nn_idx, Y, V, rn=rn, a=a, b=b, c=c, eps=eps, seed=seed, mode=mode, reorder=reorder,
+               metric="l1")
+    rn_idx = ctx.rn_edges().cpu().numpy()
+    f_ref = oracle.force(Y, nn_idx, rn_idx, c, eps, metric="l1")
+    assert _rel(-0.5 * ctx.grad().cpu().numpy(), f_ref) <= 1e-5
+    assert ctx.stress() == pytest.approx(oracle.stress(Y, nn_idx, rn_idx, c, "l1"), rel=1e-10)
+    Y1_ref, V1_ref = oracle.step(Y, V, f_ref, a, b)
+    ctx.step(1)
+    torch.cuda.synchronize()
+    assert _rel(ctx.y.cpu().numpy(), Y1_ref) <= 1e-5
+    assert _rel(ctx.v.cpu().numpy(), V1_ref) <= 1e-5
+    ctx.close()
+
+
+# ---- Nesterov look-ahead ---------------------------------------------------
+
+@pytest.mark.parametrize("metric", ["l2", "l1"])
+@pytest.mark.parametrize("mode,reorder", MODES)
+@pytest.mark.parametrize("M,nn,rn,seed,extra", CASES[:4])
+def test_nesterov_steps_match_oracle(ivhd, metric, mode, reorder, M, nn, rn, seed, extra):
+    a, b, c, eps = f32(0.9), f32(0.01), f32(0.1), f32(1e-12)
+    nn_idx, Y, V = _case(M, nn, rn, seed, **extra)
+    ctx = _ctx(ivhd, nn_idx, Y, V, rn=rn, a=a, b=b, c=c, eps=eps, seed=seed, mode=mode, reorder=reorder,
+               nesterov=True, metric=metric, rn_resample_every=2)
+    Y1, V1, _ = oracle.run(Y, V, nn_idx, rn=rn, a=a, b=b, c=c, eps=eps, seed=seed, R=2, T=1,
+                           nesterov=True, metric=metric)
+    ctx.step(1)
+    torch.cuda.synchronize()
+    assert _rel(ctx.y.cpu().numpy(), Y1) <= 1e-5
+    assert _rel(ctx.v.cpu().numpy(), V1) <= 1e-5
+    Y5, V5, _ = oracle.run(Y, V, nn_idx, rn=rn, a=a, b=b, c=c, eps=eps, seed=seed, R=2, T=5,
+                           nesterov=True, metric=metric)
+    ctx.step(4)
+    torch.cuda.synchronize()
+    assert _rel(ctx.y.cpu().numpy(), Y5) <= 1e-4
+    assert _rel(ctx.v.cpu().numpy(), V5) <= 1e-4
+    ctx.close()
+
+
+def test_nesterov_is_a_different_method(ivhd):
+    # the look-ahead changes the result (guards against the flag being ignored)
+    nn_idx, Y, V = _case(2000, 2, 1, 8)
+    outs = []
+    for nest in (False, True):
+        ctx = _ctx(ivhd, nn_idx, Y, V, rn=1, b=0.01, seed=1, nesterov=nest)
+        ctx.step(3)
+        torch.cuda.synchronize()
+        outs.append(ctx.y.cpu().numpy())
+        ctx.close()
+    ref = oracle.run(Y, V, nn_idx, rn=1, a=f32(0.9), b=f32(0.01), c=f32(0.1), seed=1, T=3, nesterov=True)[0]
+    assert _rel(outs[1], ref) <= 1e-4 and _rel(outs[0], ref) > 1e-3
+
+
+@pytest.mark.parametrize("variant", [dict(nesterov=True), dict(metric="l1"),
+                                     dict(nesterov=True, metric="l1", mode="atomic")])
+def test_variant_graphs_match_direct_launches(ivhd, variant):
+    # replayed HIP graphs (epoch graphs with draws, 64-iteration chunks) and
+    # direct launches give the same result (bitwise in det mode).  b is
+    # small: the hubs make the l1 and look-ahead iterations stiffer.
+    nn_idx, Y, V = _case(4000, 3, 1, 9, hub=0.5)
+    outs = []
+    for graphs in (True, False):
+        ctx = _ctx(ivhd, nn_idx, Y, V, rn=1, b=1e-4, seed=4, rn_resample_every=7, **variant)
+        ctx.set_graphs(graphs)
+        for n in (5, 30, 2, 130):
+            ctx.step(n)
+        torch.cuda.synchronize()
+        outs.append((ctx.y.cpu().numpy(), ctx.v.cpu().numpy()))
+        ctx.close()
+    assert np.all(np.isfinite(outs[0][0]))
+    if variant.get("mode") == "atomic":
+        assert _rel(outs[0][0], outs[1][0].astype(np.float64)) <= 1e-4
+    else:
+        assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_nesterov_set_state_restarts_the_look_ahead(ivhd):
+    nn_idx, Y, V = _case(3000, 2, 1, 10)
+    a, b, c = f32(0.9), f32(0.01), f32(0.1)
+    ctx = _ctx(ivhd, nn_idx, Y, V, rn=1, a=a, b=b, c=c, seed=3, nesterov=True)
+    ctx.step(7)
+    ctx.set_state(torch.from_numpy(Y).cuda(), torch.from_numpy(V).cuda())
+    ctx.set_iteration(0)
+    ctx.step(2)
+    torch.cuda.synchronize()
+    Y2, V2, _ = oracle.run(Y, V, nn_idx, rn=1, a=a, b=b, c=c, seed=3, T=2, nesterov=True)
+    assert _rel(ctx.y.cpu().numpy(), Y2) <= 1e-5
+    ctx.close()
+
+
+# ---- self-adaptive b -------------------------------------------------------
+
+def test_adaptive_with_infinite_tau_is_bitwise_the_fixed_b_loop(ivhd):
+    nn_idx, Y, V = _case(5003, 3, 1, 11)     # no hubs: b = 0.01 is stable here
+    outs = []
+    for adaptive in (False, True):
+        ctx = _ctx(ivhd, nn_idx, Y, V, rn=1, b=0.01, seed=5, rn_resample_every=10)
+        if adaptive:
+            ctx.set_adaptive(True, tau=float("inf"), g1=1.1, g2=0.5)
+        ctx.step(33)
+        ctx.step(70)
+        torch.cuda.synchronize()
+        outs.append((ctx.y.cpu().numpy(), ctx.v.cpu().numpy()))
+        if adaptive:
+            st = ctx.adaptive()
+            assert st["kept"] == 103 and st["rejected"] == 0 and st["b"] == f32(0.01)
+        ctx.close()
+    assert np.all(np.isfinite(outs[0][0]))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("reorder,graphs", [(True, True), (False, False)])
+def test_adaptive_decisions_and_state_match_oracle(ivhd, reorder, graphs):
+    M, T = 3001, 40
+    nn_idx, Y, V = _case(M, 3, 1, 12, scale=1.0)
+    a, b0, c, tau, g1, g2 = f32(0.9), f32(0.08), f32(0.1), 0.02, f32(1.25), f32(0.5)
+    Yr, Vr, _, b_ref, tr = oracle.run_adaptive(Y, V, nn_idx, rn=1, a=a, b=b0, c=c, tau=tau, g1=g1, g2=g2,
+                                               seed=6, R=9, T=T)
+    # the comparison is only meaningful where no decision sits on the threshold
+    margin = np.min(np.abs(np.abs(tr["dT"]) - tau)) / tau
+    assert margin > 1e-3, margin
+    assert 0 < tr["kept"].sum() < T
+    ctx = _ctx(ivhd, nn_idx, Y, V, rn=1, a=a, b=b0, c=c, seed=6, rn_resample_every=9, reorder=reorder)
+    ctx.set_graphs(graphs)
+    ctx.set_adaptive(True, tau=tau, g1=g1, g2=g2)
+    kept_prev = 0
+    for k in range(T):
+        ctx.step(1)
+        st = ctx.adaptive()
+        assert st["kept"] - kept_prev == tr["kept"][k], k
+        assert st["dT"] == pytest.approx(tr["dT"][k], rel=1e-4, abs=1e-6 * np.abs(tr["dT"]).max())
+        kept_prev = st["kept"]
+    assert st["rejected"] == T - tr["kept"].sum()
+    assert st["b"] == pytest.approx(b_ref, rel=1e-6)
+    torch.cuda.synchronize()
+    assert _rel(ctx.y.cpu().numpy(), Yr) <= 1e-4
+    assert _rel(ctx.v.cpu().numpy(), Vr) <= 1e-4
+    ctx.close()
+
+
+def test_adaptive_b_keeps_a_too_large_step_finite(ivhd):
+    nn_idx, Y, V = _case(4000, 3, 1, 13, hub=0.5, scale=1.0)
+    ctx = _ctx(ivhd, nn_idx, Y, V, rn=1, b=1.5, seed=2)
+    ctx.set_adaptive(True, tau=1.0, g1=1.05, g2=0.5)
+    ctx.step(200)
+    torch.cuda.synchronize()
+    st = ctx.adaptive()
+    y = ctx.y.cpu().numpy()
+    assert np.all(np.isfinite(y)) and np.abs(y).max() < 1e3
+    assert st["b"] < 1.5 and st["kept"] > 0 and st["kept"] + st["rejected"] == 200
+    assert np.isfinite(ctx.stress())
+    ctx.close()
+
+
+def test_adaptive_rejects_bad_use(ivhd):
+    nn_idx, Y, V = _case(500, 2, 1, 14)
+    ctx = _ctx(ivhd, nn_idx, Y, V, rn=1, mode="atomic")
+    with pytest.raises(ivhd.IvhdError, match="IVHD_MODE_DET"):
+        ctx.set_adaptive(True, tau=1.0)
+    ctx.close()
+    ctx = _ctx(ivhd, nn_idx, Y, V, rn=1, nesterov=True)
+    with pytest.raises(ivhd.IvhdError, match="NESTEROV"):
+        ctx.set_adaptive(True, tau=1.0)
+    ctx.close()
+    ctx = _ctx(ivhd, nn_idx, Y, V, rn=1)
+    with pytest.raises(ivhd.IvhdError, match="never enabled"):
+        ctx.adaptive()
+    for kw, frag in ((dict(g1=1.0), "g1"), (dict(g2=1.0), "g2"), (dict(tau=-1.0), "tau"),
+                     (dict(b=0.0), "b =")):
+        with pytest.raises(ivhd.IvhdError, match=frag):
+            ctx.set_adaptive(True, **{"tau": 1.0, **kw})
+    # switching it on at odd parity and off again keeps the state
+    ctx.step(3)
+    ctx.set_adaptive(True, tau=float("inf"))
+    ctx.step(2)
+    ctx.set_adaptive(False)
+    ctx.step(1)
+    torch.cuda.synchronize()
+    ref = oracle.run(Y, V, nn_idx, rn=1, a=f32(0.9), b=f32(0.01), c=f32(0.1), T=6)[0]
+    assert _rel(ctx.y.cpu().numpy(), ref) <= 1e-4
+    ctx.close()
+
+
+# ---- reverse-neighbour mask ------------------------------------------------
+
+def test_rnn_mask_matches_oracle_on_exact_knn_lists(ivhd):
+    rng = np.random.default_rng(15)
+    M, N, nn = 3000, 8, 3
+    X = rng.normal(size=(M, N))
+    nn_idx = oracle.knn(X, nn)
+    helper = oracle.knn(X, 4 * nn)
+    want = oracle.rnn_mask(nn_idx, helper)
+    d_nn, d_h = torch.from_numpy(nn_idx).cuda(), torch.from_numpy(helper).cuda()
+    got = ivhd.ivhd_rnn_mask(d_nn, d_h).cpu().numpy()
+    assert np.array_equal(got, want)
+    assert 0 < (got < 0).sum() < got.size
+    ivhd.ivhd_rnn_mask(d_nn, d_h, out=d_nn)           # in place
+    assert np.array_equal(d_nn.cpu().numpy(), want)
+
+
+def test_rnn_mask_at_full_size(ivhd):
+    cfg = synth.CONFIGS["C3"]
+    rng = np.random.default_rng(16)
+    nn_idx = synth.random_neighbour_graph(cfg.M, cfg.nn, rng, hub_alpha=1.2, absent_frac=0.01)
+    helper = synth.random_neighbour_graph(cfg.M, 4 * cfg.nn, rng)
+    # make part of the helper lists reciprocal so both outcomes occur
+    rows = rng.choice(cfg.M, cfg.M // 3, replace=False)
+    tgt = nn_idx[rows, 0]
+    ok = tgt >= 0
+    helper[tgt[ok], 0] = rows[ok]
+    want = oracle.rnn_mask(nn_idx, helper)
+    got = ivhd.ivhd_rnn_mask(torch.from_numpy(nn_idx).cuda(), torch.from_numpy(helper).cuda()).cpu().numpy()
+    assert np.array_equal(got, want)
+    assert 100_000 < (got >= 0).sum() < (nn_idx >= 0).sum()
+
+
+def test_rnn_mask_rejects_bad_indices(ivhd):
+    nn_idx = np.array([[1], [2], [5]], np.int32)     # 5 is outside [-1, 3)
+    helper = np.zeros((3, 2), np.int32)
+    with pytest.raises(ivhd.IvhdError, match="outside"):
+        ivhd.ivhd_rnn_mask(torch.from_numpy(nn_idx).cuda(), torch.from_numpy(helper).cuda())
