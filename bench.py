@@ -23,6 +23,11 @@ Other workloads (one JSON line each, not the headline):
                 (gradient kernel) at 1,000,000 points, nn = 5, rn = 1
   --config C5   the parametric encoder: training throughput, embedding of the
                 held-out points, and their kNN preservation beside plain IVHD
+  --refine      the late-stage refinements (reverse-neighbour mask for the
+                last 200 iterations, l1 distance for the last 50) against the
+                plain loop, by Q_NX(10) and cf_10 (use with --config C2)
+The C1-C3 lines also carry the loop's variants (Nesterov, l1, adaptive b)
+timed on the same workload.
 """
 from __future__ import annotations
 
@@ -44,6 +49,8 @@ BF16_PEAK_TFLOPS = 2500.0
 STEP_SOURCE = os.path.join(ROOT, "paper_2303_05455_amd", "csrc", "step.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_det_C3_traffic.md")
 METRIC = "edge-updates/sec (M·(nn+rn)·iters/s) at M=1.4M + achieved HBM GB/s"
+# adaptive-b threshold on |dT| (the kinetic energy change per step), per point
+ADAPT_TAU_PER_POINT = 1e-6
 
 
 def log(msg):
@@ -211,6 +218,36 @@ def run_loop(args, cfg):
         log(f"det step kernel: {per_launch * 1e6:.2f} us/launch, {achieved:.0f} GB/s algorithmic "
             f"({achieved / HBM_PEAK_GBPS:.1%} of 8 TB/s)")
 
+    # the thesis's variants of the loop on the same workload (det mode).  The
+    # look-ahead and the l1 distance lower the stability bound of b (Nesterov:
+    # b lambda_max < 2 (1 + a) / (1 + 2 a); l1: up to twice the stiffness), so
+    # those two run at b / 2.
+    variants = {}
+    for name, kw, b in () if args.no_variants else (("nesterov", dict(nesterov=True), cfg.b / 2), ("l1", dict(metric="l1"), cfg.b / 2),
+                        ("adaptive", dict(), cfg.b)):
+        y = d_y0.clone()
+        v = torch.zeros_like(y)
+        ctx = Context(nn_idx, y, v, rn=rn, a=cfg.a, b=b, c=cfg.c, seed=cfg.seed,
+                      rn_resample_every=R, mode="det", **kw)
+        if name == "adaptive":
+            ctx.set_adaptive(True, tau=ADAPT_TAU_PER_POINT * M, g1=1.05, g2=0.5)
+        ctx.set_graphs(not args.no_graphs)
+        ctx.step(T)
+        torch.cuda.synchronize()
+        e0, e1 = events()
+        e0.record()
+        ctx.step(T)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 1e3
+        variants[name] = {"value": M * (nn + rn) * T / t, "us_per_iter": t * 1e6 / T, "b": b,
+                          "final_stress": ctx.stress()}
+        if name == "adaptive":
+            variants[name].update(ctx.adaptive())
+        ctx.close()
+        log(f"variant {name}: {variants[name]['value']:.4g} edge-updates/s, "
+            f"{variants[name]['us_per_iter']:.2f} us/iter")
+
     cpu = None
     if not args.no_cpu:
         log(f"timing the FP64 oracle on {args.cpu_iters} iterations ...")
@@ -244,6 +281,7 @@ def run_loop(args, cfg):
         "gbps_alg": r["gbps_alg"],
         "us_per_iter": r["us_per_iter"],
         "modes": res,
+        "variants": variants,
         "knn_build_s": knn_s,
         "max_nn_in_degree": max_in,
         "roofline": roofline,
@@ -301,7 +339,7 @@ def run_stress(args, cfg):
                                f"nn={nn}, rn={rn}", "M": M, "nn": nn, "rn": rn},
         "forward_us": t_fwd * 1e6, "backward_us": t_bwd * 1e6,
         "forward_gbps_alg": fwd_bytes / t_fwd / 1e9, "backward_gbps_alg": bwd_bytes / t_bwd / 1e9,
-        "knn_build_s": knn_s, "max_nn_in_degree": max_in, "heldout_max_nn_in_degree": max_in_h,
+        "knn_build_s": knn_s, "max_nn_in_degree": max_in,
     }
 
 
@@ -409,6 +447,72 @@ def run_encoder(args, cfg):
     }
 
 
+def run_refine(args, cfg):
+    """Late-stage refinements of the thesis's improvements chapter: the
+    reverse-neighbour mask (helper graph of 4 nn) for the last 200 iterations
+    and the l1 distance for the last 50, against the plain loop with the
+    same iteration count; quality by Q_NX(10) and cf_10 on 2000 sampled
+    points, cost as the extra wall time of the refinement stages."""
+    import torch
+    from paper_2303_05455_amd import Context, ivhd_knn_build, ivhd_rnn_mask
+    dev = torch.device("cuda:0")
+    M, nn, rn, T = cfg.M, cfg.nn, cfg.rn, cfg.T
+    dX, labels, Y0, nn_idx, knn_s, max_in = build_graph(cfg, dev)
+    rows = np.random.default_rng(5).choice(M, 2000, replace=False)
+    kw = dict(rn=rn, a=cfg.a, b=cfg.b, c=cfg.c, seed=cfg.seed, rn_resample_every=cfg.R)
+
+    def run_plain(n_iter):
+        y = torch.from_numpy(Y0).to(dev)
+        v = torch.zeros_like(y)
+        ctx = Context(nn_idx, y, v, **kw)
+        ctx.step(n_iter)
+        torch.cuda.synchronize()
+        ctx.close()
+        return y, v
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    y_base, _ = run_plain(T)
+    t_base = time.perf_counter() - t0
+    q_base, cf_base = q_nx_gpu(dX, y_base, rows, labels=labels)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    y, v = run_plain(T - 200)
+    t_helper = time.perf_counter()
+    helper = ivhd_knn_build(dX, 4 * nn)
+    nn_rnn = ivhd_rnn_mask(nn_idx, helper)
+    torch.cuda.synchronize()
+    t_helper = time.perf_counter() - t_helper
+    kept = float((nn_rnn >= 0).float().mean())
+    ctx = Context(nn_rnn, y, v, **kw)
+    ctx.set_iteration(T - 200)
+    ctx.step(150)
+    ctx.close()
+    ctx = Context(nn_rnn, y, v, metric="l1", **{**kw, "b": cfg.b / 2})   # l1 is stiffer: b / 2
+    ctx.set_iteration(T - 50)
+    ctx.step(50)
+    torch.cuda.synchronize()
+    ctx.close()
+    t_ref = time.perf_counter() - t0
+    q_ref, cf_ref = q_nx_gpu(dX, y, rows, labels=labels)
+    log(f"refine {cfg.name}: plain {T} it Q_NX(10)={q_base:.4f} cf_10={cf_base:.4f} in {t_base:.2f} s; "
+        f"reverse-neighbour mask (keeps {kept:.1%} of nn edges) for the last 200 it, l1 for the last 50: "
+        f"Q_NX(10)={q_ref:.4f} cf_10={cf_ref:.4f} in {t_ref:.2f} s (helper graph + mask {t_helper:.2f} s)")
+    return {
+        "metric": "late-stage refinement: Q_NX(10) and cf_10 vs plain IVHD, same iteration count",
+        "value": t_ref, "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": t_ref * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: M={M:,} N={cfg.N}, nn={nn}, rn={rn}, {T} iterations; helper "
+                               f"kNN graph of {4 * nn}; reverse-neighbour mask for the last 200, l1 "
+                               f"distance for the last 50", "M": M, "N": cfg.N, "T": T},
+        "q_nx10_plain": q_base, "cf10_plain": cf_base, "plain_s": t_base,
+        "q_nx10_refined": q_ref, "cf10_refined": cf_ref, "refined_s": t_ref,
+        "helper_and_mask_s": t_helper, "nn_edges_kept": kept, "knn_build_s": knn_s,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -418,9 +522,12 @@ def main():
     ap.add_argument("--mode", default="both", choices=["det", "atomic", "both"])
     ap.add_argument("--cpu-iters", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the Nesterov / l1 / adaptive lines")
     ap.add_argument("--no-graphs", action="store_true")
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB")
+    ap.add_argument("--refine", action="store_true",
+                    help="late-stage refinements (reverse-neighbour mask, l1) vs the plain loop")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -435,7 +542,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     import synth
     cfg = synth.CONFIGS[args.config]
-    if cfg.name == "C4":
+    if args.refine:
+        out = run_refine(args, cfg)
+    elif cfg.name == "C4":
         out = run_stress(args, cfg)
     elif cfg.name == "C5":
         out = run_encoder(args, cfg)
