@@ -232,27 +232,22 @@ __global__ void colsum_kernel(int mode, const void *__restrict__ Xp, const float
   if (j >= J) return;
   const int64_t r0 = (int64_t)blockIdx.y * rows_per_chunk;
   const int64_t r1 = r0 + rows_per_chunk < R ? r0 + rows_per_chunk : R;
-  float s = 0.f;
-  if (mode == 0) {
-    const uint16_t *X = static_cast<const uint16_t *>(Xp);
-    for (int64_t r = r0; r < r1; ++r) s += bf2f(X[r * J + j]);
-  } else if (mode == 1) {
-    const uint16_t *H = static_cast<const uint16_t *>(Xp);
-    const int64_t o = j / K, k = j % K;
-    for (int64_t r = r0; r < r1; ++r) s += dZ[2 * r + o] * bf2f(H[r * K + k]);
-  } else {
-    const float *X = static_cast<const float *>(Xp);
-    for (int64_t r = r0; r < r1; ++r) s += X[r * J + j];
+  auto val = [&](int64_t r) -> float {
+    if (mode == 0) return bf2f(static_cast<const uint16_t *>(Xp)[r * J + j]);
+    if (mode == 1) return dZ[2 * r + j / K] * bf2f(static_cast<const uint16_t *>(Xp)[r * K + j % K]);
+    return static_cast<const float *>(Xp)[r * J + j];
+  };
+  // four running sums (loads in flight), combined in a fixed order
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  int64_t r = r0;
+  for (; r + 4 <= r1; r += 4) {
+    s0 += val(r);
+    s1 += val(r + 1);
+    s2 += val(r + 2);
+    s3 += val(r + 3);
   }
-  part[(int64_t)blockIdx.y * J + j] = s;
-}
-
-__global__ void chunk_reduce_kernel(const float *__restrict__ part, int chunks, int64_t J, float *__restrict__ out) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= J) return;
-  float s = 0.f;
-  for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * J + j];
-  out[j] = s;
+  for (; r < r1; ++r) s0 += val(r);
+  part[(int64_t)blockIdx.y * J + j] = (s0 + s1) + (s2 + s3);
 }
 
 // Adam with bias correction 1/(1 - beta^t); refreshes the BF16 copy
@@ -345,12 +340,30 @@ hipError_t launch_head_dgrad(const float *dZ, const uint16_t *W3, const uint16_t
   return hipGetLastError();
 }
 
-hipError_t launch_colsum(int mode, const void *X, const float *dZ, int64_t R, int64_t J, int64_t K,
-                         float *part, int chunks, float *out, hipStream_t s) {
-  const int64_t rpc = (R + chunks - 1) / chunks;
-  dim3 grid(grid_for(J), (unsigned)chunks);
-  colsum_kernel<<<grid, kBlock, 0, s>>>(mode, X, dZ, R, J, K, rpc < 1 ? 1 : rpc, part);
-  chunk_reduce_kernel<<<grid_for(J), kBlock, 0, s>>>(part, chunks, J, out);
+int64_t colsum_workspace(int64_t R, int64_t J) {
+  const int64_t c0 = (R + kColsumRows - 1) / kColsumRows;
+  return (c0 + (c0 + kColsumRows - 1) / kColsumRows) * J;
+}
+
+// Column sums as a tree: each level sums kColsumRows consecutive rows per
+// thread into partials [ceil(rows / kColsumRows)][J], until one row is left
+// (written to out).  Levels ping-pong between two regions of ws.
+hipError_t launch_colsum(int mode, const void *X, const float *dZ, int64_t R, int64_t J, int64_t K, float *ws,
+                         float *out, hipStream_t s) {
+  if (R < 1 || (R + kColsumRows - 1) / kColsumRows > 65535) return hipErrorInvalidValue;
+  const int64_t c0 = (R + kColsumRows - 1) / kColsumRows;
+  float *buf[2] = {ws, ws + c0 * J};
+  const void *src = X;
+  int64_t rows = R;
+  for (int level = 0;; ++level) {
+    const int64_t chunks = (rows + kColsumRows - 1) / kColsumRows;
+    float *dst = chunks == 1 ? out : buf[level & 1];
+    colsum_kernel<<<dim3(grid_for(J), (unsigned)chunks), kBlock, 0, s>>>(level == 0 ? mode : 2, src, dZ, rows, J,
+                                                                         K, kColsumRows, dst);
+    if (chunks == 1) break;
+    src = dst;
+    rows = chunks;
+  }
   return hipGetLastError();
 }
 

@@ -16,6 +16,8 @@
 #include <new>
 #include <unordered_set>
 
+#include <algorithm>
+
 #include "enc_internal.h"
 
 struct ivhd_enc {
@@ -32,7 +34,6 @@ struct ivhd_enc {
   float *ws = nullptr;
   int64_t ws_elems = 0;
   int splits = 16;
-  int chunks = 64;
   // epoch training state
   int32_t *rows = nullptr;
   int32_t *lnn = nullptr, *lrn = nullptr;
@@ -121,18 +122,18 @@ int train_step_rows(ivhd_enc *e, int64_t R, ivhd_edges *plan, float c, float eps
   if ((rc = ivhd_edges_grad(plan, e->z, c, eps, nullptr, e->dz))) return rc;
   // head
   HIPCHK(launch_head_dgrad(e->dz, e->w16 + e->oW3, e->a2, R, e->h2, e->d2, s));
-  HIPCHK(launch_colsum(1, e->a2, e->dz, R, 2 * (int64_t)e->h2, e->h2, e->ws, e->chunks, e->g + e->oW3, s));
-  HIPCHK(launch_colsum(2, e->dz, nullptr, R, 2, 2, e->ws, e->chunks, e->g + e->ob3, s));
+  HIPCHK(launch_colsum(1, e->a2, e->dz, R, 2 * (int64_t)e->h2, e->h2, e->ws, e->g + e->oW3, s));
+  HIPCHK(launch_colsum(2, e->dz, nullptr, R, 2, 2, e->ws, e->g + e->ob3, s));
   // layer 2
   GemmArgs gd = gemm(e->d2, e->w16 + e->oW2, R, e->h1, e->h2, e->h2, e->h1, e->d1, e->h1);
   gd.mask = e->a1;
   gd.ldm = e->h1;
   HIPCHK(launch_gemm_bf16(gd, 0, 0, GEMM_EPI_RELU_MASK_BF16, 1, s));
   if ((rc = wgrad(e, e->d2, e->h2, e->a1, e->h1, R, e->g + e->oW2))) return rc;
-  HIPCHK(launch_colsum(0, e->d2, nullptr, R, e->h2, e->h2, e->ws, e->chunks, e->g + e->ob2, s));
+  HIPCHK(launch_colsum(0, e->d2, nullptr, R, e->h2, e->h2, e->ws, e->g + e->ob2, s));
   // layer 1
   if ((rc = wgrad(e, e->d1, e->h1, e->xb, e->n_in, R, e->g + e->oW1))) return rc;
-  HIPCHK(launch_colsum(0, e->d1, nullptr, R, e->h1, e->h1, e->ws, e->chunks, e->g + e->ob1, s));
+  HIPCHK(launch_colsum(0, e->d1, nullptr, R, e->h1, e->h1, e->ws, e->g + e->ob1, s));
   // Adam
   e->t += 1;
   HIPCHK(launch_adam(e->w, e->g, e->m, e->v, e->w16, e->n_params, lr, 0.9f, 0.999f, 1e-8f, e->t, scale, s));
@@ -185,7 +186,8 @@ int ivhd_enc_create(ivhd_enc **out, int32_t n_in, int32_t h1, int32_t h2, uint64
   e->r_cap = max_rows;
   const int64_t wmax = (int64_t)h1 * n_in > (int64_t)h2 * h1 ? (int64_t)h1 * n_in : (int64_t)h2 * h1;
   e->ws_elems = wmax * e->splits;
-  const int64_t colsum_ws = (int64_t)e->chunks * (2 * (int64_t)h2 > (h1 > h2 ? h1 : h2) ? 2 * (int64_t)h2 : (h1 > h2 ? h1 : h2));
+  const int64_t jmax = std::max<int64_t>(2 * (int64_t)h2, std::max(h1, h2));
+  const int64_t colsum_ws = colsum_workspace(max_rows, jmax);
   if (colsum_ws > e->ws_elems) e->ws_elems = colsum_ws;
   int rc;
 #define ENC_CHK(expr) \

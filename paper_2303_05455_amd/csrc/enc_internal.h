@@ -33,9 +33,13 @@ hipError_t launch_head_forward(const uint16_t *H, int64_t R, int K, const uint16
                                hipStream_t s);
 hipError_t launch_head_dgrad(const float *dZ, const uint16_t *W3, const uint16_t *H, int64_t R, int K,
                              uint16_t *dH, hipStream_t s);
-// column sums over R rows (chunks partial sums, then a fixed-order reduce); see colsum_kernel
-hipError_t launch_colsum(int mode, const void *X, const float *dZ, int64_t R, int64_t J, int64_t K,
-                         float *part, int chunks, float *out, hipStream_t s);
+// column sums over R rows as a fixed-order tree of kColsumRows-row partial
+// sums (deterministic); see colsum_kernel for the modes.  ws must hold
+// colsum_workspace(R, J) floats.
+constexpr int kColsumRows = 32;
+int64_t colsum_workspace(int64_t R, int64_t J);
+hipError_t launch_colsum(int mode, const void *X, const float *dZ, int64_t R, int64_t J, int64_t K, float *ws,
+                         float *out, hipStream_t s);
 hipError_t launch_adam(float *w, const float *g, float *m, float *v, uint16_t *w16, int64_t n, float lr, float b1,
                        float b2, float eps, int64_t t, float gscale, hipStream_t s);
 hipError_t launch_glorot(float *w, int64_t n, int fan_in, int fan_out, uint64_t seed, uint64_t offset,

@@ -179,9 +179,18 @@ int stress_partials(int64_t M);
 // ---- knn.hip ----
 int knn_max_k();
 hipError_t launch_row_norms(const float *X, int64_t M, int N, float *out, hipStream_t s);
-// self_mode: 0 = none, 1 = query q excludes candidate q, 2 = query q excludes self[q]
-hipError_t launch_knn(const float *X, int64_t M, int N, const float *Q, int64_t nq, int self_mode,
-                      const int32_t *self, const float *cnorm, int k, int32_t *idx, float *dist,
+// largest |X[e]| over n values as float bits, max-combined into *out (zero it first)
+hipError_t launch_absmax(const float *X, int64_t n, uint32_t *out, hipStream_t s);
+int knn_padded_width(int N);            // N rounded up to the staged K step
+float knn_split_scale(float absmax);    // power of two keeping scaled values below 2^14
+// hi / lo FP16 rows of scale * X, [M][Np], zero padded
+hipError_t launch_split(const float *X, int64_t M, int N, int Np, float scale, _Float16 *hi, _Float16 *lo,
+                        hipStream_t s);
+// self_mode: 0 = none, 1 = query q excludes candidate q, 2 = query q excludes self[q].
+// Xh/Xl, Qh/Ql: the split rows of X and Q at the same scale (Qh == Xh when Q == X).
+hipError_t launch_knn(const float *X, int64_t M, int N, const float *Q, int64_t nq, const _Float16 *Xh,
+                      const _Float16 *Xl, const _Float16 *Qh, const _Float16 *Ql, int Np, float scale,
+                      int self_mode, const int32_t *self, const float *cnorm, int k, int32_t *idx, float *dist,
                       hipStream_t s);
 
 }  // namespace ivhd

@@ -5,15 +5,25 @@
 // Order: squared Euclidean distance, ties to the lower index, the query
 // itself excluded.
 //
+// Dot products on the FP16 matrix cores with FP32 accumulation, at close to
+// FP32 accuracy: every coordinate, scaled by a power of two so the largest
+// magnitude sits below 2^14, is split into hi = fp16(x) and
+// lo = fp16(x - hi) (22 significant bits together), and
+//     q.x ~= hi_q.hi_x + hi_q.lo_x + lo_q.hi_x
+// (the dropped lo.lo term is below 2^-22 of |q_k x_k|; each fp16 product is
+// exact in FP32).  Three v_mfma_f32_16x16x32_f16 per product block give
+// about 5x the throughput of the FP32 matrix path.
+//
 // A block of 256 threads (4 waves) owns 128 queries and sweeps all
-// candidates in tiles of 64.  The dot products of a 128 x 64 tile come from
-// FP32 MFMA (v_mfma_f32_16x16x4f32), with both operand tiles staged in LDS
-// 16 features at a time.  The ranking score |x_c|^2 - 2 q.x_c (|q|^2 is
-// the same for the whole row) goes to LDS, where two threads per query row
-// keep running top-KP lists in registers.  At the end the two lists are
-// merged and the KP survivors are re-ranked by their exact FP32 distance
-// sum_k (q_k - x_k)^2, which removes the cancellation error of the
-// expanded form; KP >= k + 4 leaves room for candidates the score misranks.
+// candidates in tiles of 64, K in steps of 32 staged in LDS (K contiguous per
+// row: one lane's operand, 8 consecutive k, is one 16-byte read).  The
+// ranking score |x_c|^2 - 2 q.x_c (|q|^2 is the same for the whole row) goes
+// to LDS (aliasing the operand buffers, which are dead by then), where two
+// threads per query row keep running top-KP lists in registers.  At the end
+// the two lists are merged and the KP survivors are re-ranked by their exact
+// FP32 distance sum_k (q_k - x_k)^2, which removes the cancellation error of
+// the expanded form; KP >= k + 4 leaves room for candidates the score
+// misranks.
 #include <cfloat>
 
 #include "ivhd_internal.h"
@@ -22,14 +32,15 @@ namespace ivhd {
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
 constexpr int QB = 128;        // queries per block
 constexpr int CB = 64;         // candidates per tile
-constexpr int KC = 16;         // features per staged chunk
-constexpr int QP = QB + 16;    // LDS row pitch (== 16 mod 32: the two 16-lane
-constexpr int CP = CB + 16;    //   groups of an operand read hit disjoint banks)
-constexpr int SP = CB + 1;     // score tile pitch
+constexpr int TKK = 32;        // features per staged step
+constexpr int HP = TKK + 8;    // LDS row pitch in halves (80 bytes, 16-byte aligned rows)
+constexpr int SP = CB + 1;     // score tile pitch (floats)
 constexpr int kKnnThreads = 256;
+constexpr int kSplitMaxExp = 14;   // scaled magnitudes stay below 2^14
 
 __device__ __forceinline__ bool pair_less(float a, int32_t ia, float b, int32_t ib) {
   return a < b || (a == b && ia < ib);
@@ -62,15 +73,69 @@ __global__ void __launch_bounds__(256) row_norms_kernel(const float *__restrict_
   if (lane == 0) out[row] = s;
 }
 
+// largest |x| (as the bits of a non-negative float, so integer max is float
+// max); NaN sets the top bits and is reported by the host
+__global__ void __launch_bounds__(256) absmax_kernel(const float *__restrict__ X, int64_t n, uint32_t *out) {
+  uint32_t m = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t u = __float_as_uint(X[e]) & 0x7fffffffu;
+    m = u > m ? u : m;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t t = __shfl_xor(m, o, 64);
+    m = t > m ? t : m;
+  }
+  if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+}
+
+// hi / lo FP16 rows of scale * X, padded with zeros to Np (a multiple of TKK)
+__global__ void split_kernel(const float *__restrict__ X, int64_t M, int N, int Np, float scale,
+                             _Float16 *__restrict__ hi, _Float16 *__restrict__ lo) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * Np) return;
+  const int64_t r = e / Np;
+  const int c = (int)(e % Np);
+  const float x = c < N ? X[r * N + c] * scale : 0.f;
+  const _Float16 h = (_Float16)x;
+  hi[e] = h;
+  lo[e] = (_Float16)(x - (float)h);
+}
+
+// rows r0..r0+ROWS-1 of a [rows][Np] half array, features k0..k0+31, into LDS
+// (pitch HP); rows past the end read as zeros
+template <int ROWS>
+__device__ __forceinline__ void stage_rows(_Float16 *__restrict__ lds, const _Float16 *__restrict__ P, int64_t rows,
+                                           int Np, int64_t r0, int k0) {
+  constexpr int kChunks = ROWS * (TKK / 8);   // 16-byte chunks
+#pragma unroll
+  for (int c = 0; c < (kChunks + kKnnThreads - 1) / kKnnThreads; ++c) {
+    const int id = threadIdx.x + kKnnThreads * c;
+    if (kChunks % kKnnThreads == 0 || id < kChunks) {
+      const int r = id >> 2, kc = (id & 3) * 8;
+      halfx8 v = {};
+      if (r0 + r < rows) v = *reinterpret_cast<const halfx8 *>(P + (r0 + r) * Np + k0 + kc);
+      *reinterpret_cast<halfx8 *>(lds + r * HP + kc) = v;
+    }
+  }
+}
+
 // self_mode: 0 = no exclusion, 1 = query q excludes candidate q, 2 = self[q]
 template <int KP>
 __global__ void __launch_bounds__(kKnnThreads)
 knn_kernel(const float *__restrict__ X, int64_t M, int N, const float *__restrict__ Q, int64_t nq,
-           int self_mode, const int32_t *__restrict__ self, const float *__restrict__ cnorm, int k,
+           const _Float16 *__restrict__ Xh, const _Float16 *__restrict__ Xl, const _Float16 *__restrict__ Qh,
+           const _Float16 *__restrict__ Ql, int Np, float inv_scale2, int self_mode,
+           const int32_t *__restrict__ self, const float *__restrict__ cnorm, int k,
            int32_t *__restrict__ out_idx, float *__restrict__ out_dist) {
-  __shared__ float sQ[KC * QP];
-  __shared__ float sC[KC * CP];
-  __shared__ float sS[QB * SP];
+  // one LDS area: the operand tiles during the K loop, then the score tile
+  __shared__ __attribute__((aligned(16))) float smem[QB * SP];
+  static_assert((2 * QB + 2 * CB) * HP * 2 <= QB * SP * 4, "operand tiles must fit in the score tile");
+  _Float16 *sQh = reinterpret_cast<_Float16 *>(smem);
+  _Float16 *sQl = sQh + QB * HP;
+  _Float16 *sCh = sQl + QB * HP;
+  _Float16 *sCl = sCh + CB * HP;
+  float *sS = smem;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -89,6 +154,7 @@ knn_kernel(const float *__restrict__ X, int64_t M, int N, const float *__restric
 #pragma unroll
   for (int p = 0; p < KP; ++p) { ks[p] = FLT_MAX; ki[p] = INT32_MAX; }
 
+  const int kq = (lane >> 4) * 8;
   for (int64_t c0 = 0; c0 < M; c0 += CB) {
     floatx4 acc[2][4];
 #pragma unroll
@@ -96,44 +162,38 @@ knn_kernel(const float *__restrict__ X, int64_t M, int N, const float *__restric
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    for (int kc = 0; kc < N; kc += KC) {
+    for (int k0 = 0; k0 < Np; k0 += TKK) {
+      __syncthreads();   // the previous step's operands, or the previous tile's scores, are consumed
+      stage_rows<QB>(sQh, Qh, nq, Np, q0, k0);
+      stage_rows<QB>(sQl, Ql, nq, Np, q0, k0);
+      stage_rows<CB>(sCh, Xh, M, Np, c0, k0);
+      stage_rows<CB>(sCl, Xl, M, Np, c0, k0);
       __syncthreads();
+      halfx8 ah[2], al[2], bh[4], bl[4];
 #pragma unroll
-      for (int i = 0; i < (QB * KC) / kKnnThreads; ++i) {
-        const int e = tid + kKnnThreads * i;
-        const int r = e / KC, kk = e % KC;
-        const int64_t q = q0 + r;
-        float v = 0.f;
-        if (q < nq && kc + kk < N) v = Q[q * N + kc + kk];
-        sQ[kk * QP + r] = v;
+      for (int rb = 0; rb < 2; ++rb) {
+        const int r = 32 * wave + 16 * rb + (lane & 15);
+        ah[rb] = *reinterpret_cast<const halfx8 *>(sQh + r * HP + kq);
+        al[rb] = *reinterpret_cast<const halfx8 *>(sQl + r * HP + kq);
       }
 #pragma unroll
-      for (int i = 0; i < (CB * KC) / kKnnThreads; ++i) {
-        const int e = tid + kKnnThreads * i;
-        const int r = e / KC, kk = e % KC;
-        const int64_t c = c0 + r;
-        float v = 0.f;
-        if (c < M && kc + kk < N) v = X[c * N + kc + kk];
-        sC[kk * CP + r] = v;
+      for (int cb = 0; cb < 4; ++cb) {
+        const int r = 16 * cb + (lane & 15);
+        bh[cb] = *reinterpret_cast<const halfx8 *>(sCh + r * HP + kq);
+        bl[cb] = *reinterpret_cast<const halfx8 *>(sCl + r * HP + kq);
       }
-      __syncthreads();
 #pragma unroll
-      for (int s = 0; s < KC / 4; ++s) {
-        const int kidx = 4 * s + (lane >> 4);
-        float a[2], b[4];
+      for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb) a[rb] = sQ[kidx * QP + 32 * wave + 16 * rb + (lane & 15)];
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) b[cb] = sC[kidx * CP + 16 * cb + (lane & 15)];
-#pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-          for (int cb = 0; cb < 4; ++cb)
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
-      }
+        for (int cb = 0; cb < 4; ++cb) {
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[rb], bh[cb], acc[rb][cb], 0, 0, 0);
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[rb], bl[cb], acc[rb][cb], 0, 0, 0);
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[rb], bh[cb], acc[rb][cb], 0, 0, 0);
+        }
     }
+    __syncthreads();   // operands dead: the area becomes the score tile
 
-    // scores into LDS: D[i][j] of a 16x16 block sits in lane j + 16*(i/4), register i%4
+    // scores: D[i][j] of a 16x16 block sits in lane j + 16 (i / 4), register i % 4
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) {
       const int col = 16 * cb + (lane & 15);
@@ -144,7 +204,7 @@ knn_kernel(const float *__restrict__ X, int64_t M, int N, const float *__restric
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = 32 * wave + 16 * rb + 4 * (lane >> 4) + r;
-          sS[row * SP + col] = cn - 2.f * acc[rb][cb][r];
+          sS[row * SP + col] = cn - 2.f * (acc[rb][cb][r] * inv_scale2);
         }
     }
     __syncthreads();
@@ -170,49 +230,53 @@ knn_kernel(const float *__restrict__ X, int64_t M, int N, const float *__restric
   if (half == 0 && my_q < nq) {
 #pragma unroll
     for (int p = 0; p < KP; ++p) list_insert<KP>(ks, ki, mS[my_row * KP + p], mI[my_row * KP + p]);
+    // exact FP32 distances of the survivors, sorted in this row's LDS slots
+    // (a rolled loop: unrolled it would hold 3 KP values in registers for the
+    // whole kernel and cut its occupancy)
+    float *rs = mS + my_row * KP;
+    int32_t *ri = mI + my_row * KP;
     const float *qrow = Q + my_q * N;
-    float ed[KP];
 #pragma unroll
+    for (int p = 0; p < KP; ++p) ri[p] = ki[p];
+#pragma unroll 1
     for (int p = 0; p < KP; ++p) {
+      const int32_t c = ri[p];
       float d = FLT_MAX;
-      if (ki[p] != INT32_MAX) {
-        const float *xr = X + (int64_t)ki[p] * N;
+      if (c != INT32_MAX) {
+        const float *xr = X + (int64_t)c * N;
         d = 0.f;
         for (int kk = 0; kk < N; ++kk) {
           const float t = qrow[kk] - xr[kk];
           d += t * t;
         }
       }
-      ed[p] = d;
-    }
-    // exact re-rank: insertion sort of (ed, ki), fully unrolled
-#pragma unroll
-    for (int p = 1; p < KP; ++p) {
-#pragma unroll
-      for (int q = p; q > 0; --q) {
-        if (pair_less(ed[q], ki[q], ed[q - 1], ki[q - 1])) {
-          float t = ed[q]; ed[q] = ed[q - 1]; ed[q - 1] = t;
-          int32_t u = ki[q]; ki[q] = ki[q - 1]; ki[q - 1] = u;
-        }
+      // insertion into the sorted prefix rs[0..p)
+      int q = p;
+      while (q > 0 && pair_less(d, c, rs[q - 1], ri[q - 1])) {
+        rs[q] = rs[q - 1];
+        ri[q] = ri[q - 1];
+        --q;
       }
+      rs[q] = d;
+      ri[q] = c;
     }
-#pragma unroll
-    for (int p = 0; p < KP; ++p) {
-      if (p < k) {
-        out_idx[my_q * k + p] = ki[p] == INT32_MAX ? -1 : ki[p];
-        if (out_dist) out_dist[my_q * k + p] = ed[p];
-      }
+#pragma unroll 1
+    for (int p = 0; p < k; ++p) {
+      out_idx[my_q * k + p] = ri[p] == INT32_MAX ? -1 : ri[p];
+      if (out_dist) out_dist[my_q * k + p] = rs[p];
     }
   }
 }
 
 template <int KP>
-hipError_t launch_knn_kp(const float *X, int64_t M, int N, const float *Q, int64_t nq, int self_mode,
-                         const int32_t *self, const float *cnorm, int k, int32_t *idx, float *dist,
+hipError_t launch_knn_kp(const float *X, int64_t M, int N, const float *Q, int64_t nq, const _Float16 *Xh,
+                         const _Float16 *Xl, const _Float16 *Qh, const _Float16 *Ql, int Np, float inv_scale2,
+                         int self_mode, const int32_t *self, const float *cnorm, int k, int32_t *idx, float *dist,
                          hipStream_t s) {
   static_assert(2 * QB * KP <= QB * SP, "merge buffers must fit in the score tile");
   const unsigned grid = (unsigned)((nq + QB - 1) / QB);
-  knn_kernel<KP><<<grid, kKnnThreads, 0, s>>>(X, M, N, Q, nq, self_mode, self, cnorm, k, idx, dist);
+  knn_kernel<KP><<<grid, kKnnThreads, 0, s>>>(X, M, N, Q, nq, Xh, Xl, Qh, Ql, Np, inv_scale2, self_mode, self,
+                                               cnorm, k, idx, dist);
   return hipGetLastError();
 }
 
@@ -220,17 +284,46 @@ hipError_t launch_knn_kp(const float *X, int64_t M, int N, const float *Q, int64
 
 int knn_max_k() { return 28; }
 
+int knn_padded_width(int N) { return (N + TKK - 1) / TKK * TKK; }
+
 hipError_t launch_row_norms(const float *X, int64_t M, int N, float *out, hipStream_t s) {
   row_norms_kernel<<<grid_for(M, 4), 256, 0, s>>>(X, M, N, out);
   return hipGetLastError();
 }
 
-hipError_t launch_knn(const float *X, int64_t M, int N, const float *Q, int64_t nq, int self_mode,
-                      const int32_t *self, const float *cnorm, int k, int32_t *idx, float *dist,
+hipError_t launch_absmax(const float *X, int64_t n, uint32_t *out, hipStream_t s) {
+  absmax_kernel<<<1024, 256, 0, s>>>(X, n, out);
+  return hipGetLastError();
+}
+
+// 2^s with the largest scaled magnitude below 2^kSplitMaxExp; |s| <= 60 so
+// that 1 / scale^2 is a normal float (beyond that range squared distances
+// overflow or vanish in FP32 anyway)
+float knn_split_scale(float absmax) {
+  if (!(absmax > 0.f)) return 1.f;
+  int e;
+  (void)frexpf(absmax, &e);   // absmax = m 2^e, 0.5 <= m < 1
+  int sh = kSplitMaxExp - e;
+  sh = sh > 60 ? 60 : (sh < -60 ? -60 : sh);
+  return ldexpf(1.f, sh);
+}
+
+hipError_t launch_split(const float *X, int64_t M, int N, int Np, float scale, _Float16 *hi, _Float16 *lo,
+                        hipStream_t s) {
+  split_kernel<<<grid_for(M * Np), kBlock, 0, s>>>(X, M, N, Np, scale, hi, lo);
+  return hipGetLastError();
+}
+
+hipError_t launch_knn(const float *X, int64_t M, int N, const float *Q, int64_t nq, const _Float16 *Xh,
+                      const _Float16 *Xl, const _Float16 *Qh, const _Float16 *Ql, int Np, float scale,
+                      int self_mode, const int32_t *self, const float *cnorm, int k, int32_t *idx, float *dist,
                       hipStream_t s) {
-  if (k + 4 <= 8) return launch_knn_kp<8>(X, M, N, Q, nq, self_mode, self, cnorm, k, idx, dist, s);
-  if (k + 4 <= 16) return launch_knn_kp<16>(X, M, N, Q, nq, self_mode, self, cnorm, k, idx, dist, s);
-  return launch_knn_kp<32>(X, M, N, Q, nq, self_mode, self, cnorm, k, idx, dist, s);
+  const float inv2 = 1.f / (scale * scale);
+  if (k + 4 <= 8)
+    return launch_knn_kp<8>(X, M, N, Q, nq, Xh, Xl, Qh, Ql, Np, inv2, self_mode, self, cnorm, k, idx, dist, s);
+  if (k + 4 <= 16)
+    return launch_knn_kp<16>(X, M, N, Q, nq, Xh, Xl, Qh, Ql, Np, inv2, self_mode, self, cnorm, k, idx, dist, s);
+  return launch_knn_kp<32>(X, M, N, Q, nq, Xh, Xl, Qh, Ql, Np, inv2, self_mode, self, cnorm, k, idx, dist, s);
 }
 
 }  // namespace ivhd

@@ -5,6 +5,8 @@
 #include <new>
 #include <unordered_set>
 
+#include <cstring>
+
 #include "ivhd_internal.h"
 
 using namespace ivhd;
@@ -237,13 +239,50 @@ static int knn_common(const float *d_x, int64_t M, int32_t N, const float *d_q, 
   if (k < 1 || k > kmax) return fail(IVHD_EINVAL, "k = %d outside [1, %lld]", k, (long long)kmax);
   if (Q == 0) return IVHD_OK;
   hipStream_t s = (hipStream_t)stream;
+  const bool same = d_q == d_x && Q == M;
+  const int Np = knn_padded_width(N);
   float *norms = nullptr;
+  uint32_t *amax = nullptr;
+  _Float16 *xs = nullptr, *qs = nullptr;   // [2][rows][Np]: hi then lo
   int rc = dev_alloc(&norms, (size_t)M, "row norms");
-  if (rc) return rc;
-  hipError_t e = launch_row_norms(d_x, M, N, norms, s);
-  if (e == hipSuccess) e = launch_knn(d_x, M, N, d_q, Q, self_mode, d_self, norms, k, d_idx, d_dist, s);
+  if (!rc) rc = dev_alloc(&amax, 1, "largest magnitude");
+  if (!rc) rc = dev_alloc(&xs, (size_t)2 * M * Np, "split rows of X");
+  if (!rc && !same) rc = dev_alloc(&qs, (size_t)2 * Q * Np, "split rows of the queries");
+  auto cleanup = [&]() {
+    void *bufs[] = {norms, amax, xs, qs};
+    for (void *b : bufs)
+      if (b) (void)hipFree(b);
+  };
+  if (rc) {
+    cleanup();
+    return rc;
+  }
+  uint32_t bits = 0;
+  hipError_t e = hipMemsetAsync(amax, 0, sizeof *amax, s);
+  if (e == hipSuccess) e = launch_absmax(d_x, M * (int64_t)N, amax, s);
+  if (e == hipSuccess && !same) e = launch_absmax(d_q, Q * (int64_t)N, amax, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&bits, amax, sizeof bits, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(norms);
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "knn input scan");
+  }
+  float amx;
+  std::memcpy(&amx, &bits, sizeof amx);
+  if (!std::isfinite(amx)) {
+    cleanup();
+    return fail(IVHD_EINVAL, "the points hold a non-finite coordinate");
+  }
+  const float scale = knn_split_scale(amx);
+  _Float16 *qh = same ? xs : qs, *ql = same ? xs + M * Np : qs + Q * Np;
+  e = launch_row_norms(d_x, M, N, norms, s);
+  if (e == hipSuccess) e = launch_split(d_x, M, N, Np, scale, xs, xs + M * Np, s);
+  if (e == hipSuccess && !same) e = launch_split(d_q, Q, N, Np, scale, qs, qs + Q * Np, s);
+  if (e == hipSuccess)
+    e = launch_knn(d_x, M, N, d_q, Q, xs, xs + M * Np, qh, ql, Np, scale, self_mode, d_self, norms, k, d_idx, d_dist,
+                   s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  cleanup();
   if (e != hipSuccess) return hip_fail(e, "knn");
   return IVHD_OK;
 }
