@@ -74,6 +74,9 @@ def _load():
                                          i64, i64, i64, dbl, dbl, dbl, i32, vp, vp, vp, vp,
                                          vp, vp]
         lib.orc_run_adaptive.restype = i64
+        lib.orc_run_adam.argtypes = [i64, vp, vp, vp, i32, vp, i32, vp, dbl, dbl, dbl, dbl, dbl,
+                                     dbl, u64, i64, i64, i64, i64, i32, vp]
+        lib.orc_run_adam.restype = None
         _lib = lib
         return lib
 
@@ -200,6 +203,26 @@ def run_adaptive(Y0, V0, nn_idx, *, rn: int, a: float, b: float, c: float, tau: 
                              g1, g2, METRICS[metric], _ptr(dT), _ptr(bs), _ptr(kept),
                              *[_ptr(x) for x in scratch])
     return Y, V, rn_idx, bb.value, {"dT": dT, "b": bs, "kept": kept}
+
+
+def run_adam(Y0, nn_idx, *, rn: int, lr: float, c: float, b1: float = 0.9, b2: float = 0.999,
+             eps_adam: float = 1e-8, eps: float = 1e-12, seed: int = 0, R: int = 0, n0: int = 0,
+             T: int = 1, m0=None, s0=None, t0: int = 0, metric: str = "l2"):
+    """T iterations of Adam on the stress (see ivhd_oracle.c).
+
+    Returns (Y, m, s, rn_idx) in FP64; moments start at m0, s0 (zeros).
+    """
+    nn_idx, _ = _graph(nn_idx)
+    M, nn = nn_idx.shape
+    Y = np.array(Y0, dtype=np.float64, order="C", copy=True)
+    Mo = np.zeros((M, 2)) if m0 is None else np.array(m0, dtype=np.float64, order="C", copy=True)
+    S = np.zeros((M, 2)) if s0 is None else np.array(s0, dtype=np.float64, order="C", copy=True)
+    rn_idx = np.zeros((M, rn), dtype=np.int32)
+    f = np.empty((M, 2), dtype=np.float64)
+    _load().orc_run_adam(M, _ptr(Y), _ptr(Mo), _ptr(S), nn, _ptr(nn_idx), rn, _ptr(rn_idx), lr, b1, b2,
+                         eps_adam, c, eps, seed & 0xFFFFFFFFFFFFFFFF, R, n0, T, t0, METRICS[metric],
+                         _ptr(f))
+    return Y, Mo, S, rn_idx
 
 
 # ---------------------------------------------------------------------------

@@ -38,6 +38,10 @@
  *            and scales b by g1 > 1 when dT < -tau or by g2 < 1 when
  *            dT > tau (or dT is not finite); otherwise the step is kept and
  *            b stays.
+ *   adam     Adam of Sec. "Optimization methods" on g = grad E = -2 f, per
+ *            coordinate: m <- b1 m + (1 - b1) g, s <- b2 s + (1 - b2) g^2,
+ *            Y <- Y - lr (m / (1 - b1^t)) / (eps + sqrt(s / (1 - b2^t))),
+ *            t = 1, 2, ... the Adam step count (textbook bias correction).
  *   mask     reverse-neighbour pruning of Sec. "Reverse neighbors
  *            mechanism": an nn edge i -> j is kept only when i is also
  *            among the kh nearest neighbours of j in a wider helper graph.
@@ -256,4 +260,27 @@ int64_t orc_run_adaptive(int64_t M, double *Y, double *V, int32_t nn, const int3
         if (acc) acc[k] = keep;
     }
     return kept;
+}
+
+/* T Adam iterations from iteration n0; t0 Adam steps were taken before (the
+ * first step here uses t = t0 + 1).  Y, Mo (first moment), S (second
+ * moment): 2*M doubles, updated in place.  f: 2*M doubles of scratch.     */
+void orc_run_adam(int64_t M, double *Y, double *Mo, double *S, int32_t nn, const int32_t *nn_idx,
+                  int32_t rn, int32_t *rn_idx, double lr, double b1, double b2, double eps_a,
+                  double c, double eps, uint64_t seed, int64_t R, int64_t n0, int64_t T,
+                  int64_t t0, int32_t metric, double *f)
+{
+    for (int64_t n = n0; n < n0 + T; ++n) {
+        if (n == n0 || (R > 0 && n % R == 0))
+            orc_rn_sample(M, nn, nn_idx, rn, seed, R > 0 ? n / R : 0, rn_idx);
+        orc_force(M, Y, nn, nn_idx, rn, rn_idx, c, eps, metric, f);
+        double t = (double)(t0 + (n - n0) + 1);
+        double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
+        for (int64_t i = 0; i < 2 * M; ++i) {
+            double g = -2.0 * f[i];
+            Mo[i] = b1 * Mo[i] + (1.0 - b1) * g;
+            S[i] = b2 * S[i] + (1.0 - b2) * g * g;
+            Y[i] = Y[i] - lr * (Mo[i] / c1) / (eps_a + sqrt(S[i] / c2));
+        }
+    }
 }

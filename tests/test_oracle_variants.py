@@ -232,3 +232,34 @@ def test_adaptive_b_tames_a_step_that_diverges():
                                          g1=1.05, g2=0.5, T=60)
     assert np.all(np.isfinite(Y)) and np.abs(Y).max() < 100
     assert b < b_bad and tr["kept"].sum() > 0
+
+
+# ---- Adam on the stress ----------------------------------------------------
+
+def test_adam_matches_torch_adam_on_the_same_gradients():
+    torch = pytest.importorskip("torch")
+    nn_idx, rn_idx, Y0 = _graph(50, 3, 1, 17)
+    lr, b1, b2, eps_a, c, T = 0.01, 0.9, 0.999, 1e-8, 0.1, 12
+    Y, Mo, S, rn_got = oracle.run_adam(Y0, nn_idx, rn=1, lr=lr, c=c, b1=b1, b2=b2, eps_adam=eps_a,
+                                       seed=3, T=T)
+    rn_idx = oracle.rn_sample(nn_idx, 1, 3, 0)
+    assert np.array_equal(rn_got, rn_idx)
+    p = torch.tensor(Y0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([p], lr=lr, betas=(b1, b2), eps=eps_a)
+    for _ in range(T):
+        opt.zero_grad()
+        p.grad = torch.from_numpy(oracle.grad(p.detach().numpy(), nn_idx, rn_idx, c))
+        opt.step()
+    np.testing.assert_allclose(Y, p.detach().numpy(), rtol=1e-12, atol=1e-12)
+    st = opt.state[p]
+    np.testing.assert_allclose(Mo, st["exp_avg"].numpy(), rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(S, st["exp_avg_sq"].numpy(), rtol=1e-12, atol=1e-18)
+
+
+def test_adam_split_runs_resume_with_their_moments():
+    nn_idx, _, Y0 = _graph(40, 2, 0, 18)
+    A = oracle.run_adam(Y0, nn_idx, rn=1, lr=0.02, c=0.1, R=3, T=10)
+    Y1, m1, s1, _ = oracle.run_adam(Y0, nn_idx, rn=1, lr=0.02, c=0.1, R=3, T=4)
+    B = oracle.run_adam(Y1, nn_idx, rn=1, lr=0.02, c=0.1, R=3, n0=4, T=6, m0=m1, s0=s1, t0=4)
+    for x, y in zip(A[:3], B[:3]):
+        np.testing.assert_array_equal(x, y)
