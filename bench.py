@@ -26,8 +26,8 @@ Other workloads (one JSON line each, not the headline):
   --refine      the late-stage refinements (reverse-neighbour mask for the
                 last 200 iterations, l1 distance for the last 50) against the
                 plain loop, by Q_NX(10) and cf_10 (use with --config C2)
-The C1-C3 lines also carry the loop's variants (Nesterov, l1, adaptive b)
-timed on the same workload.
+The C1-C3 lines also carry the loop's variants (Nesterov, l1, adaptive b,
+Adam) timed on the same workload.
 """
 from __future__ import annotations
 
@@ -51,6 +51,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_det_C3_traffic.md")
 METRIC = "edge-updates/sec (M·(nn+rn)·iters/s) at M=1.4M + achieved HBM GB/s"
 # adaptive-b threshold on |dT| (the kinetic energy change per step), per point
 ADAPT_TAU_PER_POINT = 1e-6
+# Adam on the loop: each coordinate moves by about lr per step
+ADAM_LR = 1e-3
 
 
 def log(msg):
@@ -224,13 +226,15 @@ def run_loop(args, cfg):
     # those two run at b / 2.
     variants = {}
     for name, kw, b in () if args.no_variants else (("nesterov", dict(nesterov=True), cfg.b / 2), ("l1", dict(metric="l1"), cfg.b / 2),
-                        ("adaptive", dict(), cfg.b)):
+                        ("adaptive", dict(), cfg.b), ("adam", dict(), cfg.b)):
         y = d_y0.clone()
         v = torch.zeros_like(y)
         ctx = Context(nn_idx, y, v, rn=rn, a=cfg.a, b=b, c=cfg.c, seed=cfg.seed,
                       rn_resample_every=R, mode="det", **kw)
         if name == "adaptive":
             ctx.set_adaptive(True, tau=ADAPT_TAU_PER_POINT * M, g1=1.05, g2=0.5)
+        if name == "adam":
+            ctx.set_adam(True, lr=ADAM_LR)
         ctx.set_graphs(not args.no_graphs)
         ctx.step(T)
         torch.cuda.synchronize()

@@ -179,10 +179,22 @@ int ivhd_set_graphs(ivhd_ctx *ctx, int32_t enable);
  *   b     the current b (replaces params.b), b > 0
  *   tau   threshold on |dT|, tau >= 0 (+inf: never reject)
  *   g1    > 1;  g2 in (0, 1)
- * Deterministic mode only, not with IVHD_FLAG_NESTEROV (IVHD_EINVAL).
+ * Deterministic mode only, not with IVHD_FLAG_NESTEROV or Adam (IVHD_EINVAL).
  * Clears the kept / rejected counters.  enable = 0 returns to the fixed
  * params.b (the other arguments are ignored).  Synchronises the stream.     */
 int ivhd_set_adaptive(ivhd_ctx *ctx, int32_t enable, float b, double tau, float g1, float g2);
+
+/* ivhd_set_adam: Adam (Sec. "Optimization methods") in place of the momentum
+ * update, on the gradient g = grad E per coordinate:
+ *   m <- beta1 m + (1 - beta1) g,  s <- beta2 s + (1 - beta2) g^2,
+ *   Y <- Y - lr (m / (1 - beta1^t)) / (eps + sqrt(s / (1 - beta2^t))),
+ * t = 1, 2, ... counting Adam steps since it was enabled.  V holds (and
+ * returns to the caller) the first moments m.  enable = 1 zeroes m and s
+ * and restarts t; enable = 0 goes back to the momentum update with the
+ * current V.  lr > 0, beta1 and beta2 in [0, 1), eps > 0.  Deterministic
+ * mode only, not with IVHD_FLAG_NESTEROV or the adaptive b (IVHD_EINVAL).
+ * Synchronises the stream.                                                  */
+int ivhd_set_adam(ivhd_ctx *ctx, int32_t enable, float lr, float beta1, float beta2, float eps);
 
 /* ivhd_get_adaptive: the adaptive state after the work queued so far
  * (synchronises): current b, kept and rejected step counts, and dT of the

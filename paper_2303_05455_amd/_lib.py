@@ -44,6 +44,7 @@ SIGNATURES = {
     "ivhd_set_graphs": (i32, [vp, i32]),
     "ivhd_set_adaptive": (i32, [vp, i32, f32, f64, f32, f32]),
     "ivhd_get_adaptive": (i32, [vp, vp, vp, vp, vp]),
+    "ivhd_set_adam": (i32, [vp, i32, f32, f32, f32, f32]),
     "ivhd_rnn_mask": (i32, [vp, i64, i32, vp, i32, vp, vp]),
     "ivhd_destroy": (i32, [vp]),
     "ivhd_edges_create": (i32, [ctypes.POINTER(vp), i64, vp, i32, vp, i32, vp]),

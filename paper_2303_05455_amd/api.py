@@ -23,7 +23,7 @@ __all__ = [
     "ivhd_get_iteration", "ivhd_set_graphs", "ivhd_destroy", "ivhd_last_error",
     "ivhd_version", "ivhd_knn_build", "ivhd_knn_query", "ivhd_edges_create", "ivhd_edges_stress",
     "ivhd_edges_grad", "ivhd_edges_destroy", "ivhd_grad_edges", "ivhd_set_adaptive",
-    "ivhd_get_adaptive", "ivhd_rnn_mask",
+    "ivhd_get_adaptive", "ivhd_rnn_mask", "ivhd_set_adam",
 ]
 
 
@@ -138,6 +138,11 @@ def ivhd_destroy(ctx) -> None:
 def ivhd_set_adaptive(ctx, enable: bool, b: float = 0.0, tau: float = float("inf"), g1: float = 1.05,
                       g2: float = 0.5) -> None:
     check(_lib.load().ivhd_set_adaptive(ctx, 1 if enable else 0, b, tau, g1, g2))
+
+
+def ivhd_set_adam(ctx, enable: bool, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+                  eps: float = 1e-8) -> None:
+    check(_lib.load().ivhd_set_adam(ctx, 1 if enable else 0, lr, beta1, beta2, eps))
 
 
 def ivhd_get_adaptive(ctx) -> dict:
@@ -334,6 +339,11 @@ class Context:
     def adaptive(self) -> dict:
         """{"b", "kept", "rejected", "dT"} of the adaptive b."""
         return ivhd_get_adaptive(self.handle)
+
+    def set_adam(self, enable: bool = True, *, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+                 eps: float = 1e-8) -> None:
+        """Adam in place of the momentum update (see include/ivhd.h); V holds its first moments."""
+        ivhd_set_adam(self.handle, enable, lr, beta1, beta2, eps)
 
     def close(self) -> None:
         if self._h is not None:

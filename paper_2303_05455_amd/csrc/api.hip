@@ -74,6 +74,10 @@ struct ivhd_ctx {
   int adapt_on = 0;
   double tau = 0.0;
   float g1 = 1.f, g2 = 1.f;
+  float2 *s2 = nullptr;                  // Adam: second moments (v holds the first)
+  AdamState *adam = nullptr;             // Adam: step count and bias corrections
+  int adam_on = 0;
+  float lr = 0.f, beta1 = 0.9f, beta2 = 0.999f, eps_adam = 1e-8f;
   float2 *tmp = nullptr;          // [M] scratch (gradients in internal order)
   int parity = 0;                 // det mode: 0 -> Y_n in ya, 1 -> in yb
   Csc nn_csc, rn_csc;
@@ -114,7 +118,7 @@ void free_ctx(ivhd_ctx *c) {
   void *bufs[] = {c->perm, c->inv, c->nn_own, c->ya, c->yb, c->v, c->tmp, c->nn_csc.ptr, c->nn_csc.src,
                   c->rn_csc.ptr, c->rn_csc.src, c->sc.cnt, c->sc.tmp, c->sc.part, c->sc.big, c->rn_idx,
                   c->epoch, c->flags, c->fbuf, c->heavy, c->partials, c->d_E, c->ha, c->hb, c->vb,
-                  c->adapt, c->ke_part};
+                  c->adapt, c->ke_part, c->s2, c->adam};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (c->cap) (void)hipStreamDestroy(c->cap);
@@ -209,12 +213,22 @@ int enqueue_steps(ivhd_ctx *c, hipStream_t s, int64_t count, int *par) {
       float2 *dst = *par ? c->ya : c->yb;
       StepArgs a = step_args(c, src, dst);
       if (c->nest()) {
-        a.nesterov = 1;
+        a.opt = OPT_NEST;
         a.h = *par ? c->hb : c->ha;
         a.h_out = *par ? c->ha : c->hb;
       }
+      if (c->adam_on) {
+        a.opt = OPT_ADAM;
+        a.s2 = c->s2;
+        a.adam = c->adam;
+        a.lr = c->lr;
+        a.beta1 = c->beta1;
+        a.beta2 = c->beta2;
+        a.eps_adam = c->eps_adam;
+        HIPCHK(launch_adam_prep(c->adam, c->beta1, c->beta2, s));
+      }
       if (c->adapt_on) {
-        a.adapt = 1;
+        a.opt = OPT_ADAPT;
         a.v = *par ? c->vb : c->v;
         a.v_out = *par ? c->v : c->vb;
         a.b_dev = &c->adapt->b;
@@ -229,7 +243,7 @@ int enqueue_steps(ivhd_ctx *c, hipStream_t s, int64_t count, int *par) {
     } else {
       StepArgs a = step_args(c, c->ya, c->ya);
       if (c->nest()) {
-        a.nesterov = 1;
+        a.opt = OPT_NEST;
         a.h = c->ha;
         a.h_out = c->ha;
       }
@@ -621,6 +635,7 @@ int ivhd_set_adaptive(ivhd_ctx *c, int32_t enable, float b, double tau, float g1
   }
   if (!c->det()) return fail(IVHD_EINVAL, "the adaptive b needs IVHD_MODE_DET");
   if (c->nest()) return fail(IVHD_EINVAL, "the adaptive b is not combined with IVHD_FLAG_NESTEROV");
+  if (c->adam_on) return fail(IVHD_EINVAL, "the adaptive b is not combined with Adam");
   if (!std::isfinite(b) || !(b > 0.f)) return fail(IVHD_EINVAL, "b = %g must be > 0", (double)b);
   if (std::isnan(tau) || tau < 0.0) return fail(IVHD_EINVAL, "tau = %g must be >= 0", tau);
   if (!std::isfinite(g1) || !(g1 > 1.f)) return fail(IVHD_EINVAL, "g1 = %g must be > 1", (double)g1);
@@ -643,6 +658,43 @@ int ivhd_set_adaptive(ivhd_ctx *c, int32_t enable, float b, double tau, float g1
   c->tau = tau;
   c->g1 = g1;
   c->g2 = g2;
+  drop_graphs(c);
+  return IVHD_OK;
+}
+
+int ivhd_set_adam(ivhd_ctx *c, int32_t enable, float lr, float beta1, float beta2, float eps) {
+  if (!live(c)) return fail(IVHD_ESTATE, "invalid context");
+  if (!enable) {
+    if (c->adam_on) {
+      c->adam_on = 0;
+      drop_graphs(c);
+    }
+    return IVHD_OK;
+  }
+  if (!c->det()) return fail(IVHD_EINVAL, "Adam needs IVHD_MODE_DET");
+  if (c->nest()) return fail(IVHD_EINVAL, "Adam is not combined with IVHD_FLAG_NESTEROV");
+  if (c->adapt_on) return fail(IVHD_EINVAL, "Adam is not combined with the adaptive b");
+  if (!std::isfinite(lr) || !(lr > 0.f)) return fail(IVHD_EINVAL, "lr = %g must be > 0", (double)lr);
+  if (!std::isfinite(beta1) || beta1 < 0.f || !(beta1 < 1.f))
+    return fail(IVHD_EINVAL, "beta1 = %g outside [0, 1)", (double)beta1);
+  if (!std::isfinite(beta2) || beta2 < 0.f || !(beta2 < 1.f))
+    return fail(IVHD_EINVAL, "beta2 = %g outside [0, 1)", (double)beta2);
+  if (!std::isfinite(eps) || !(eps > 0.f)) return fail(IVHD_EINVAL, "eps = %g must be > 0", (double)eps);
+  const int64_t M = c->p.M;
+  int rc;
+  if (!c->s2 && (rc = dev_alloc(&c->s2, M, "second moments"))) return rc;
+  if (!c->adam && (rc = dev_alloc(&c->adam, 1, "Adam state"))) return rc;
+  // fresh moments: V (the first moments) and the second moments start at zero
+  HIPCHK(launch_fill_i32((int32_t *)c->v, 2 * M, 0, c->stream));
+  HIPCHK(launch_fill_i32((int32_t *)c->s2, 2 * M, 0, c->stream));
+  AdamState st{};
+  HIPCHK(hipMemcpyAsync(c->adam, &st, sizeof st, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));   // st lives on this stack frame
+  c->adam_on = 1;
+  c->lr = lr;
+  c->beta1 = beta1;
+  c->beta2 = beta2;
+  c->eps_adam = eps;
   drop_graphs(c);
   return IVHD_OK;
 }

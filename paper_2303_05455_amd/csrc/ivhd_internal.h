@@ -113,6 +113,15 @@ struct AdaptState {
   double dT;          // kinetic energy change of the last tentative step
 };
 
+// state of Adam on the loop: step count and bias corrections of this step
+struct AdamState {
+  int64_t t;
+  float c1, c2;       // 1 - beta1^t, 1 - beta2^t
+};
+
+// update rule of the deterministic step (template argument of its kernel)
+enum { OPT_PLAIN = 0, OPT_NEST = 1, OPT_ADAPT = 2, OPT_ADAM = 3 };
+
 struct StepArgs {
   const float2 *y;        // positions read (Y_n)
   const float2 *h;        // positions the forces are taken at: y, or H = Y + a V (nesterov)
@@ -122,7 +131,10 @@ struct StepArgs {
   float2 *v_out;          // adapt: tentative velocities
   const float *b_dev;     // adapt: b read from device memory
   double *ke_part;        // adapt: per-block sums of |v'|^2 - |v|^2 [det_grid]
-  int32_t l1, nesterov, adapt;
+  float2 *s2;             // adam: second moments (v holds the first moments)
+  const AdamState *adam;  // adam: bias corrections of this step
+  float lr, beta1, beta2, eps_adam;
+  int32_t l1, opt;        // opt: OPT_* (atomic mode: OPT_PLAIN or OPT_NEST)
   const int32_t *nn_idx;  // [M][nn]
   const int32_t *rn_idx;  // [M][rn]
   const int32_t *nn_ptr, *nn_src;   // CSC of nn edges
@@ -151,6 +163,8 @@ inline void set_launch_shape(StepArgs &a) {
 unsigned det_grid(const StepArgs &a);   // blocks of one deterministic launch
 hipError_t launch_step_det(const StepArgs &a, hipStream_t s);
 hipError_t launch_lookahead(const float2 *y, const float2 *v, float a, int64_t M, float2 *h, hipStream_t s);
+// t += 1 and the bias corrections of step t
+hipError_t launch_adam_prep(AdamState *st, float beta1, float beta2, hipStream_t s);
 hipError_t launch_adapt_decide(const double *part, int nparts, double tau, float g1, float g2, AdaptState *st,
                                hipStream_t s);
 // when st->reject: y_next = y, v_next = v

@@ -40,6 +40,11 @@
 //          tentative (V is written to a second buffer), b is read from
 //          device memory, and each block leaves the FP64 sum of
 //          |v'|^2 - |v|^2 over its vertices for the accept / reject decision.
+//   ADAM   Adam (Sec. "Optimization methods") on g = grad E = -2 f per
+//          coordinate; V holds the first moments, a second array the second
+//          moments, and the bias corrections of the step come from device
+//          memory (one tiny kernel per iteration advances them).
+// (NEST, ADAPT and ADAM are the values of one template argument, OPT.)
 #include "ivhd_internal.h"
 
 namespace ivhd {
@@ -151,18 +156,34 @@ __device__ __forceinline__ float2 heavy_force(const StepArgs &A, int64_t i, floa
   return make_float2(fx, fy);
 }
 
-// v' = a v + b f, y' = y + v'.  hi is the position the force was taken at
-// (y itself unless NEST).  Returns the vertex's |v'|^2 - |v|^2 in FP64 for
-// ADAPT (+inf when the tentative position is not finite, which forces a
-// rejection); the non-finite flag is raised only for steps that are final.
-template <bool NEST, bool ADAPT>
+// v' = a v + b f, y' = y + v' (Adam: its moment update instead).  hi is the
+// position the force was taken at (y itself unless OPT_NEST).  Returns the
+// vertex's |v'|^2 - |v|^2 in FP64 for OPT_ADAPT (+inf when the tentative
+// position is not finite, which forces a rejection); the non-finite flag is
+// raised only for steps that are final.
+template <int OPT>
 __device__ __forceinline__ double apply_update(const StepArgs &A, int64_t i, float2 hi, float2 f) {
+  constexpr bool NEST = OPT == OPT_NEST, ADAPT = OPT == OPT_ADAPT, ADAM = OPT == OPT_ADAM;
   const float2 yi = NEST ? A.y[i] : hi;
   const float2 v0 = A.v[i];
-  const float b = ADAPT ? *A.b_dev : A.b;
-  // explicit fused multiply-adds: every variant rounds the update identically
-  const float2 v = make_float2(fmaf(b, f.x, A.a * v0.x), fmaf(b, f.y, A.a * v0.y));
-  const float2 yn = make_float2(yi.x + v.x, yi.y + v.y);
+  float2 yn;
+  float2 v;
+  if (ADAM) {
+    const float gx = -2.f * f.x, gy = -2.f * f.y;
+    const float2 s0 = A.s2[i];
+    const float c1 = A.adam->c1, c2 = A.adam->c2;
+    v = make_float2(fmaf(A.beta1, v0.x, (1.f - A.beta1) * gx), fmaf(A.beta1, v0.y, (1.f - A.beta1) * gy));
+    const float2 s1 = make_float2(fmaf(A.beta2, s0.x, (1.f - A.beta2) * gx * gx),
+                                  fmaf(A.beta2, s0.y, (1.f - A.beta2) * gy * gy));
+    yn = make_float2(yi.x - A.lr * (v.x / c1) / (A.eps_adam + sqrtf(s1.x / c2)),
+                     yi.y - A.lr * (v.y / c1) / (A.eps_adam + sqrtf(s1.y / c2)));
+    A.s2[i] = s1;
+  } else {
+    const float b = ADAPT ? *A.b_dev : A.b;
+    // explicit fused multiply-adds: every variant rounds the update identically
+    v = make_float2(fmaf(b, f.x, A.a * v0.x), fmaf(b, f.y, A.a * v0.y));
+    yn = make_float2(yi.x + v.x, yi.y + v.y);
+  }
   A.y_out[i] = yn;
   if (ADAPT) {
     A.v_out[i] = v;
@@ -194,7 +215,7 @@ __device__ __forceinline__ void block_sum_store(double x, double *out) {
 // GRAD = true: out = s grad E = -2 s f with s = *gscale (1 when NULL), at
 // A.h = A.y; otherwise one iteration (force + update).  No thread leaves
 // before the ADAPT block sum.
-template <bool GRAD, bool L1, bool NEST, bool ADAPT>
+template <bool GRAD, bool L1, int OPT>
 __global__ void __launch_bounds__(kBlock) det_kernel(StepArgs A, float2 *out) {
   double ke = 0.0;
   if ((int32_t)blockIdx.x < A.heavy_blocks) {
@@ -209,7 +230,7 @@ __global__ void __launch_bounds__(kBlock) det_kernel(StepArgs A, float2 *out) {
           const float g = -2.f * (A.gscale ? *A.gscale : 1.f);
           out[i] = make_float2(g * f.x, g * f.y);
         } else {
-          ke = apply_update<NEST, ADAPT>(A, i, hi, f);
+          ke = apply_update<OPT>(A, i, hi, f);
         }
       }
     }
@@ -229,12 +250,12 @@ __global__ void __launch_bounds__(kBlock) det_kernel(StepArgs A, float2 *out) {
           const float g = -2.f * (A.gscale ? *A.gscale : 1.f);
           out[i] = make_float2(g * f.x, g * f.y);
         } else {
-          ke = apply_update<NEST, ADAPT>(A, i, hi, f);
+          ke = apply_update<OPT>(A, i, hi, f);
         }
       }
     }
   }
-  if (ADAPT) block_sum_store(ke, A.ke_part + blockIdx.x);
+  if (OPT == OPT_ADAPT) block_sum_store(ke, A.ke_part + blockIdx.x);
 }
 
 __global__ void heavy_list_kernel(const int32_t *__restrict__ nn_ptr, int64_t M, int32_t *list,
@@ -272,13 +293,13 @@ __global__ void __launch_bounds__(kBlock) scatter_force_kernel(StepArgs A) {
 }
 
 // update after the scatter pass; in place (y_out == y), H rewritten in place
-template <bool NEST>
+template <int OPT>
 __global__ void __launch_bounds__(kBlock) atomic_update_kernel(StepArgs A) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.M) return;
   const float2 f = A.fbuf[i];
   A.fbuf[i] = make_float2(0.f, 0.f);
-  (void)apply_update<NEST, false>(A, i, NEST ? make_float2(0.f, 0.f) : A.y[i], f);
+  (void)apply_update<OPT>(A, i, OPT == OPT_NEST ? make_float2(0.f, 0.f) : A.y[i], f);
 }
 
 __global__ void __launch_bounds__(kBlock) atomic_grad_out_kernel(float2 *fbuf, int64_t M, const float *gscale,
@@ -289,6 +310,13 @@ __global__ void __launch_bounds__(kBlock) atomic_grad_out_kernel(float2 *fbuf, i
   fbuf[i] = make_float2(0.f, 0.f);
   const float g = -2.f * (gscale ? *gscale : 1.f);
   out[i] = make_float2(g * f.x, g * f.y);
+}
+
+__global__ void adam_prep_kernel(AdamState *st, float beta1, float beta2) {
+  const int64_t t = st->t + 1;
+  st->t = t;
+  st->c1 = 1.f - powf(beta1, (float)t);
+  st->c2 = 1.f - powf(beta2, (float)t);
 }
 
 // H = Y + a V (the look-ahead positions of the Nesterov variant)
@@ -345,6 +373,11 @@ hipError_t launch_lookahead(const float2 *y, const float2 *v, float a, int64_t M
   return hipGetLastError();
 }
 
+hipError_t launch_adam_prep(AdamState *st, float beta1, float beta2, hipStream_t s) {
+  adam_prep_kernel<<<1, 1, 0, s>>>(st, beta1, beta2);
+  return hipGetLastError();
+}
+
 hipError_t launch_adapt_decide(const double *part, int nparts, double tau, float g1, float g2, AdaptState *st,
                                hipStream_t s) {
   adapt_decide_kernel<<<1, kBlock, 0, s>>>(part, nparts, tau, g1, g2, st);
@@ -365,32 +398,33 @@ hipError_t launch_heavy_list(const int32_t *nn_ptr, int64_t M, int32_t *list, in
   return hipGetLastError();
 }
 
-hipError_t launch_step_det(const StepArgs &a, hipStream_t s) {
-  const unsigned g = det_grid(a);
-  if (a.adapt) {
-    if (a.l1) det_kernel<false, true, false, true><<<g, kBlock, 0, s>>>(a, nullptr);
-    else det_kernel<false, false, false, true><<<g, kBlock, 0, s>>>(a, nullptr);
-  } else if (a.nesterov) {
-    if (a.l1) det_kernel<false, true, true, false><<<g, kBlock, 0, s>>>(a, nullptr);
-    else det_kernel<false, false, true, false><<<g, kBlock, 0, s>>>(a, nullptr);
-  } else {
-    if (a.l1) det_kernel<false, true, false, false><<<g, kBlock, 0, s>>>(a, nullptr);
-    else det_kernel<false, false, false, false><<<g, kBlock, 0, s>>>(a, nullptr);
+template <bool L1>
+void launch_det_opt(const StepArgs &a, unsigned g, hipStream_t s) {
+  switch (a.opt) {
+    case OPT_NEST: det_kernel<false, L1, OPT_NEST><<<g, kBlock, 0, s>>>(a, nullptr); break;
+    case OPT_ADAPT: det_kernel<false, L1, OPT_ADAPT><<<g, kBlock, 0, s>>>(a, nullptr); break;
+    case OPT_ADAM: det_kernel<false, L1, OPT_ADAM><<<g, kBlock, 0, s>>>(a, nullptr); break;
+    default: det_kernel<false, L1, OPT_PLAIN><<<g, kBlock, 0, s>>>(a, nullptr); break;
   }
+}
+
+hipError_t launch_step_det(const StepArgs &a, hipStream_t s) {
+  if (a.l1) launch_det_opt<true>(a, det_grid(a), s);
+  else launch_det_opt<false>(a, det_grid(a), s);
   return hipGetLastError();
 }
 
 hipError_t launch_step_atomic(const StepArgs &a, hipStream_t s) {
   if (a.l1) scatter_force_kernel<true><<<grid_for(a.M), kBlock, 0, s>>>(a);
   else scatter_force_kernel<false><<<grid_for(a.M), kBlock, 0, s>>>(a);
-  if (a.nesterov) atomic_update_kernel<true><<<grid_for(a.M), kBlock, 0, s>>>(a);
-  else atomic_update_kernel<false><<<grid_for(a.M), kBlock, 0, s>>>(a);
+  if (a.opt == OPT_NEST) atomic_update_kernel<OPT_NEST><<<grid_for(a.M), kBlock, 0, s>>>(a);
+  else atomic_update_kernel<OPT_PLAIN><<<grid_for(a.M), kBlock, 0, s>>>(a);
   return hipGetLastError();
 }
 
 hipError_t launch_grad_det(const StepArgs &a, float2 *out, hipStream_t s) {
-  if (a.l1) det_kernel<true, true, false, false><<<det_grid(a), kBlock, 0, s>>>(a, out);
-  else det_kernel<true, false, false, false><<<det_grid(a), kBlock, 0, s>>>(a, out);
+  if (a.l1) det_kernel<true, true, OPT_PLAIN><<<det_grid(a), kBlock, 0, s>>>(a, out);
+  else det_kernel<true, false, OPT_PLAIN><<<det_grid(a), kBlock, 0, s>>>(a, out);
   return hipGetLastError();
 }
 

@@ -104,6 +104,7 @@ def test_calls_on_a_missing_or_foreign_context_report_state(lib):
         assert lib.ivhd_get_order(ctx, FAKE) == -4
         assert lib.ivhd_set_adaptive(ctx, 1, 0.01, 1.0, 1.1, 0.5) == -4
         assert lib.ivhd_get_adaptive(ctx, None, None, None, None) == -4
+        assert lib.ivhd_set_adam(ctx, 1, 1e-3, 0.9, 0.999, 1e-8) == -4
     assert lib.ivhd_destroy(None) == 0
     assert lib.ivhd_destroy(bogus) == -4
     assert "invalid context" in lib.ivhd_last_error().decode()

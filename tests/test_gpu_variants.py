@@ -289,3 +289,74 @@ def test_rnn_mask_rejects_bad_indices(ivhd):
     helper = np.zeros((3, 2), np.int32)
     with pytest.raises(ivhd.IvhdError, match="outside"):
         ivhd.ivhd_rnn_mask(torch.from_numpy(nn_idx).cuda(), torch.from_numpy(helper).cuda())
+
+
+# ---- Adam on the loop ------------------------------------------------------
+
+@pytest.mark.parametrize("metric", ["l2", "l1"])
+@pytest.mark.parametrize("reorder", [True, False])
+@pytest.mark.parametrize("M,nn,rn,seed,extra", CASES[:4])
+def test_adam_steps_match_oracle(ivhd, metric, reorder, M, nn, rn, seed, extra):
+    lr, b1, b2, eps_a, c, eps = f32(1e-3), f32(0.9), f32(0.999), f32(1e-8), f32(0.1), f32(1e-12)
+    nn_idx, Y, V = _case(M, nn, rn, seed, **extra)
+    ctx = _ctx(ivhd, nn_idx, Y, V, rn=rn, c=c, eps=eps, seed=seed, reorder=reorder, metric=metric,
+               rn_resample_every=3)
+    ctx.set_adam(True, lr=lr, beta1=b1, beta2=b2, eps=eps_a)
+    ctx.step(1)
+    torch.cuda.synchronize()
+    Y1, m1, _, _ = oracle.run_adam(Y, nn_idx, rn=rn, lr=lr, c=c, b1=b1, b2=b2, eps_adam=eps_a, eps=eps,
+                                   seed=seed, R=3, T=1, metric=metric)
+    # Adam's first step moves every coordinate by about lr whatever its gradient:
+    # compare the displacement, relative to lr
+    assert np.max(np.abs((ctx.y.cpu().numpy() - Y) - (Y1 - Y))) <= 1e-3 * lr
+    assert _rel(ctx.v.cpu().numpy(), m1) <= 1e-5
+    ctx.step(6)
+    torch.cuda.synchronize()
+    Y7, m7, _, _ = oracle.run_adam(Y, nn_idx, rn=rn, lr=lr, c=c, b1=b1, b2=b2, eps_adam=eps_a, eps=eps,
+                                   seed=seed, R=3, T=7, metric=metric)
+    assert np.max(np.abs((ctx.y.cpu().numpy() - Y) - (Y7 - Y))) <= 1e-2 * lr
+    ctx.close()
+
+
+def test_adam_graphs_match_direct_launches_and_switch_back(ivhd):
+    nn_idx, Y, V = _case(4000, 3, 1, 19, hub=0.5)
+    outs = []
+    for graphs in (True, False):
+        ctx = _ctx(ivhd, nn_idx, Y, V, rn=1, b=1e-4, seed=4, rn_resample_every=7)
+        ctx.set_graphs(graphs)
+        ctx.step(3)
+        ctx.set_adam(True, lr=1e-3)
+        for n in (5, 30, 2, 130):
+            ctx.step(n)
+        ctx.set_adam(False)
+        ctx.step(9)
+        torch.cuda.synchronize()
+        outs.append((ctx.y.cpu().numpy(), ctx.v.cpu().numpy()))
+        ctx.close()
+    assert np.all(np.isfinite(outs[0][0]))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_adam_rejects_bad_use(ivhd):
+    nn_idx, Y, V = _case(500, 2, 1, 20)
+    ctx = _ctx(ivhd, nn_idx, Y, V, rn=1, mode="atomic")
+    with pytest.raises(ivhd.IvhdError, match="IVHD_MODE_DET"):
+        ctx.set_adam(True)
+    ctx.close()
+    ctx = _ctx(ivhd, nn_idx, Y, V, rn=1, nesterov=True)
+    with pytest.raises(ivhd.IvhdError, match="NESTEROV"):
+        ctx.set_adam(True)
+    ctx.close()
+    ctx = _ctx(ivhd, nn_idx, Y, V, rn=1)
+    for kw, frag in ((dict(lr=0.0), "lr"), (dict(beta1=1.0), "beta1"), (dict(beta2=-0.1), "beta2"),
+                     (dict(eps=0.0), "eps")):
+        with pytest.raises(ivhd.IvhdError, match=frag):
+            ctx.set_adam(True, **kw)
+    ctx.set_adaptive(True, tau=1.0)
+    with pytest.raises(ivhd.IvhdError, match="adaptive"):
+        ctx.set_adam(True)
+    ctx.set_adaptive(False)
+    ctx.set_adam(True)
+    with pytest.raises(ivhd.IvhdError, match="Adam"):
+        ctx.set_adaptive(True, tau=1.0)
+    ctx.close()
