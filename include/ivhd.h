@@ -256,6 +256,46 @@ int ivhd_grad_edges(const float *d_y, int64_t M, const int32_t *d_nn_idx, int32_
 int ivhd_knn_build(const float *d_x, int64_t M, int32_t N, int32_t k, int32_t *d_idx,
                    void *stream);
 
+/* ---- approximate kNN: an inverted file over a k-means coarse quantizer ----
+ * The thesis builds its kNN graphs with an approximate GPU library and
+ * finds that graph construction dominates the end-to-end time (Sec.
+ * "IVHD-CUDA").  This is the MI355X stand-in: points are grouped into nlist
+ * lists by their nearest centroid; a query scans only the points of its
+ * nprobe nearest lists (list-major: the queries probing a list are tiled
+ * against the list's points on the matrix cores, as in ivhd_knn_build), and
+ * the survivors are ranked by their exact FP32 distance.  nprobe = nlist - 1
+ * or more lists makes it exact in practice; the recall at lower nprobe
+ * depends on the data.                                                      */
+
+/* ivhd_ivf_train: centroids started at the points floor(c M / nlist), then
+ * n_iter Lloyd iterations (nearest centroid by squared distance, ties to
+ * the lower index; each centroid moves to the FP32 mean of its points,
+ * summed in id order; an empty list keeps its centroid), then the final
+ * assignment.
+ *   d_x          float32 [M][N] points (read only)
+ *   d_centroids  float32 [nlist][N] output
+ *   d_assign     int32 [M] output: the list of every point
+ * 2 <= nlist <= M, n_iter >= 0.  Synchronises the stream.                   */
+int ivhd_ivf_train(const float *d_x, int64_t M, int32_t N, int32_t nlist, int32_t n_iter,
+                   float *d_centroids, int32_t *d_assign, void *stream);
+
+/* ivhd_ivf_search: the k nearest points among the lists of the nprobe
+ * centroids nearest to each query (order: exact FP32 squared distance,
+ * ties to the lower index).
+ *   d_x, M, N              the indexed points; d_centroids [nlist][N] and
+ *                          d_assign [M] (entries in [0, nlist)) as from
+ *                          ivhd_ivf_train (or any caller-made index)
+ *   d_q [Q][N]             queries; d_self int32 [Q] or NULL: point
+ *                          d_self[q] is excluded for query q (-1 = none)
+ *   d_idx int32 [Q][k]     output (-1 where fewer than k points were probed);
+ *   d_dist float32 [Q][k]  squared distances, or NULL
+ * 1 <= k <= min(28, M-1), 1 <= nprobe <= min(28, nlist-1).  Allocates about
+ * (4 (M + Q) N_pad + 8 Q nprobe k) bytes of temporaries and synchronises
+ * the stream.                                                              */
+int ivhd_ivf_search(const float *d_x, int64_t M, int32_t N, const float *d_centroids, int32_t nlist,
+                    const int32_t *d_assign, const float *d_q, int64_t Q, const int32_t *d_self,
+                    int32_t k, int32_t nprobe, int32_t *d_idx, float *d_dist, void *stream);
+
 /* ivhd_rnn_mask: the reverse-neighbour pruning of Sec. "Reverse neighbors
  * mechanism".  An nn edge i -> j is kept when i is also among the kh
  * nearest neighbours of j in a wider helper graph (the thesis uses

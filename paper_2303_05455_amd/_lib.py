@@ -46,6 +46,8 @@ SIGNATURES = {
     "ivhd_get_adaptive": (i32, [vp, vp, vp, vp, vp]),
     "ivhd_set_adam": (i32, [vp, i32, f32, f32, f32, f32]),
     "ivhd_rnn_mask": (i32, [vp, i64, i32, vp, i32, vp, vp]),
+    "ivhd_ivf_train": (i32, [vp, i64, i32, i32, i32, vp, vp, vp]),
+    "ivhd_ivf_search": (i32, [vp, i64, i32, vp, i32, vp, vp, i64, vp, i32, i32, vp, vp, vp]),
     "ivhd_destroy": (i32, [vp]),
     "ivhd_edges_create": (i32, [ctypes.POINTER(vp), i64, vp, i32, vp, i32, vp]),
     "ivhd_edges_stress": (i32, [vp, vp, f32, vp]),

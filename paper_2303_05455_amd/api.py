@@ -23,7 +23,8 @@ __all__ = [
     "ivhd_get_iteration", "ivhd_set_graphs", "ivhd_destroy", "ivhd_last_error",
     "ivhd_version", "ivhd_knn_build", "ivhd_knn_query", "ivhd_edges_create", "ivhd_edges_stress",
     "ivhd_edges_grad", "ivhd_edges_destroy", "ivhd_grad_edges", "ivhd_set_adaptive",
-    "ivhd_get_adaptive", "ivhd_rnn_mask", "ivhd_set_adam",
+    "ivhd_get_adaptive", "ivhd_rnn_mask", "ivhd_set_adam", "ivhd_ivf_train", "ivhd_ivf_search",
+    "ivf_knn_graph",
 ]
 
 
@@ -247,6 +248,45 @@ def ivhd_knn_query(x: torch.Tensor, q: torch.Tensor, k: int, self_idx: Optional[
                                      dist.data_ptr() if dist is not None else None,
                                      _stream_handle(stream)))
     return (idx, dist) if with_dist else idx
+
+
+def ivhd_ivf_train(x: torch.Tensor, nlist: int, n_iter: int = 10,
+                   stream: Optional[torch.cuda.Stream] = None):
+    """k-means coarse quantizer of x (float32 [M, N]): (centroids [nlist, N], assign int32 [M])."""
+    M, N = x.shape
+    _dev(x, torch.float32, (M, N), "x")
+    C = torch.empty((nlist, N), dtype=torch.float32, device=x.device)
+    a = torch.empty(M, dtype=torch.int32, device=x.device)
+    check(_lib.load().ivhd_ivf_train(x.data_ptr(), M, N, nlist, n_iter, C.data_ptr(), a.data_ptr(),
+                                     _stream_handle(stream)))
+    return C, a
+
+
+def ivhd_ivf_search(x: torch.Tensor, centroids: torch.Tensor, assign: torch.Tensor, q: torch.Tensor, k: int,
+                    nprobe: int, self_idx: Optional[torch.Tensor] = None, with_dist: bool = False,
+                    stream: Optional[torch.cuda.Stream] = None):
+    """Approximate k nearest rows of x to each row of q over the nprobe nearest lists."""
+    M, N = x.shape
+    nlist = centroids.shape[0]
+    Q = q.shape[0]
+    _dev(x, torch.float32, (M, N), "x")
+    _dev(centroids, torch.float32, (nlist, N), "centroids")
+    _dev(assign, torch.int32, (M,), "assign")
+    _dev(q, torch.float32, (Q, N), "q")
+    p_self = _dev(self_idx, torch.int32, (Q,), "self_idx") if self_idx is not None else None
+    idx = torch.empty((Q, k), dtype=torch.int32, device=x.device)
+    dist = torch.empty((Q, k), dtype=torch.float32, device=x.device) if with_dist else None
+    check(_lib.load().ivhd_ivf_search(x.data_ptr(), M, N, centroids.data_ptr(), nlist, assign.data_ptr(),
+                                      q.data_ptr(), Q, p_self, k, nprobe, idx.data_ptr(),
+                                      dist.data_ptr() if dist is not None else None, _stream_handle(stream)))
+    return (idx, dist) if with_dist else idx
+
+
+def ivf_knn_graph(x: torch.Tensor, k: int, nlist: int, nprobe: int, n_iter: int = 10) -> torch.Tensor:
+    """Approximate kNN graph of the rows of x (each row excluded from its own list): int32 [M, k]."""
+    C, a = ivhd_ivf_train(x, nlist, n_iter)
+    self_idx = torch.arange(x.shape[0], dtype=torch.int32, device=x.device)
+    return ivhd_ivf_search(x, C, a, x, k, nprobe, self_idx=self_idx)
 
 
 def ivhd_last_error() -> str:

@@ -149,6 +149,14 @@ __global__ void gather_f2_kernel(const float2 *__restrict__ src, const int32_t *
   if (p < M) dst[p] = src[idx ? (int64_t)idx[p] : p];
 }
 
+// flags[FLAG_BAD_INDEX] = 1 if an entry is outside [0, hi)
+__global__ void range_check_kernel(const int32_t *__restrict__ idx, int64_t n, int32_t hi, int32_t *flags) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int32_t j = idx[e];
+  if (j < 0 || j >= hi) flags[FLAG_BAD_INDEX] = 1;
+}
+
 // reverse-neighbour mask: nn edge i -> j kept when i is among the kh helper
 // neighbours of j, else -1 (absent slots stay absent)
 __global__ void rnn_mask_kernel(const int32_t *nn_idx, int64_t M, int nn, const int32_t *__restrict__ helper,
@@ -393,6 +401,26 @@ hipError_t launch_scan(int32_t *cnt, int64_t M, int32_t *part, int32_t *ptr, hip
   scan_partials_kernel<<<(unsigned)nb, kBlock, 0, s>>>(cnt, M, part);
   scan_top_kernel<<<1, kBlock, 0, s>>>(part, nb);
   scan_final_kernel<<<(unsigned)nb, kBlock, 0, s>>>(cnt, M, part, nb, ptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_range_check(const int32_t *idx, int64_t n, int32_t hi, int32_t *flags, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  range_check_kernel<<<grid_for(n), kBlock, 0, s>>>(idx, n, hi, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose(const int32_t *idx, int64_t rows, int k, int64_t ntargets, int32_t *ptr, int32_t *cnt,
+                            int32_t *part, int32_t *tmp, int32_t *big, int32_t *flags, int32_t *src_out,
+                            hipStream_t s) {
+  fill_i32_kernel<<<grid_for(ntargets + 1), kBlock, 0, s>>>(cnt, ntargets + 1, 0);
+  fill_i32_kernel<<<1, kBlock, 0, s>>>(flags + FLAG_BIG_COUNT, 1, 0);
+  count_kernel<<<grid_for(rows * k), kBlock, 0, s>>>(idx, rows, k, cnt);
+  hipError_t e = launch_scan(cnt, ntargets, part, ptr, s);
+  if (e != hipSuccess) return e;
+  scatter_kernel<<<grid_for(rows * k), kBlock, 0, s>>>(idx, rows, k, cnt, tmp);
+  sort_small_kernel<<<grid_for(ntargets), kBlock, 0, s>>>(ptr, tmp, ntargets, big, flags, src_out);
+  sort_big_kernel<<<kBigSortBlocks, kBlock, 0, s>>>(ptr, tmp, big, flags, src_out);
   return hipGetLastError();
 }
 

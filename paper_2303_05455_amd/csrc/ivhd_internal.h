@@ -94,6 +94,14 @@ hipError_t launch_rnn_mask(const int32_t *nn_idx, int64_t M, int nn, const int32
 hipError_t launch_count(const int32_t *idx, int64_t M, int k, int32_t *cnt, hipStream_t s);
 // From counts cnt[0..M-1]: ptr = exclusive scan (ptr[M] = total), cnt = cursor copy.
 hipError_t launch_scan(int32_t *cnt, int64_t M, int32_t *part, int32_t *ptr, hipStream_t s);
+// flags[FLAG_BAD_INDEX] = 1 if an entry of idx[0..n) is outside [0, hi)
+hipError_t launch_range_check(const int32_t *idx, int64_t n, int32_t hi, int32_t *flags, hipStream_t s);
+// Transpose of rows x k lists with targets in [0, ntargets) (entries < 0 skipped): ptr [ntargets+1],
+// src_out [rows*k] (per target the source rows ascending).  Scratch: cnt [ntargets+1], part
+// [ntargets / kScanChunk + 2], tmp [rows*k], big [ntargets].
+hipError_t launch_transpose(const int32_t *idx, int64_t rows, int k, int64_t ntargets, int32_t *ptr, int32_t *cnt,
+                            int32_t *part, int32_t *tmp, int32_t *big, int32_t *flags, int32_t *src_out,
+                            hipStream_t s);
 // Scatter + canonical sort: csc.src segments end sorted ascending.
 hipError_t launch_scatter_sort(const int32_t *idx, int64_t M, int k, const int32_t *ptr,
                                int32_t *cursor, int32_t *tmp, int32_t *big, int32_t *flags,
@@ -206,5 +214,23 @@ hipError_t launch_knn(const float *X, int64_t M, int N, const float *Q, int64_t 
                       const _Float16 *Xl, const _Float16 *Qh, const _Float16 *Ql, int Np, float scale,
                       int self_mode, const int32_t *self, const float *cnorm, int k, int32_t *idx, float *dist,
                       hipStream_t s);
+
+// inverted-file search (knn.hip): split rows gathered in list order
+hipError_t launch_gather_f32(const float *src, const int32_t *idx, int64_t n, float *dst, hipStream_t s);
+hipError_t launch_split_gather(const float *X, int64_t M, int N, int Np, float scale, const int32_t *pos_id,
+                               _Float16 *hi, _Float16 *lo, hipStream_t s);
+// one block per work item (list work_list[b], chunk work_chunk[b] of its probing queries); each
+// query's top k of the list goes to part_[idx|dist][(q * nprobe + slot) * k]
+hipError_t launch_ivf_lists(const float *X, int N, const float *Q, const _Float16 *Xh, const _Float16 *Xl,
+                            const _Float16 *Qh, const _Float16 *Ql, int Np, float scale, const float *pnorm,
+                            const int32_t *pos_id, const int32_t *lptr, const int32_t *pptr, const int32_t *pq,
+                            const int32_t *work_list, const int32_t *work_chunk, int64_t n_work,
+                            const int32_t *probes, int nprobe, const int32_t *self, int k, int32_t *part_idx,
+                            float *part_dist, hipStream_t s);
+hipError_t launch_ivf_merge(const int32_t *part_idx, const float *part_dist, int64_t nq, int nprobe, int k,
+                            int32_t *idx, float *dist, hipStream_t s);
+hipError_t launch_init_centroids(const float *X, int64_t M, int N, int nlist, float *C, hipStream_t s);
+hipError_t launch_centroid_mean(const float *X, int N, const int32_t *lptr, const int32_t *pos_id, int nlist,
+                                float *C, hipStream_t s);
 
 }  // namespace ivhd

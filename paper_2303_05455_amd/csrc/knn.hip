@@ -268,6 +268,269 @@ knn_kernel(const float *__restrict__ X, int64_t M, int N, const float *__restric
   }
 }
 
+// ---- inverted-file (approximate) search ------------------------------------
+// The index: nlist centroids and the points' list assignment.  The points are
+// reordered by list (sorted position p holds point pos_id[p]; list c is
+// positions [lptr[c], lptr[c+1])), split into hi / lo FP16 rows in that
+// order.  The work is list-major: each block takes up to 128 of the queries
+// that probe one list (query ids pq[qbeg..qend)) and sweeps that list's
+// points with the same MFMA tiles, score tile and top-KP lists as the exact
+// kernel, then re-ranks its survivors exactly and writes them to the query's
+// probe slot.  A merge kernel then takes each query's best k over its slots.
+
+__global__ void gather_f32_kernel(const float *__restrict__ src, const int32_t *__restrict__ idx, int64_t n,
+                                  float *__restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) dst[e] = src[idx[e]];
+}
+
+// rows of the split arrays in list order
+__global__ void split_gather_kernel(const float *__restrict__ X, int64_t M, int N, int Np, float scale,
+                                    const int32_t *__restrict__ pos_id, _Float16 *__restrict__ hi,
+                                    _Float16 *__restrict__ lo) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * Np) return;
+  const int64_t p = e / Np;
+  const int c = (int)(e % Np);
+  const float x = c < N ? X[(int64_t)pos_id[p] * N + c] * scale : 0.f;
+  const _Float16 h = (_Float16)x;
+  hi[e] = h;
+  lo[e] = (_Float16)(x - (float)h);
+}
+
+// like stage_rows, with row r taken from rows_of[r0 + r] (r0 + r < n)
+template <int ROWS>
+__device__ __forceinline__ void stage_rows_indexed(_Float16 *__restrict__ lds, const _Float16 *__restrict__ P,
+                                                   const int32_t *__restrict__ rows_of, int64_t n, int Np,
+                                                   int64_t r0, int k0) {
+  constexpr int kChunks = ROWS * (TKK / 8);
+#pragma unroll
+  for (int c = 0; c < (kChunks + kKnnThreads - 1) / kKnnThreads; ++c) {
+    const int id = threadIdx.x + kKnnThreads * c;
+    if (kChunks % kKnnThreads == 0 || id < kChunks) {
+      const int r = id >> 2, kc = (id & 3) * 8;
+      halfx8 v = {};
+      if (r0 + r < n) v = *reinterpret_cast<const halfx8 *>(P + (int64_t)rows_of[r0 + r] * Np + k0 + kc);
+      *reinterpret_cast<halfx8 *>(lds + r * HP + kc) = v;
+    }
+  }
+}
+
+// contiguous rows [r0, r0 + ROWS) of P, valid while < rend
+template <int ROWS>
+__device__ __forceinline__ void stage_rows_range(_Float16 *__restrict__ lds, const _Float16 *__restrict__ P,
+                                                 int64_t rend, int Np, int64_t r0, int k0) {
+  constexpr int kChunks = ROWS * (TKK / 8);
+#pragma unroll
+  for (int c = 0; c < (kChunks + kKnnThreads - 1) / kKnnThreads; ++c) {
+    const int id = threadIdx.x + kKnnThreads * c;
+    if (kChunks % kKnnThreads == 0 || id < kChunks) {
+      const int r = id >> 2, kc = (id & 3) * 8;
+      halfx8 v = {};
+      if (r0 + r < rend) v = *reinterpret_cast<const halfx8 *>(P + (r0 + r) * Np + k0 + kc);
+      *reinterpret_cast<halfx8 *>(lds + r * HP + kc) = v;
+    }
+  }
+}
+
+template <int KP>
+__global__ void __launch_bounds__(kKnnThreads)
+ivf_list_kernel(const float *__restrict__ X, int N, const float *__restrict__ Q, const _Float16 *__restrict__ Xh,
+                const _Float16 *__restrict__ Xl, const _Float16 *__restrict__ Qh, const _Float16 *__restrict__ Ql,
+                int Np, float inv_scale2, const float *__restrict__ pnorm, const int32_t *__restrict__ pos_id,
+                const int32_t *__restrict__ lptr, const int32_t *__restrict__ pptr, const int32_t *__restrict__ pq,
+                const int32_t *__restrict__ work_list, const int32_t *__restrict__ work_chunk,
+                const int32_t *__restrict__ probes, int nprobe, const int32_t *__restrict__ self, int k,
+                int32_t *__restrict__ part_idx, float *__restrict__ part_dist) {
+  __shared__ __attribute__((aligned(16))) float smem[QB * SP];
+  _Float16 *sQh = reinterpret_cast<_Float16 *>(smem);
+  _Float16 *sQl = sQh + QB * HP;
+  _Float16 *sCh = sQl + QB * HP;
+  _Float16 *sCl = sCh + CB * HP;
+  float *sS = smem;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int32_t c = work_list[blockIdx.x];
+  const int64_t qbeg = (int64_t)pptr[c] + (int64_t)work_chunk[blockIdx.x] * QB;
+  const int64_t qend = pptr[c + 1];
+  const int64_t pbeg = lptr[c], pend = lptr[c + 1];
+
+  const int my_row = tid >> 1;
+  const int half = tid & 1;
+  const bool have_q = qbeg + my_row < qend;
+  const int32_t my_q = have_q ? pq[qbeg + my_row] : -1;
+  const int32_t my_self = have_q && self ? self[my_q] : -1;
+
+  float ks[KP];
+  int32_t ki[KP];
+#pragma unroll
+  for (int p = 0; p < KP; ++p) { ks[p] = FLT_MAX; ki[p] = INT32_MAX; }
+
+  const int kq = (lane >> 4) * 8;
+  for (int64_t c0 = pbeg; c0 < pend; c0 += CB) {
+    floatx4 acc[2][4];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < Np; k0 += TKK) {
+      __syncthreads();
+      stage_rows_indexed<QB>(sQh, Qh, pq, qend, Np, qbeg, k0);
+      stage_rows_indexed<QB>(sQl, Ql, pq, qend, Np, qbeg, k0);
+      stage_rows_range<CB>(sCh, Xh, pend, Np, c0, k0);
+      stage_rows_range<CB>(sCl, Xl, pend, Np, c0, k0);
+      __syncthreads();
+      halfx8 ah[2], al[2], bh[4], bl[4];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        const int r = 32 * wave + 16 * rb + (lane & 15);
+        ah[rb] = *reinterpret_cast<const halfx8 *>(sQh + r * HP + kq);
+        al[rb] = *reinterpret_cast<const halfx8 *>(sQl + r * HP + kq);
+      }
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        const int r = 16 * cb + (lane & 15);
+        bh[cb] = *reinterpret_cast<const halfx8 *>(sCh + r * HP + kq);
+        bl[cb] = *reinterpret_cast<const halfx8 *>(sCl + r * HP + kq);
+      }
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[rb], bh[cb], acc[rb][cb], 0, 0, 0);
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[rb], bl[cb], acc[rb][cb], 0, 0, 0);
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[rb], bh[cb], acc[rb][cb], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      const int col = 16 * cb + (lane & 15);
+      const float cn = c0 + col < pend ? pnorm[c0 + col] : 0.f;
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 32 * wave + 16 * rb + 4 * (lane >> 4) + r;
+          sS[row * SP + col] = cn - 2.f * (acc[rb][cb][r] * inv_scale2);
+        }
+    }
+    __syncthreads();
+    if (have_q) {
+      for (int m = 0; m < CB / 2; ++m) {
+        const int col = 2 * m + half;
+        if (c0 + col >= pend) continue;
+        const int32_t id = pos_id[c0 + col];
+        if (id == my_self) continue;
+        list_insert<KP>(ks, ki, sS[my_row * SP + col], id);
+      }
+    }
+  }
+
+  __syncthreads();
+  float *mS = sS;
+  int32_t *mI = (int32_t *)(sS + QB * KP);
+  if (half == 1) {
+#pragma unroll
+    for (int p = 0; p < KP; ++p) { mS[my_row * KP + p] = ks[p]; mI[my_row * KP + p] = ki[p]; }
+  }
+  __syncthreads();
+  if (half == 0 && have_q) {
+#pragma unroll
+    for (int p = 0; p < KP; ++p) list_insert<KP>(ks, ki, mS[my_row * KP + p], mI[my_row * KP + p]);
+    float *rs = mS + my_row * KP;
+    int32_t *ri = mI + my_row * KP;
+    const float *qrow = Q + (int64_t)my_q * N;
+#pragma unroll
+    for (int p = 0; p < KP; ++p) ri[p] = ki[p];
+#pragma unroll 1
+    for (int p = 0; p < KP; ++p) {
+      const int32_t id = ri[p];
+      float d = FLT_MAX;
+      if (id != INT32_MAX) {
+        const float *xr = X + (int64_t)id * N;
+        d = 0.f;
+        for (int kk = 0; kk < N; ++kk) {
+          const float t = qrow[kk] - xr[kk];
+          d += t * t;
+        }
+      }
+      int q = p;
+      while (q > 0 && pair_less(d, id, rs[q - 1], ri[q - 1])) {
+        rs[q] = rs[q - 1];
+        ri[q] = ri[q - 1];
+        --q;
+      }
+      rs[q] = d;
+      ri[q] = id;
+    }
+    // this list's probe slot of the query
+    int slot = 0;
+    for (int p = 0; p < nprobe; ++p)
+      if (probes[(int64_t)my_q * nprobe + p] == c) slot = p;
+    int32_t *oi = part_idx + ((int64_t)my_q * nprobe + slot) * k;
+    float *od = part_dist + ((int64_t)my_q * nprobe + slot) * k;
+#pragma unroll 1
+    for (int p = 0; p < k; ++p) {
+      oi[p] = ri[p] == INT32_MAX ? -1 : ri[p];
+      od[p] = ri[p] == INT32_MAX ? FLT_MAX : rs[p];
+    }
+  }
+}
+
+// each query's k best over its nprobe sorted slots (slots of lists it did not
+// probe twice stay at -1 / FLT_MAX from the fill)
+__global__ void ivf_merge_kernel(const int32_t *__restrict__ part_idx, const float *__restrict__ part_dist,
+                                 int64_t nq, int nprobe, int k, int32_t *__restrict__ out_idx,
+                                 float *__restrict__ out_dist) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  int head[32];
+  for (int p = 0; p < nprobe; ++p) head[p] = 0;
+  const int32_t *pi = part_idx + q * nprobe * k;
+  const float *pd = part_dist + q * nprobe * k;
+  for (int r = 0; r < k; ++r) {
+    int best = -1;
+    float bd = FLT_MAX;
+    int32_t bi = INT32_MAX;
+    for (int p = 0; p < nprobe; ++p) {
+      if (head[p] >= k) continue;
+      const int32_t i = pi[p * k + head[p]];
+      if (i < 0) continue;
+      const float d = pd[p * k + head[p]];
+      if (pair_less(d, i, bd, bi)) { bd = d; bi = i; best = p; }
+    }
+    if (best >= 0) head[best] += 1;
+    out_idx[q * k + r] = best >= 0 ? bi : -1;
+    if (out_dist) out_dist[q * k + r] = best >= 0 ? bd : FLT_MAX;
+  }
+}
+
+__global__ void init_centroids_kernel(const float *__restrict__ X, int64_t M, int N, int nlist, float *__restrict__ C) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)nlist * N) return;
+  const int64_t c = e / N;
+  const int d = (int)(e % N);
+  C[e] = X[(c * M / nlist) * N + d];
+}
+
+// centroid c <- mean of the points of list c, summed in list order (ids
+// ascending); an empty list keeps its centroid
+__global__ void centroid_mean_kernel(const float *__restrict__ X, int N, const int32_t *__restrict__ lptr,
+                                     const int32_t *__restrict__ pos_id, float *__restrict__ C) {
+  const int c = blockIdx.x;
+  const int32_t b = lptr[c], e = lptr[c + 1];
+  if (e == b) return;
+  const float inv = 1.f / (float)(e - b);
+  for (int d = threadIdx.x; d < N; d += blockDim.x) {
+    float s = 0.f;
+    for (int32_t p = b; p < e; ++p) s += X[(int64_t)pos_id[p] * N + d];
+    C[(int64_t)c * N + d] = s * inv;
+  }
+}
+
 template <int KP>
 hipError_t launch_knn_kp(const float *X, int64_t M, int N, const float *Q, int64_t nq, const _Float16 *Xh,
                          const _Float16 *Xl, const _Float16 *Qh, const _Float16 *Ql, int Np, float inv_scale2,
@@ -324,6 +587,52 @@ hipError_t launch_knn(const float *X, int64_t M, int N, const float *Q, int64_t 
   if (k + 4 <= 16)
     return launch_knn_kp<16>(X, M, N, Q, nq, Xh, Xl, Qh, Ql, Np, inv2, self_mode, self, cnorm, k, idx, dist, s);
   return launch_knn_kp<32>(X, M, N, Q, nq, Xh, Xl, Qh, Ql, Np, inv2, self_mode, self, cnorm, k, idx, dist, s);
+}
+
+hipError_t launch_gather_f32(const float *src, const int32_t *idx, int64_t n, float *dst, hipStream_t s) {
+  gather_f32_kernel<<<grid_for(n), kBlock, 0, s>>>(src, idx, n, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_gather(const float *X, int64_t M, int N, int Np, float scale, const int32_t *pos_id,
+                               _Float16 *hi, _Float16 *lo, hipStream_t s) {
+  split_gather_kernel<<<grid_for(M * Np), kBlock, 0, s>>>(X, M, N, Np, scale, pos_id, hi, lo);
+  return hipGetLastError();
+}
+
+hipError_t launch_ivf_lists(const float *X, int N, const float *Q, const _Float16 *Xh, const _Float16 *Xl,
+                            const _Float16 *Qh, const _Float16 *Ql, int Np, float scale, const float *pnorm,
+                            const int32_t *pos_id, const int32_t *lptr, const int32_t *pptr, const int32_t *pq,
+                            const int32_t *work_list, const int32_t *work_chunk, int64_t n_work,
+                            const int32_t *probes, int nprobe, const int32_t *self, int k, int32_t *part_idx,
+                            float *part_dist, hipStream_t s) {
+  if (n_work == 0) return hipSuccess;
+  const float inv2 = 1.f / (scale * scale);
+  const unsigned g = (unsigned)n_work;
+#define IVHD_IVF_ARGS X, N, Q, Xh, Xl, Qh, Ql, Np, inv2, pnorm, pos_id, lptr, pptr, pq, work_list, work_chunk, \
+                      probes, nprobe, self, k, part_idx, part_dist
+  if (k + 4 <= 8) ivf_list_kernel<8><<<g, kKnnThreads, 0, s>>>(IVHD_IVF_ARGS);
+  else if (k + 4 <= 16) ivf_list_kernel<16><<<g, kKnnThreads, 0, s>>>(IVHD_IVF_ARGS);
+  else ivf_list_kernel<32><<<g, kKnnThreads, 0, s>>>(IVHD_IVF_ARGS);
+#undef IVHD_IVF_ARGS
+  return hipGetLastError();
+}
+
+hipError_t launch_ivf_merge(const int32_t *part_idx, const float *part_dist, int64_t nq, int nprobe, int k,
+                            int32_t *idx, float *dist, hipStream_t s) {
+  ivf_merge_kernel<<<grid_for(nq), kBlock, 0, s>>>(part_idx, part_dist, nq, nprobe, k, idx, dist);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_centroids(const float *X, int64_t M, int N, int nlist, float *C, hipStream_t s) {
+  init_centroids_kernel<<<grid_for((int64_t)nlist * N), kBlock, 0, s>>>(X, M, N, nlist, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_centroid_mean(const float *X, int N, const int32_t *lptr, const int32_t *pos_id, int nlist,
+                                float *C, hipStream_t s) {
+  centroid_mean_kernel<<<(unsigned)nlist, kBlock, 0, s>>>(X, N, lptr, pos_id, C);
+  return hipGetLastError();
 }
 
 }  // namespace ivhd

@@ -4,6 +4,7 @@
 #include <mutex>
 #include <new>
 #include <unordered_set>
+#include <vector>
 
 #include <cstring>
 
@@ -294,6 +295,161 @@ int ivhd_knn_build(const float *d_x, int64_t M, int32_t N, int32_t k, int32_t *d
 int ivhd_knn_query(const float *d_x, int64_t M, int32_t N, const float *d_q, int64_t Q,
                    const int32_t *d_self, int32_t k, int32_t *d_idx, float *d_dist, void *stream) {
   return knn_common(d_x, M, N, d_q, Q, d_self ? 2 : 0, d_self, k, d_idx, d_dist, stream);
+}
+
+}  // extern "C"
+
+namespace ivhd {
+namespace {
+
+// device buffers released together
+struct Scratch {
+  std::vector<void *> bufs;
+  ~Scratch() {
+    for (void *b : bufs)
+      if (b) (void)hipFree(b);
+  }
+  template <typename T>
+  int get(T **p, size_t n, const char *what) {
+    int rc = dev_alloc(p, n, what);
+    if (!rc) bufs.push_back(*p);
+    return rc;
+  }
+};
+
+// per-target lists of a rows x k index array (targets in [0, ntargets)):
+// ptr [ntargets+1], src [rows*k]
+int transpose_lists(Scratch &S, const int32_t *idx, int64_t rows, int k, int64_t ntargets, int32_t **ptr,
+                    int32_t **src, int32_t *flags, hipStream_t s) {
+  int32_t *cnt, *part, *tmp, *big;
+  int rc;
+  if ((rc = S.get(ptr, ntargets + 1, "list offsets")) || (rc = S.get(src, rows * k, "list members")) ||
+      (rc = S.get(&cnt, ntargets + 1, "list counts")) ||
+      (rc = S.get(&part, ntargets / kScanChunk + 2, "scan partials")) ||
+      (rc = S.get(&tmp, rows * k, "scatter buffer")) || (rc = S.get(&big, ntargets, "large-list list")))
+    return rc;
+  HIPCHK(launch_transpose(idx, rows, k, ntargets, *ptr, cnt, part, tmp, big, flags, *src, s));
+  return IVHD_OK;
+}
+
+int check_range(const int32_t *idx, int64_t n, int32_t hi, int32_t *flags, hipStream_t s, const char *what) {
+  int32_t h[FLAG_SLOTS] = {0};
+  HIPCHK(launch_fill_i32(flags, FLAG_SLOTS, 0, s));
+  HIPCHK(launch_range_check(idx, n, hi, flags, s));
+  HIPCHK(hipMemcpyAsync(h, flags, sizeof h, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (h[FLAG_BAD_INDEX]) return fail(IVHD_EINVAL, "%s holds an entry outside [0, %d)", what, hi);
+  return IVHD_OK;
+}
+
+}  // namespace
+}  // namespace ivhd
+
+extern "C" {
+
+int ivhd_ivf_train(const float *d_x, int64_t M, int32_t N, int32_t nlist, int32_t n_iter, float *d_centroids,
+                   int32_t *d_assign, void *stream) {
+  clear_error();
+  if (!d_x || !d_centroids || !d_assign) return fail(IVHD_EINVAL, "d_x, d_centroids and d_assign must not be NULL");
+  if (M < 2 || M > (int64_t)INT32_MAX - 1) return fail(IVHD_EINVAL, "M = %lld outside [2, 2^31-2]", (long long)M);
+  if (N < 1) return fail(IVHD_EINVAL, "N = %d must be >= 1", N);
+  if (nlist < 2 || nlist > M) return fail(IVHD_EINVAL, "nlist = %d outside [2, M]", nlist);
+  if (n_iter < 0) return fail(IVHD_EINVAL, "n_iter = %d < 0", n_iter);
+  hipStream_t s = (hipStream_t)stream;
+  Scratch S;
+  int32_t *flags;
+  int rc = S.get(&flags, FLAG_SLOTS, "device flags");
+  if (rc) return rc;
+  HIPCHK(launch_init_centroids(d_x, M, N, nlist, d_centroids, s));
+  for (int it = 0; it <= n_iter; ++it) {
+    if ((rc = ivhd_knn_query(d_centroids, nlist, N, d_x, M, nullptr, 1, d_assign, nullptr, stream))) return rc;
+    if (it == n_iter) break;
+    Scratch L;
+    int32_t *lptr, *pos_id;
+    if ((rc = transpose_lists(L, d_assign, M, 1, nlist, &lptr, &pos_id, flags, s))) return rc;
+    HIPCHK(launch_centroid_mean(d_x, N, lptr, pos_id, nlist, d_centroids, s));
+    HIPCHK(hipStreamSynchronize(s));   // before L frees the lists
+  }
+  return IVHD_OK;
+}
+
+int ivhd_ivf_search(const float *d_x, int64_t M, int32_t N, const float *d_centroids, int32_t nlist,
+                    const int32_t *d_assign, const float *d_q, int64_t Q, const int32_t *d_self, int32_t k,
+                    int32_t nprobe, int32_t *d_idx, float *d_dist, void *stream) {
+  clear_error();
+  if (!d_x || !d_centroids || !d_assign || !d_q || !d_idx) return fail(IVHD_EINVAL, "a required pointer is NULL");
+  if (M < 2 || M > (int64_t)INT32_MAX - 1) return fail(IVHD_EINVAL, "M = %lld outside [2, 2^31-2]", (long long)M);
+  if (N < 1) return fail(IVHD_EINVAL, "N = %d must be >= 1", N);
+  if (nlist < 2 || nlist > M) return fail(IVHD_EINVAL, "nlist = %d outside [2, M]", nlist);
+  if (Q < 0 || Q > (int64_t)INT32_MAX - 1) return fail(IVHD_EINVAL, "Q = %lld outside [0, 2^31-2]", (long long)Q);
+  const int32_t kmax = knn_max_k() < M - 1 ? knn_max_k() : (int32_t)(M - 1);
+  if (k < 1 || k > kmax) return fail(IVHD_EINVAL, "k = %d outside [1, %d]", k, kmax);
+  const int32_t pmax = knn_max_k() < nlist - 1 ? knn_max_k() : nlist - 1;
+  if (nprobe < 1 || nprobe > pmax) return fail(IVHD_EINVAL, "nprobe = %d outside [1, %d]", nprobe, pmax);
+  if (Q * (int64_t)nprobe > (int64_t)INT32_MAX) return fail(IVHD_EINVAL, "Q * nprobe exceeds 2^31-1");
+  if (Q == 0) return IVHD_OK;
+  hipStream_t s = (hipStream_t)stream;
+  Scratch S;
+  int32_t *flags;
+  int rc = S.get(&flags, FLAG_SLOTS, "device flags");
+  if (rc) return rc;
+  if ((rc = check_range(d_assign, M, nlist, flags, s, "d_assign"))) return rc;
+  // probes: the nprobe nearest centroids of every query
+  int32_t *probes;
+  if ((rc = S.get(&probes, Q * nprobe, "probes"))) return rc;
+  if ((rc = ivhd_knn_query(d_centroids, nlist, N, d_q, Q, nullptr, nprobe, probes, nullptr, stream))) return rc;
+  // lists (points by list, ids ascending) and, per list, its probing queries
+  int32_t *lptr, *pos_id, *pptr, *pq;
+  if ((rc = transpose_lists(S, d_assign, M, 1, nlist, &lptr, &pos_id, flags, s))) return rc;
+  if ((rc = transpose_lists(S, probes, Q, nprobe, nlist, &pptr, &pq, flags, s))) return rc;
+  // work items: (list, chunk of 128 probing queries)
+  std::vector<int32_t> hp(nlist + 1), wl, wc;
+  HIPCHK(hipMemcpyAsync(hp.data(), pptr, (nlist + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int32_t c = 0; c < nlist; ++c)
+    for (int32_t h = 0; (int64_t)h * 128 < (int64_t)hp[c + 1] - hp[c]; ++h) {
+      wl.push_back(c);
+      wc.push_back(h);
+    }
+  const int64_t n_work = (int64_t)wl.size();
+  int32_t *d_wl, *d_wc;
+  if ((rc = S.get(&d_wl, n_work, "work lists")) || (rc = S.get(&d_wc, n_work, "work chunks"))) return rc;
+  if (n_work) {
+    HIPCHK(hipMemcpyAsync(d_wl, wl.data(), n_work * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_wc, wc.data(), n_work * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  }
+  // split rows at one scale: points in list order, queries in their own order
+  uint32_t *amax;
+  if ((rc = S.get(&amax, 1, "largest magnitude"))) return rc;
+  uint32_t bits = 0;
+  HIPCHK(hipMemsetAsync(amax, 0, sizeof *amax, s));
+  HIPCHK(launch_absmax(d_x, M * (int64_t)N, amax, s));
+  HIPCHK(launch_absmax(d_q, Q * (int64_t)N, amax, s));
+  HIPCHK(hipMemcpyAsync(&bits, amax, sizeof bits, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));   // also orders the host vectors' copies above
+  float amx;
+  std::memcpy(&amx, &bits, sizeof amx);
+  if (!std::isfinite(amx)) return fail(IVHD_EINVAL, "the points hold a non-finite coordinate");
+  const float scale = knn_split_scale(amx);
+  const int Np = knn_padded_width(N);
+  _Float16 *xs, *qs;
+  float *norms, *pnorm, *part_dist;
+  int32_t *part_idx;
+  if ((rc = S.get(&xs, (size_t)2 * M * Np, "split points")) || (rc = S.get(&qs, (size_t)2 * Q * Np, "split queries")) ||
+      (rc = S.get(&norms, M, "row norms")) || (rc = S.get(&pnorm, M, "row norms in list order")) ||
+      (rc = S.get(&part_idx, Q * nprobe * k, "per-probe results")) ||
+      (rc = S.get(&part_dist, Q * nprobe * k, "per-probe distances")))
+    return rc;
+  HIPCHK(launch_split_gather(d_x, M, N, Np, scale, pos_id, xs, xs + M * Np, s));
+  HIPCHK(launch_split(d_q, Q, N, Np, scale, qs, qs + Q * Np, s));
+  HIPCHK(launch_row_norms(d_x, M, N, norms, s));
+  HIPCHK(launch_gather_f32(norms, pos_id, M, pnorm, s));
+  HIPCHK(launch_fill_i32(part_idx, Q * nprobe * k, -1, s));
+  HIPCHK(launch_ivf_lists(d_x, N, d_q, xs, xs + M * Np, qs, qs + Q * Np, Np, scale, pnorm, pos_id, lptr, pptr, pq,
+                          d_wl, d_wc, n_work, probes, nprobe, d_self, k, part_idx, part_dist, s));
+  HIPCHK(launch_ivf_merge(part_idx, part_dist, Q, nprobe, k, d_idx, d_dist, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return IVHD_OK;
 }
 
 int ivhd_rnn_mask(const int32_t *d_nn_idx, int64_t M, int32_t nn, const int32_t *d_helper, int32_t kh,
