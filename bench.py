@@ -144,12 +144,44 @@ def build_graph(cfg, dev):
     return dX, labels, Y0, nn_idx, knn_s, int(indeg.max())
 
 
+def ivf_report(dX, exact, cfg):
+    """Approximate kNN graph (inverted file, nlist ~ sqrt(M)) beside the exact
+    one: build and search times, recall of the exact neighbours on 20,000
+    sampled rows, for two probe counts."""
+    import torch
+    from paper_2303_05455_amd import ivhd_ivf_train, ivhd_ivf_search
+    M = cfg.M
+    nlist = 1 << int(round(np.log2(np.sqrt(M))))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    C, a = ivhd_ivf_train(dX, nlist, 6)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    me = torch.arange(M, dtype=torch.int32, device=dX.device)
+    rows = np.random.default_rng(9).choice(M, min(M, 20000), replace=False)
+    ex = exact.cpu().numpy()
+    out = {"nlist": nlist, "lloyd_iterations": 6, "train_s": train_s, "search": {}}
+    for nprobe in (4, 16):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = ivhd_ivf_search(dX, C, a, dX, cfg.nn, nprobe, self_idx=me)
+        torch.cuda.synchronize()
+        search_s = time.perf_counter() - t0
+        g = g.cpu().numpy()
+        recall = float(np.mean([len(np.intersect1d(g[i], ex[i])) for i in rows]) / cfg.nn)
+        out["search"][str(nprobe)] = {"search_s": search_s, "recall": recall}
+        log(f"approximate kNN (nlist {nlist}, nprobe {nprobe}): train {train_s:.2f} s + search "
+            f"{search_s:.2f} s, recall {recall:.3f}")
+    return out
+
+
 def run_loop(args, cfg):
     import torch
     from paper_2303_05455_amd import Context
     dev = torch.device("cuda:0")
     M, nn, rn, R, T = cfg.M, cfg.nn, cfg.rn, cfg.R, cfg.T
     dX, labels, Y0, nn_idx, knn_s, max_in = build_graph(cfg, dev)
+    knn_ivf = None if args.no_variants else ivf_report(dX, nn_idx, cfg)
     del dX
     # heavy-ball stability: b * lambda_max < 2 (1 + a), lambda_max <= max degree + 1
     bound = 2 * (1 + cfg.a) / (max_in + nn + 2 * rn + 2)
@@ -287,6 +319,7 @@ def run_loop(args, cfg):
         "modes": res,
         "variants": variants,
         "knn_build_s": knn_s,
+        "knn_ivf": knn_ivf,
         "max_nn_in_degree": max_in,
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -373,6 +406,7 @@ def run_encoder(args, cfg):
     dev = torch.device("cuda:0")
     epochs = args.epochs
     dX, labels, _, nn_idx, knn_s, max_in = build_graph(cfg, dev)
+    knn_ivf = ivf_report(dX, nn_idx, cfg)
     x16 = ParametricIVHD.to_bf16(dX)
     del dX
     torch.cuda.empty_cache()
@@ -447,7 +481,8 @@ def run_encoder(args, cfg):
         "cf10_encoder": cf_enc, "cf10_plain_ivhd": cf_ivhd, "cf10_ivhd_from_encoder_200it": cf_fb,
         "q_nx10_random_layout": 10 / (cfg.M_heldout - 1),
         "plain_ivhd_s": t_ivhd, "q_nx10_ivhd_from_encoder_200it": q_fb, "fallback_s": t_fb,
-        "knn_build_s": knn_s, "max_nn_in_degree": max_in, "heldout_max_nn_in_degree": max_in_h,
+        "knn_build_s": knn_s, "knn_ivf": knn_ivf, "max_nn_in_degree": max_in,
+        "heldout_max_nn_in_degree": max_in_h,
     }
 
 
