@@ -120,6 +120,44 @@ __device__ __forceinline__ void stage_rows(_Float16 *__restrict__ lds, const _Fl
   }
 }
 
+// One K step of operand rows held in registers: the global loads of step
+// s + 1 are issued before the MFMAs of step s (software pipelining), so their
+// latency hides behind the matrix work instead of stalling after a barrier.
+struct StepFrag {
+  halfx8 qh[2], ql[2], ch, cl;   // 128 query rows and 64 candidate rows x 8 features per thread
+};
+
+__device__ __forceinline__ void load_frag(StepFrag &F, const _Float16 *__restrict__ Qh, const _Float16 *__restrict__ Ql,
+                                          int64_t nq, int64_t q0, const _Float16 *__restrict__ Xh,
+                                          const _Float16 *__restrict__ Xl, int64_t M, int64_t c0, int Np, int k0) {
+  const int kc = (threadIdx.x & 3) * 8;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int r = (threadIdx.x + kKnnThreads * c) >> 2;
+    const bool ok = q0 + r < nq;
+    F.qh[c] = ok ? *reinterpret_cast<const halfx8 *>(Qh + (q0 + r) * Np + k0 + kc) : halfx8{};
+    F.ql[c] = ok ? *reinterpret_cast<const halfx8 *>(Ql + (q0 + r) * Np + k0 + kc) : halfx8{};
+  }
+  const int r = threadIdx.x >> 2;
+  const bool ok = c0 + r < M;
+  F.ch = ok ? *reinterpret_cast<const halfx8 *>(Xh + (c0 + r) * Np + k0 + kc) : halfx8{};
+  F.cl = ok ? *reinterpret_cast<const halfx8 *>(Xl + (c0 + r) * Np + k0 + kc) : halfx8{};
+}
+
+__device__ __forceinline__ void store_frag(const StepFrag &F, _Float16 *sQh, _Float16 *sQl, _Float16 *sCh,
+                                           _Float16 *sCl) {
+  const int kc = (threadIdx.x & 3) * 8;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int r = (threadIdx.x + kKnnThreads * c) >> 2;
+    *reinterpret_cast<halfx8 *>(sQh + r * HP + kc) = F.qh[c];
+    *reinterpret_cast<halfx8 *>(sQl + r * HP + kc) = F.ql[c];
+  }
+  const int r = threadIdx.x >> 2;
+  *reinterpret_cast<halfx8 *>(sCh + r * HP + kc) = F.ch;
+  *reinterpret_cast<halfx8 *>(sCl + r * HP + kc) = F.cl;
+}
+
 // self_mode: 0 = no exclusion, 1 = query q excludes candidate q, 2 = self[q]
 template <int KP>
 __global__ void __launch_bounds__(kKnnThreads)
@@ -155,6 +193,9 @@ knn_kernel(const float *__restrict__ X, int64_t M, int N, const float *__restric
   for (int p = 0; p < KP; ++p) { ks[p] = FLT_MAX; ki[p] = INT32_MAX; }
 
   const int kq = (lane >> 4) * 8;
+  static_assert(QB * (TKK / 8) == 2 * kKnnThreads && CB * (TKK / 8) == kKnnThreads, "fragment shape");
+  StepFrag F;
+  load_frag(F, Qh, Ql, nq, q0, Xh, Xl, M, 0, Np, 0);
   for (int64_t c0 = 0; c0 < M; c0 += CB) {
     floatx4 acc[2][4];
 #pragma unroll
@@ -164,11 +205,17 @@ knn_kernel(const float *__restrict__ X, int64_t M, int N, const float *__restric
 
     for (int k0 = 0; k0 < Np; k0 += TKK) {
       __syncthreads();   // the previous step's operands, or the previous tile's scores, are consumed
-      stage_rows<QB>(sQh, Qh, nq, Np, q0, k0);
-      stage_rows<QB>(sQl, Ql, nq, Np, q0, k0);
-      stage_rows<CB>(sCh, Xh, M, Np, c0, k0);
-      stage_rows<CB>(sCl, Xl, M, Np, c0, k0);
+      store_frag(F, sQh, sQl, sCh, sCl);
       __syncthreads();
+      {  // prefetch the next step: the next K slice, or the first of the next tile
+        int64_t nc0 = c0;
+        int nk0 = k0 + TKK;
+        if (nk0 >= Np) {
+          nk0 = 0;
+          nc0 = c0 + CB;
+        }
+        if (nc0 < M) load_frag(F, Qh, Ql, nq, q0, Xh, Xl, M, nc0, Np, nk0);
+      }
       halfx8 ah[2], al[2], bh[4], bl[4];
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb) {
