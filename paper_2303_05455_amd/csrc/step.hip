@@ -330,14 +330,17 @@ __global__ void lookahead_kernel(const float2 *__restrict__ y, const float2 *__r
 
 // accept / reject of a tentative step: dT = the fixed-order sum of the block
 // partials; kept when finite and |dT| <= tau, else b *= (dT < -tau ? g1 : g2)
-__global__ void __launch_bounds__(kBlock) adapt_decide_kernel(const double *__restrict__ part, int nparts,
-                                                              double tau, float g1, float g2, AdaptState *st) {
-  __shared__ double lds[kBlock];
+constexpr int kDecideThreads = 1024;
+
+__global__ void __launch_bounds__(kDecideThreads) adapt_decide_kernel(const double *__restrict__ part, int nparts,
+                                                                      double tau, float g1, float g2,
+                                                                      AdaptState *st) {
+  __shared__ double lds[kDecideThreads];
   double x = 0.0;
-  for (int p = threadIdx.x; p < nparts; p += kBlock) x += part[p];
+  for (int p = threadIdx.x; p < nparts; p += kDecideThreads) x += part[p];
   lds[threadIdx.x] = x;
   __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
+  for (int s = kDecideThreads / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
     __syncthreads();
   }
@@ -355,15 +358,16 @@ __global__ void __launch_bounds__(kBlock) adapt_decide_kernel(const double *__re
   }
 }
 
-// after a rejection the next state is the current one again
+// after a rejection the next state is the current one again (a small
+// grid-stride launch: it costs next to nothing when the step was kept)
 __global__ void adapt_commit_kernel(const AdaptState *__restrict__ st, const float2 *__restrict__ y,
                                     const float2 *__restrict__ v, int64_t M, float2 *__restrict__ y_next,
                                     float2 *__restrict__ v_next) {
   if (!st->reject) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= M) return;
-  y_next[i] = y[i];
-  v_next[i] = v[i];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
+    y_next[i] = y[i];
+    v_next[i] = v[i];
+  }
 }
 
 }  // namespace
@@ -380,13 +384,14 @@ hipError_t launch_adam_prep(AdamState *st, float beta1, float beta2, hipStream_t
 
 hipError_t launch_adapt_decide(const double *part, int nparts, double tau, float g1, float g2, AdaptState *st,
                                hipStream_t s) {
-  adapt_decide_kernel<<<1, kBlock, 0, s>>>(part, nparts, tau, g1, g2, st);
+  adapt_decide_kernel<<<1, kDecideThreads, 0, s>>>(part, nparts, tau, g1, g2, st);
   return hipGetLastError();
 }
 
 hipError_t launch_adapt_commit(const AdaptState *st, const float2 *y, const float2 *v, int64_t M, float2 *y_next,
                                float2 *v_next, hipStream_t s) {
-  adapt_commit_kernel<<<grid_for(M), kBlock, 0, s>>>(st, y, v, M, y_next, v_next);
+  const unsigned g = grid_for(M) < 1024u ? grid_for(M) : 1024u;
+  adapt_commit_kernel<<<g, kBlock, 0, s>>>(st, y, v, M, y_next, v_next);
   return hipGetLastError();
 }
 
