@@ -39,44 +39,59 @@ struct alignas(16) U16x8 {
   uint16_t v[8];
 };
 
-// stage one operand tile: rows r0..r0+127 of op (row index = m or n), k0..k0+31;
-// op[row][k] = T ? P[k*ld + row] : P[row*ld + k]; out of range -> 0
+// one operand tile (rows r0..r0+127 of op, k0..k0+31) in two halves, so the
+// global loads of step s + 1 can be issued before the MFMAs of step s:
+// op[row][k] = T ? P[k*ld + row] : P[row*ld + k]; out of range -> 0.
+// Each thread holds two 8-element chunks.
+struct TileFrag {
+  U16x8 v[2];
+};
+
 template <bool T>
-__device__ __forceinline__ void stage(uint16_t *__restrict__ lds, const uint16_t *__restrict__ P, int64_t ld,
-                                      int64_t rows, int64_t r0, int64_t k0, int64_t kend, bool vec_ok) {
+__device__ __forceinline__ void load_tile(TileFrag &F, const uint16_t *__restrict__ P, int64_t ld, int64_t rows,
+                                          int64_t r0, int64_t k0, int64_t kend, bool vec_ok) {
   const int tid = threadIdx.x;
-  if (!T) {
-    // 128 rows x 4 chunks of 8 k: 512 chunks, two per thread
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const int id = tid + kGemmThreads * c;
+  for (int c = 0; c < 2; ++c) {
+    const int id = tid + kGemmThreads * c;
+    U16x8 &v = F.v[c];
+    if (!T) {
+      // 128 rows x 4 chunks of 8 k
       const int r = id >> 2, kc = (id & 3) * 8;
       const int64_t row = r0 + r, k = k0 + kc;
-      U16x8 v;
       if (row < rows && vec_ok && k + 8 <= kend) {
         v = *reinterpret_cast<const U16x8 *>(P + row * ld + k);
       } else {
 #pragma unroll
         for (int j = 0; j < 8; ++j) v.v[j] = (row < rows && k + j < kend) ? P[row * ld + k + j] : (uint16_t)0;
       }
-      *reinterpret_cast<U16x8 *>(lds + r * KP + kc) = v;
-    }
-  } else {
-    // k-major source: 32 k x 16 chunks of 8 rows, two per thread, scattered into LDS
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const int id = tid + kGemmThreads * c;
+    } else {
+      // k-major source: 32 k x 16 chunks of 8 rows
       const int kk = id >> 4, rc = (id & 15) * 8;
       const int64_t k = k0 + kk, row = r0 + rc;
-      U16x8 v;
       if (k < kend && vec_ok && row + 8 <= rows) {
         v = *reinterpret_cast<const U16x8 *>(P + k * ld + row);
       } else {
 #pragma unroll
         for (int j = 0; j < 8; ++j) v.v[j] = (k < kend && row + j < rows) ? P[k * ld + row + j] : (uint16_t)0;
       }
+    }
+  }
+}
+
+template <bool T>
+__device__ __forceinline__ void store_tile(const TileFrag &F, uint16_t *__restrict__ lds) {
+  const int tid = threadIdx.x;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) lds[(rc + j) * KP + kk] = v.v[j];
+  for (int c = 0; c < 2; ++c) {
+    const int id = tid + kGemmThreads * c;
+    if (!T) {
+      const int r = id >> 2, kc = (id & 3) * 8;
+      *reinterpret_cast<U16x8 *>(lds + r * KP + kc) = F.v[c];
+    } else {
+      const int kk = id >> 4, rc = (id & 15) * 8;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) lds[(rc + j) * KP + kk] = F.v[c].v[j];
     }
   }
 }
@@ -97,13 +112,20 @@ __global__ void __launch_bounds__(kGemmThreads) gemm_kernel(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
+  // A rows are m: opA[m][k] is P[row*ld + k] unless transposed.  B rows are
+  // n: opB[k][n] is P[row*ld + k] exactly when B is given transposed.
+  TileFrag fa, fb;
+  load_tile<TA>(fa, g.A, g.lda, g.M, m0, kbeg, kend, g.vec_a);
+  load_tile<!TB>(fb, g.B, g.ldb, g.N, n0, kbeg, kend, g.vec_b);
   for (int64_t k0 = kbeg; k0 < kend; k0 += TK) {
     __syncthreads();
-    // A rows are m: opA[m][k] is P[row*ld + k] unless transposed.  B rows are
-    // n: opB[k][n] is P[row*ld + k] exactly when B is given transposed.
-    stage<TA>(As, g.A, g.lda, g.M, m0, k0, kend, g.vec_a);
-    stage<!TB>(Bs, g.B, g.ldb, g.N, n0, k0, kend, g.vec_b);
+    store_tile<TA>(fa, As);
+    store_tile<!TB>(fb, Bs);
     __syncthreads();
+    if (k0 + TK < kend) {   // the next step's loads fly during this step's MFMAs
+      load_tile<TA>(fa, g.A, g.lda, g.M, m0, k0 + TK, kend, g.vec_a);
+      load_tile<!TB>(fb, g.B, g.ldb, g.N, n0, k0 + TK, kend, g.vec_b);
+    }
     const int kq = (lane >> 4) * 8;
     bf16x8 a[4], b[4];
 #pragma unroll
@@ -177,10 +199,19 @@ __global__ void f32_to_bf16_kernel(const float *__restrict__ x, int64_t n, uint1
   if (e < n) y[e] = f2bf(x[e]);
 }
 
-// out[r][:] = X[rows[r]][:] (BF16 rows of width N)
+// out[r][:] = X[rows[r]][:] (BF16 rows of width N); 16-byte chunks when the
+// rows are 16-byte multiples (N % 8 == 0, aligned bases), else elements
 __global__ void gather_rows_kernel(const uint16_t *__restrict__ X, int64_t N, const int32_t *__restrict__ rows,
-                                   int64_t R, uint16_t *__restrict__ out) {
+                                   int64_t R, uint16_t *__restrict__ out, bool vec) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (vec) {
+    const int64_t cpr = N / 8;   // chunks per row
+    if (e >= R * cpr) return;
+    const int64_t r = e / cpr, c = e % cpr;
+    *reinterpret_cast<U16x8 *>(out + r * N + 8 * c) =
+        *reinterpret_cast<const U16x8 *>(X + (int64_t)rows[r] * N + 8 * c);
+    return;
+  }
   if (e >= R * N) return;
   const int64_t r = e / N, k = e % N;
   out[e] = X[(int64_t)rows[r] * N + k];
@@ -324,7 +355,8 @@ hipError_t launch_f32_to_bf16(const float *x, int64_t n, uint16_t *y, hipStream_
 
 hipError_t launch_gather_rows(const uint16_t *X, int64_t N, const int32_t *rows, int64_t R, uint16_t *out,
                               hipStream_t s) {
-  gather_rows_kernel<<<grid_for(R * N), kBlock, 0, s>>>(X, N, rows, R, out);
+  const bool vec = N % 8 == 0 && ((uintptr_t)X % 16 == 0) && ((uintptr_t)out % 16 == 0);
+  gather_rows_kernel<<<grid_for(vec ? R * (N / 8) : R * N), kBlock, 0, s>>>(X, N, rows, R, out, vec);
   return hipGetLastError();
 }
 
