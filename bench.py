@@ -59,8 +59,8 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def source_digest(path=STEP_SOURCE) -> str:
-    return hashlib.sha1(open(path, "rb").read()).hexdigest()[:12]
+def source_digest(path=None) -> str:
+    return hashlib.sha1(open(path or STEP_SOURCE, "rb").read()).hexdigest()[:12]
 
 
 def stored_traffic():
