@@ -96,6 +96,39 @@ __device__ __forceinline__ void store_tile(const TileFrag &F, uint16_t *__restri
   }
 }
 
+// Epilogue of a 128 x 128 tile: wave (wm, wn) holds rows wm..wm+63 and
+// columns wn..wn+63 as 4 x 4 MFMA results; lane l has column l%16 and rows
+// 4(l/16)..+4 of each.  z selects the FP32 split-K slab.
+template <int EPI>
+__device__ __forceinline__ void gemm_epilogue(const GemmArgs &g, const floatx4 (&acc)[4][4], int64_t m0, int64_t n0,
+                                              int wm, int wn, int lane, int64_t z) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t n = n0 + wn + 16 * j + (lane & 15);
+      if (n >= g.N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+        if (m >= g.M) continue;
+        float x = acc[i][j][r];
+        if (EPI == GEMM_EPI_F32) {
+          float *C = static_cast<float *>(g.C) + z * g.M * g.ldc;
+          C[m * g.ldc + n] = x;
+        } else if (EPI == GEMM_EPI_BIAS_RELU_BF16) {
+          x += g.bias ? g.bias[n] : 0.f;
+          x = fmaxf(x, 0.f);
+          static_cast<uint16_t *>(g.C)[m * g.ldc + n] = f2bf(x);
+        } else {   // GEMM_EPI_RELU_MASK_BF16
+          const float h = bf2f(g.mask[m * g.ldm + n]);
+          static_cast<uint16_t *>(g.C)[m * g.ldc + n] = f2bf(h > 0.f ? x : 0.f);
+        }
+      }
+    }
+  }
+}
+
 template <bool TA, bool TB, int EPI>
 __global__ void __launch_bounds__(kGemmThreads) gemm_kernel(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) uint16_t As[TM * KP];
@@ -141,32 +174,118 @@ __global__ void __launch_bounds__(kGemmThreads) gemm_kernel(GemmArgs g) {
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
   }
 
-  // epilogue
+  gemm_epilogue<EPI>(g, acc, m0, n0, wm, wn, lane, blockIdx.z);
+}
+
+// ---- both operands K-contiguous (opA = A[m][k], opB = B[n][k]) -----------
+// The same 128 x 128 tile and wave layout with K steps of 64, LDS double
+// buffered (one barrier per step: the next step's tile is written into the
+// other buffer while this one is read) and the global loads of the step
+// after that in flight during the MFMAs.  Tiles are dealt to the XCDs in
+// contiguous runs (blocks go to XCD b % 8), ordered by K split, then along
+// the longer output side, then the shorter one: the few tiles that share a
+// panel of the long operand, and the tiles of one K split, run on one XCD
+// and share its L2.  Requires 16-byte aligned operands with lda, ldb and K multiples of 8,
+// so every 8-element chunk is wholly inside or outside the matrix and the
+// loads need no branches: a chunk outside reads the operand's first chunk
+// instead.  Rows past M (N) only reach outputs that are never stored; chunks
+// past the end of K are zeroed when written to LDS, after the MFMAs, so no
+// load is waited for before its step.
+constexpr int NTK = 64;
+constexpr int NKP = NTK + 8;   // LDS row pitch in bf16 (144 bytes)
+constexpr int kXcds = 8;
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+struct NtFrag {
+  u32x4 v[4];   // 128 rows x 64 k = 1024 chunks of 8 bf16, four per thread
+};
+
+__device__ __forceinline__ void nt_load(NtFrag &F, const uint16_t *__restrict__ P, int64_t ld, int64_t rows,
+                                        int64_t r0, int64_t k0, int64_t kend) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int c = 0; c < 4; ++c) {
+    const int id = threadIdx.x + kGemmThreads * c;
+    const int64_t row = r0 + (id >> 3), k = k0 + (id & 7) * 8;
+    F.v[c] = *reinterpret_cast<const u32x4 *>(row < rows && k < kend ? P + row * ld + k : P);
+  }
+}
+
+// tile loaded from K offset k0: chunks at or past kend become zeros
+__device__ __forceinline__ void nt_store(const NtFrag &F, uint16_t *__restrict__ lds, int64_t k0, int64_t kend) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t n = n0 + wn + 16 * j + (lane & 15);
-      if (n >= g.N) continue;
+  for (int c = 0; c < 4; ++c) {
+    const int id = threadIdx.x + kGemmThreads * c;
+    const bool kin = k0 + (id & 7) * 8 < kend;
+    *reinterpret_cast<u32x4 *>(lds + (id >> 3) * NKP + (id & 7) * 8) = kin ? F.v[c] : u32x4{0u, 0u, 0u, 0u};
+  }
+}
+
+template <int EPI>
+__global__ void __launch_bounds__(kGemmThreads, 2) gemm_nt_kernel(GemmArgs g, int64_t tiles_m, int64_t tiles_n) {
+  __shared__ __attribute__((aligned(16))) uint16_t S[2][(TM + TN) * NKP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t nb = (int64_t)gridDim.x, lin = blockIdx.x;
+  const int64_t q = nb / kXcds, rem = nb % kXcds, x = lin % kXcds, i = lin / kXcds;
+  const int64_t tile = x < rem ? x * (q + 1) + i : rem * (q + 1) + (x - rem) * q + i;
+  const int64_t per_z = tiles_m * tiles_n, z = tile / per_z, t = tile % per_z;
+  const bool m_outer = tiles_m >= tiles_n;
+  const int64_t m0 = (m_outer ? t / tiles_n : t % tiles_m) * TM;
+  const int64_t n0 = (m_outer ? t % tiles_n : t / tiles_m) * TN;
+  const int64_t kbeg = z * g.kchunk;
+  const int64_t kend = kbeg + g.kchunk < g.K ? kbeg + g.kchunk : g.K;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+
+  floatx4 acc[4][4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
-        if (m >= g.M) continue;
-        float x = acc[i][j][r];
-        if (EPI == GEMM_EPI_F32) {
-          float *C = static_cast<float *>(g.C) + (int64_t)blockIdx.z * g.M * g.ldc;
-          C[m * g.ldc + n] = x;
-        } else if (EPI == GEMM_EPI_BIAS_RELU_BF16) {
-          x += g.bias ? g.bias[n] : 0.f;
-          x = fmaxf(x, 0.f);
-          static_cast<uint16_t *>(g.C)[m * g.ldc + n] = f2bf(x);
-        } else {   // GEMM_EPI_RELU_MASK_BF16
-          const float h = bf2f(g.mask[m * g.ldm + n]);
-          static_cast<uint16_t *>(g.C)[m * g.ldc + n] = f2bf(h > 0.f ? x : 0.f);
-        }
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  NtFrag fa, fb;
+  nt_load(fa, g.A, g.lda, g.M, m0, kbeg, kend);
+  nt_load(fb, g.B, g.ldb, g.N, n0, kbeg, kend);
+  nt_store(fa, S[0], kbeg, kend);
+  nt_store(fb, S[0] + TM * NKP, kbeg, kend);
+  if (kbeg + NTK < kend) {
+    nt_load(fa, g.A, g.lda, g.M, m0, kbeg + NTK, kend);
+    nt_load(fb, g.B, g.ldb, g.N, n0, kbeg + NTK, kend);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = kbeg; k0 < kend; k0 += NTK) {
+    const uint16_t *As = S[buf], *Bs = S[buf] + TM * NKP;
+#pragma unroll
+    for (int kk = 0; kk < NTK; kk += 32) {
+      const int kq = kk + (lane >> 4) * 8;
+      bf16x8 a[4], b[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        a[t] = *reinterpret_cast<const bf16x8 *>(As + (wm + 16 * t + (lane & 15)) * NKP + kq);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        b[t] = *reinterpret_cast<const bf16x8 *>(Bs + (wn + 16 * t + (lane & 15)) * NKP + kq);
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+          acc[ii][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ii], b[jj], acc[ii][jj], 0, 0, 0);
+    }
+    // keep the writes of the next tile (which wait for its global loads)
+    // behind this step's MFMAs
+    __builtin_amdgcn_sched_barrier(0);
+    if (k0 + NTK < kend) {
+      nt_store(fa, S[buf ^ 1], k0 + NTK, kend);
+      nt_store(fb, S[buf ^ 1] + TM * NKP, k0 + NTK, kend);
+      if (k0 + 2 * NTK < kend) {
+        nt_load(fa, g.A, g.lda, g.M, m0, k0 + 2 * NTK, kend);
+        nt_load(fb, g.B, g.ldb, g.N, n0, k0 + 2 * NTK, kend);
       }
     }
+    __syncthreads();
+    buf ^= 1;
   }
+  gemm_epilogue<EPI>(g, acc, m0, n0, wm, wn, lane, z);
 }
 
 // sum of `splits` FP32 slabs [M][ldc] in slab order -> out (FP32, ld = ldo)
@@ -193,6 +312,24 @@ hipError_t launch_gemm_t(const GemmArgs &g, int epi, dim3 grid, hipStream_t s) {
 }
 
 // ---- small kernels around the GEMMs -------------------------------------
+
+// out[c][r] = in[r][c] for a BF16 [R][C] matrix, rows of out padded to ldo
+// (>= R) with zeros; 64 x 64 tiles through LDS (coalesced reads and writes)
+__global__ void __launch_bounds__(256) transpose_bf16_kernel(const uint16_t *__restrict__ in, int64_t R, int64_t C,
+                                                            uint16_t *__restrict__ out, int64_t ldo) {
+  __shared__ uint16_t t[64][65];
+  const int64_t r0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int i = ty; i < 64; i += 4) {
+    const int64_t r = r0 + i, c = c0 + tx;
+    t[i][tx] = (r < R && c < C) ? in[r * C + c] : (uint16_t)0;
+  }
+  __syncthreads();
+  for (int i = ty; i < 64; i += 4) {
+    const int64_t c = c0 + i, r = r0 + tx;
+    if (c < C && r < ldo) out[c * ldo + r] = t[tx][i];
+  }
+}
 
 __global__ void f32_to_bf16_kernel(const float *__restrict__ x, int64_t n, uint16_t *__restrict__ y) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -256,6 +393,59 @@ __global__ void head_dgrad_kernel(const float *__restrict__ dZ, const uint16_t *
 //   mode 0: BF16 matrix X[R][J]           (bias gradients of the hidden layers)
 //   mode 1: dZ (FP32 [R][2]) x H (BF16 [R][K]): j = o*K + k -> dZ[r][o] H[r][k]  (dW3)
 //   mode 2: FP32 matrix [R][J]            (bias gradient of the head)
+// out[j] = sum over the L entries of row j of a BF16 [J][L] matrix: each
+// thread sums its 8-element chunks (stride = block size) in order, then a
+// fixed tree over the block; deterministic
+__global__ void __launch_bounds__(kBlock) rowsum_bf16_kernel(const uint16_t *__restrict__ X, int64_t L,
+                                                            float *__restrict__ out) {
+  __shared__ float red[kBlock];
+  const uint16_t *row = X + (int64_t)blockIdx.x * L;
+  float acc = 0.f;
+  const bool vec = L % 8 == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0;
+  if (vec) {
+    for (int64_t c = threadIdx.x; c < L / 8; c += kBlock) {
+      const U16x8 v = *reinterpret_cast<const U16x8 *>(row + 8 * c);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc += bf2f(v.v[j]);
+    }
+  } else {
+    for (int64_t c = threadIdx.x; c < L; c += kBlock) acc += bf2f(row[c]);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+// first level of the column sums of a BF16 source, eight columns per
+// thread (16-byte loads): mode 0 sums X[r][j]; mode 1 sums
+// dZ[r][j / K] * X[r][j % K] for j < 2K.  Needs J, K multiples of 8 and a
+// 16-byte aligned X.  Thread (chunk, g) sums rows chunk*rows_per_chunk..
+// of columns 8g..8g+7 in row order into part[chunk][J].
+__global__ void colsum8_kernel(int mode, const uint16_t *__restrict__ X, const float *__restrict__ dZ, int64_t R,
+                               int64_t J, int64_t K, int64_t rows_per_chunk, float *__restrict__ part) {
+  const int64_t groups = J / 8;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t chunk = t / groups, j0 = (t % groups) * 8;
+  const int64_t r0 = chunk * rows_per_chunk;
+  if (r0 >= R) return;
+  const int64_t r1 = r0 + rows_per_chunk < R ? r0 + rows_per_chunk : R;
+  const int64_t half = mode == 1 ? j0 / K : 0, col = mode == 1 ? j0 % K : j0, ld = mode == 1 ? K : J;
+  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+  for (int64_t r = r0; r < r1; ++r) {
+    const U16x8 v = *reinterpret_cast<const U16x8 *>(X + r * ld + col);
+    const float w = mode == 1 ? dZ[2 * r + half] : 1.f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] += mode == 1 ? w * bf2f(v.v[j]) : bf2f(v.v[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) part[chunk * J + j0 + j] = acc[j];
+}
+
 __global__ void colsum_kernel(int mode, const void *__restrict__ Xp, const float *__restrict__ dZ,
                               int64_t R, int64_t J, int64_t K, int64_t rows_per_chunk,
                               float *__restrict__ part) {
@@ -323,10 +513,22 @@ __global__ void scale_dz_kernel(float *__restrict__ dz, int64_t n, const float *
 hipError_t launch_gemm_bf16(const GemmArgs &g0, int ta, int tb, int epi, int splits, hipStream_t s) {
   GemmArgs g = g0;
   if (splits < 1) splits = 1;
-  g.kchunk = ((g.K + splits - 1) / splits + TK - 1) / TK * TK;
-  if (g.kchunk < TK) g.kchunk = TK;
+  g.kchunk = ((g.K + splits - 1) / splits + NTK - 1) / NTK * NTK;
+  if (g.kchunk < NTK) g.kchunk = NTK;
   splits = (int)((g.K + g.kchunk - 1) / g.kchunk);
   if (splits < 1) splits = 1;
+  if (!ta && tb && g.vec_a && g.vec_b && g.K % 8 == 0) {
+    const int64_t tm = (g.M + TM - 1) / TM, tn = (g.N + TN - 1) / TN, nb = tm * tn * splits;
+    if (nb > INT32_MAX) return hipErrorInvalidValue;
+    switch (epi) {
+      case GEMM_EPI_F32: gemm_nt_kernel<GEMM_EPI_F32><<<(unsigned)nb, kGemmThreads, 0, s>>>(g, tm, tn); break;
+      case GEMM_EPI_BIAS_RELU_BF16:
+        gemm_nt_kernel<GEMM_EPI_BIAS_RELU_BF16><<<(unsigned)nb, kGemmThreads, 0, s>>>(g, tm, tn);
+        break;
+      default: gemm_nt_kernel<GEMM_EPI_RELU_MASK_BF16><<<(unsigned)nb, kGemmThreads, 0, s>>>(g, tm, tn); break;
+    }
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)((g.N + TN - 1) / TN), (unsigned)((g.M + TM - 1) / TM), (unsigned)splits);
   if (!ta && !tb) return launch_gemm_t<false, false>(g, epi, grid, s);
   if (!ta && tb) return launch_gemm_t<false, true>(g, epi, grid, s);
@@ -336,8 +538,8 @@ hipError_t launch_gemm_bf16(const GemmArgs &g0, int ta, int tb, int epi, int spl
 
 int gemm_splits_used(int64_t K, int splits) {
   if (splits < 1) splits = 1;
-  int64_t kchunk = ((K + splits - 1) / splits + TK - 1) / TK * TK;
-  if (kchunk < TK) kchunk = TK;
+  int64_t kchunk = ((K + splits - 1) / splits + NTK - 1) / NTK * NTK;
+  if (kchunk < NTK) kchunk = NTK;
   const int64_t used = (K + kchunk - 1) / kchunk;
   return (int)(used < 1 ? 1 : used);
 }
@@ -345,6 +547,22 @@ int gemm_splits_used(int64_t K, int splits) {
 hipError_t launch_splitk_reduce(const float *part, int splits, int64_t M, int64_t N, int64_t ldp, float *out,
                                 int64_t ldo, hipStream_t s) {
   splitk_reduce_kernel<<<grid_for(M * N), kBlock, 0, s>>>(part, splits, M, N, ldp, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_bf16(const uint16_t *in, int64_t R, int64_t C, uint16_t *out, int64_t ldo,
+                                 hipStream_t s) {
+  if (ldo == 0 || C == 0) return hipSuccess;
+  if (ldo < R || (C + 63) / 64 > 65535 || (ldo + 63) / 64 > INT32_MAX) return hipErrorInvalidValue;
+  transpose_bf16_kernel<<<dim3((unsigned)((ldo + 63) / 64), (unsigned)((C + 63) / 64)), 256, 0, s>>>(in, R, C, out,
+                                                                                                    ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_rowsum_bf16(const uint16_t *X, int64_t J, int64_t L, float *out, hipStream_t s) {
+  if (J == 0) return hipSuccess;
+  if (J > INT32_MAX) return hipErrorInvalidValue;
+  rowsum_bf16_kernel<<<(unsigned)J, kBlock, 0, s>>>(X, L, out);
   return hipGetLastError();
 }
 
@@ -390,8 +608,14 @@ hipError_t launch_colsum(int mode, const void *X, const float *dZ, int64_t R, in
   for (int level = 0;; ++level) {
     const int64_t chunks = (rows + kColsumRows - 1) / kColsumRows;
     float *dst = chunks == 1 ? out : buf[level & 1];
-    colsum_kernel<<<dim3(grid_for(J), (unsigned)chunks), kBlock, 0, s>>>(level == 0 ? mode : 2, src, dZ, rows, J,
-                                                                         K, kColsumRows, dst);
+    const bool vec8 = level == 0 && mode != 2 && J % 8 == 0 && K % 8 == 0 &&
+                      (reinterpret_cast<uintptr_t>(src) & 15) == 0;
+    if (vec8)
+      colsum8_kernel<<<grid_for(chunks * (J / 8)), kBlock, 0, s>>>(mode, static_cast<const uint16_t *>(src), dZ,
+                                                                  rows, J, K, kColsumRows, dst);
+    else
+      colsum_kernel<<<dim3(grid_for(J), (unsigned)chunks), kBlock, 0, s>>>(level == 0 ? mode : 2, src, dZ, rows,
+                                                                           J, K, kColsumRows, dst);
     if (chunks == 1) break;
     src = dst;
     rows = chunks;

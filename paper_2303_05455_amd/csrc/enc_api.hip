@@ -29,7 +29,11 @@ struct ivhd_enc {
   uint16_t *w16 = nullptr;
   int64_t t = 0;
   int64_t r_cap = 0;
-  uint16_t *xb = nullptr, *a1 = nullptr, *a2 = nullptr, *d1 = nullptr, *d2 = nullptr;
+  uint16_t *xb = nullptr, *a1 = nullptr, *a2 = nullptr, *d2 = nullptr;
+  // feature-major copies [features][Rp] (Rp = rows rounded up to 8, the
+  // padding zero) and W2 as [h1][h2], so that every backward GEMM reads both
+  // operands with K contiguous; the layer-1 gradient exists only this way
+  uint16_t *xbT = nullptr, *a1T = nullptr, *d1T = nullptr, *d2T = nullptr, *w2T = nullptr;
   float *z = nullptr, *dz = nullptr;
   float *ws = nullptr;
   int64_t ws_elems = 0;
@@ -63,8 +67,9 @@ bool enc_live(const ivhd_enc *e) {
 void free_enc(ivhd_enc *e) {
   if (!e) return;
   if (e->plan) (void)ivhd_edges_destroy(e->plan);
-  void *bufs[] = {e->w, e->g, e->m, e->v, e->w16, e->xb, e->a1, e->a2, e->d1, e->d2, e->z, e->dz, e->ws,
-                  e->rows, e->lnn, e->lrn, e->rn_all, e->d_epoch, e->d_losses};
+  void *bufs[] = {e->w, e->g, e->m, e->v, e->w16, e->xb, e->a1, e->a2, e->d2, e->z, e->dz, e->ws,
+                  e->rows, e->lnn, e->lrn, e->rn_all, e->d_epoch, e->d_losses, e->xbT, e->a1T, e->d1T, e->d2T,
+                  e->w2T};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   delete e;
@@ -102,12 +107,13 @@ int forward_rows(ivhd_enc *e, const uint16_t *X, int64_t R, float *z) {
   return IVHD_OK;
 }
 
-// weight gradient dW[M][N] = A^T B over R rows, split over K = R, into g
-int wgrad(ivhd_enc *e, const uint16_t *A, int64_t M, const uint16_t *B, int64_t N, int64_t R, float *out) {
+// weight gradient dW[M][N] = A^T B over R rows, split over K = R, into g;
+// AT [M][R] and BT [N][R] are the transposed operands (K contiguous)
+int wgrad(ivhd_enc *e, const uint16_t *AT, int64_t M, const uint16_t *BT, int64_t N, int64_t R, float *out) {
   hipStream_t s = e->stream;
   const int splits = gemm_splits_used(R, e->splits);
-  GemmArgs gg = gemm(A, B, M, N, R, M, N, e->ws, N);
-  HIPCHK(launch_gemm_bf16(gg, 1, 0, GEMM_EPI_F32, e->splits, s));
+  GemmArgs gg = gemm(AT, BT, M, N, R, R, R, e->ws, N);
+  HIPCHK(launch_gemm_bf16(gg, 0, 1, GEMM_EPI_F32, e->splits, s));
   HIPCHK(launch_splitk_reduce(e->ws, splits, M, N, N, out, N, s));
   return IVHD_OK;
 }
@@ -116,24 +122,31 @@ int wgrad(ivhd_enc *e, const uint16_t *A, int64_t M, const uint16_t *B, int64_t 
 int train_step_rows(ivhd_enc *e, int64_t R, ivhd_edges *plan, float c, float eps, float lr, float scale,
                     double *d_loss) {
   hipStream_t s = e->stream;
+  const int64_t Rp = (R + 7) / 8 * 8;
   int rc = forward_rows(e, e->xb, R, e->z);
   if (rc) return rc;
+  HIPCHK(launch_transpose_bf16(e->xb, R, e->n_in, e->xbT, Rp, s));
+  HIPCHK(launch_transpose_bf16(e->a1, R, e->h1, e->a1T, Rp, s));
+  HIPCHK(launch_transpose_bf16(e->w16 + e->oW2, e->h2, e->h1, e->w2T, e->h2, s));
   if (d_loss && (rc = ivhd_edges_stress(plan, e->z, c, d_loss))) return rc;
   if ((rc = ivhd_edges_grad(plan, e->z, c, eps, nullptr, e->dz))) return rc;
   // head
   HIPCHK(launch_head_dgrad(e->dz, e->w16 + e->oW3, e->a2, R, e->h2, e->d2, s));
   HIPCHK(launch_colsum(1, e->a2, e->dz, R, 2 * (int64_t)e->h2, e->h2, e->ws, e->g + e->oW3, s));
   HIPCHK(launch_colsum(2, e->dz, nullptr, R, 2, 2, e->ws, e->g + e->ob3, s));
-  // layer 2
-  GemmArgs gd = gemm(e->d2, e->w16 + e->oW2, R, e->h1, e->h2, e->h2, e->h1, e->d1, e->h1);
-  gd.mask = e->a1;
-  gd.ldm = e->h1;
-  HIPCHK(launch_gemm_bf16(gd, 0, 0, GEMM_EPI_RELU_MASK_BF16, 1, s));
-  if ((rc = wgrad(e, e->d2, e->h2, e->a1, e->h1, R, e->g + e->oW2))) return rc;
-  HIPCHK(launch_colsum(0, e->d2, nullptr, R, e->h2, e->h2, e->ws, e->g + e->ob2, s));
+  HIPCHK(launch_transpose_bf16(e->d2, R, e->h2, e->d2T, Rp, s));
+  HIPCHK(launch_rowsum_bf16(e->d2T, e->h2, Rp, e->g + e->ob2, s));
+  // layer 2, feature-major: d1^T = (W2^T d2^T) * relu'(a1^T); columns r >= R
+  // come out zero because the mask a1^T is zero there (rows of d2 past R are
+  // never multiplied into a stored value otherwise)
+  GemmArgs gd = gemm(e->w2T, e->d2, e->h1, Rp, e->h2, e->h2, e->h2, e->d1T, Rp);
+  gd.mask = e->a1T;
+  gd.ldm = Rp;
+  HIPCHK(launch_gemm_bf16(gd, 0, 1, GEMM_EPI_RELU_MASK_BF16, 1, s));
+  if ((rc = wgrad(e, e->d2T, e->h2, e->a1T, e->h1, Rp, e->g + e->oW2))) return rc;
   // layer 1
-  if ((rc = wgrad(e, e->d1, e->h1, e->xb, e->n_in, R, e->g + e->oW1))) return rc;
-  HIPCHK(launch_colsum(0, e->d1, nullptr, R, e->h1, e->h1, e->ws, e->g + e->ob1, s));
+  HIPCHK(launch_rowsum_bf16(e->d1T, e->h1, Rp, e->g + e->ob1, s));
+  if ((rc = wgrad(e, e->d1T, e->h1, e->xbT, e->n_in, Rp, e->g + e->oW1))) return rc;
   // Adam
   e->t += 1;
   HIPCHK(launch_adam(e->w, e->g, e->m, e->v, e->w16, e->n_params, lr, 0.9f, 0.999f, 1e-8f, e->t, scale, s));
@@ -216,8 +229,14 @@ int ivhd_enc_create(ivhd_enc **out, int32_t n_in, int32_t h1, int32_t h2, uint64
   ENC_CHK(dev_alloc(&e->xb, max_rows * n_in, "batch input"));
   ENC_CHK(dev_alloc(&e->a1, max_rows * h1, "layer-1 activations"));
   ENC_CHK(dev_alloc(&e->a2, max_rows * h2, "layer-2 activations"));
-  ENC_CHK(dev_alloc(&e->d1, max_rows * h1, "layer-1 gradients"));
-  ENC_CHK(dev_alloc(&e->d2, max_rows * h2, "layer-2 gradients"));
+  const int64_t rows_p = (max_rows + 7) / 8 * 8;
+  // read as a GEMM operand of Rp rows
+  ENC_CHK(dev_alloc(&e->d2, rows_p * h2, "layer-2 gradients"));
+  ENC_CHK(dev_alloc(&e->xbT, rows_p * n_in, "feature-major batch input"));
+  ENC_CHK(dev_alloc(&e->a1T, rows_p * h1, "feature-major layer-1 activations"));
+  ENC_CHK(dev_alloc(&e->d1T, rows_p * h1, "feature-major layer-1 gradients"));
+  ENC_CHK(dev_alloc(&e->d2T, rows_p * h2, "feature-major layer-2 gradients"));
+  ENC_CHK(dev_alloc(&e->w2T, (int64_t)h1 * h2, "transposed W2"));
   ENC_CHK(dev_alloc(&e->z, max_rows * 2, "embedding"));
   ENC_CHK(dev_alloc(&e->dz, max_rows * 2, "embedding gradient"));
   ENC_CHK(dev_alloc(&e->ws, e->ws_elems, "encoder workspace"));

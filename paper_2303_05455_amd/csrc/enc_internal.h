@@ -38,6 +38,12 @@ hipError_t launch_head_dgrad(const float *dZ, const uint16_t *W3, const uint16_t
 // colsum_workspace(R, J) floats.
 constexpr int kColsumRows = 32;
 int64_t colsum_workspace(int64_t R, int64_t J);
+// out [C][ldo] = transpose of the BF16 matrix in [R][C], entries r >= R of
+// each out row zero (ldo >= R)
+hipError_t launch_transpose_bf16(const uint16_t *in, int64_t R, int64_t C, uint16_t *out, int64_t ldo,
+                                 hipStream_t s);
+// out[j] = sum of row j of the BF16 matrix X [J][L] (fixed order)
+hipError_t launch_rowsum_bf16(const uint16_t *X, int64_t J, int64_t L, float *out, hipStream_t s);
 hipError_t launch_colsum(int mode, const void *X, const float *dZ, int64_t R, int64_t J, int64_t K, float *ws,
                          float *out, hipStream_t s);
 hipError_t launch_adam(float *w, const float *g, float *m, float *v, uint16_t *w16, int64_t n, float lr, float b1,

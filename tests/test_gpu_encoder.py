@@ -37,6 +37,11 @@ def _norm_rel(x, ref):
     (257, 130, 100, 0, 1, 0, 1), (128, 128, 32, 0, 0, 0, 1), (300, 77, 513, 1, 0, 0, 4),
     (64, 200, 1000, 1, 1, 0, 3), (1000, 512, 784, 0, 1, 1, 1), (999, 512, 512, 0, 0, 2, 1),
     (512, 784, 4096, 1, 0, 0, 16), (5, 3, 7, 0, 1, 0, 1),
+    # K-contiguous operands with K % 8 == 0 (the double-buffered path): ragged
+    # M and N, a K tail inside the last step, split-K, every epilogue, K = 8,
+    # more column tiles than row tiles
+    (300, 200, 840, 0, 1, 0, 5), (999, 136, 512, 0, 1, 2, 1), (64, 8, 8, 0, 1, 0, 1),
+    (130, 640, 4160, 0, 1, 0, 16), (200, 1000, 72, 0, 1, 1, 1), (136, 4104, 512, 0, 1, 2, 1),
 ])
 def test_gemm_matches_fp64_on_identical_bf16_operands(pkg, M, N, K, ta, tb, epi, splits):
     m, api, _, _ = pkg
@@ -79,7 +84,10 @@ def _setup(pkg, n_in, h1, h2, B, nn, rn, seed):
     return X, p, lnn, lrn, R
 
 
-@pytest.mark.parametrize("n_in,h1,h2,B,nn,rn", [(40, 32, 24, 50, 2, 1), (784, 512, 512, 256, 5, 1)])
+# (51, 2, 1): 204 batch rows, not a multiple of 8 (the feature-major copies
+# are padded with zeros to 208)
+@pytest.mark.parametrize("n_in,h1,h2,B,nn,rn", [(40, 32, 24, 50, 2, 1), (784, 512, 512, 256, 5, 1),
+                                               (48, 40, 16, 51, 2, 1)])
 def test_training_step_matches_the_reference(pkg, n_in, h1, h2, B, nn, rn):
     m, api, ag, par = pkg
     X, p, lnn, lrn, R = _setup(pkg, n_in, h1, h2, B, nn, rn, 11)
@@ -95,6 +103,13 @@ def test_training_step_matches_the_reference(pkg, n_in, h1, h2, B, nn, rn):
     assert loss.item() == pytest.approx(E_ref, rel=1e-4)
     g_gpu = enc.grads().cpu().numpy().astype(np.float64)
     assert _norm_rel(g_gpu, g_ref) <= 1e-3
+    L = mlp.layout(n_in, h1, h2)
+    blk = lambda g, name: g[L[name][0]:L[name][0] + L[name][1]]
+    for name in ("W1", "b1", "W2", "b2", "W3"):   # each block on its own, biases included
+        assert _norm_rel(blk(g_gpu, name), blk(g_ref, name)) <= 2e-3, name
+    # the output bias receives the sum of all forces, zero because every
+    # pair pushes its two ends equally and oppositely: only rounding is left
+    assert np.linalg.norm(blk(g_gpu, "b3")) <= 1e-3 * np.linalg.norm(blk(g_ref, "W3"))
     # the Adam step itself, on the GPU's own gradients (a sign flip of a
     # near-zero gradient moves a weight by 2 lr, so it is checked apart)
     p1_from_gpu_grads, _, _ = mlp.adam(p, g_gpu * scale, np.zeros_like(p), np.zeros_like(p), 1, lr)
