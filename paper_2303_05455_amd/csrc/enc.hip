@@ -221,9 +221,103 @@ __device__ __forceinline__ void nt_store(const NtFrag &F, uint16_t *__restrict__
   }
 }
 
+// Epilogue through LDS: the FP32 tile is staged in Ct [128][kCtPitch] (the
+// operand buffers, free after the last barrier), then every thread finishes
+// whole row chunks (4 FP32 or 8 BF16 outputs) with 16-byte loads and stores
+// where the leading dimensions and pointers allow; the ReLU masks of all of
+// a thread's chunks are loaded before any is used.  Same arithmetic as the
+// register epilogue.
+constexpr int kCtPitch = TN + 4;   // 132 floats: the four 16-lane groups of a store hit disjoint banks
+
+template <int EPI>
+__device__ __forceinline__ void gemm_epilogue_lds(const GemmArgs &g, const floatx4 (&acc)[4][4], int64_t m0,
+                                                  int64_t n0, int wm, int wn, int lane, int64_t z,
+                                                  float *__restrict__ Ct) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        Ct[(wm + 16 * i + 4 * (lane >> 4) + r) * kCtPitch + wn + 16 * j + (lane & 15)] = acc[i][j][r];
+  __syncthreads();
+  const int tid = threadIdx.x;
+  if (EPI == GEMM_EPI_F32) {
+    float *C = static_cast<float *>(g.C) + z * g.M * g.ldc;
+    const bool vec = g.ldc % 4 == 0 && (reinterpret_cast<uintptr_t>(C) & 15) == 0;
+#pragma unroll 4
+    for (int c = 0; c < 16; ++c) {   // 128 rows x 32 chunks of 4
+      const int id = tid + kGemmThreads * c, m = id >> 5, q = (id & 31) * 4;
+      const int64_t row = m0 + m, col = n0 + q;
+      if (row >= g.M || col >= g.N) continue;
+      const floatx4 v = *reinterpret_cast<const floatx4 *>(Ct + m * kCtPitch + q);
+      if (vec && col + 4 <= g.N) {
+        *reinterpret_cast<floatx4 *>(C + row * g.ldc + col) = v;
+      } else {
+        for (int e = 0; e < 4 && col + e < g.N; ++e) C[row * g.ldc + col + e] = v[e];
+      }
+    }
+    return;
+  }
+  uint16_t *C = static_cast<uint16_t *>(g.C);
+  const bool vec = g.ldc % 8 == 0 && (reinterpret_cast<uintptr_t>(C) & 15) == 0;
+  const bool vec_m = EPI == GEMM_EPI_RELU_MASK_BF16 && g.ldm % 8 == 0 &&
+                     (reinterpret_cast<uintptr_t>(g.mask) & 15) == 0;
+  // 128 rows x 16 chunks of 8: thread chunk c is row (tid >> 4) + 16 c.
+  // Whole mask chunks are loaded here, branch-free (others read the first
+  // chunk and are replaced element by element below).
+  U16x8 mk[8];
+  if (EPI == GEMM_EPI_RELU_MASK_BF16) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int64_t row = m0 + (tid >> 4) + 16 * c, col = n0 + (tid & 15) * 8;
+      const bool full = vec_m && row < g.M && col + 8 <= g.N;
+      mk[c] = *reinterpret_cast<const U16x8 *>(full ? g.mask + row * g.ldm + col : g.mask);
+    }
+  }
+  // a thread's columns are the same in all its chunks: their biases once
+  float bv[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (EPI == GEMM_EPI_BIAS_RELU_BF16 && g.bias) {
+    const int64_t col = n0 + (tid & 15) * 8;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float b = g.bias[col + e < g.N ? col + e : g.N - 1];
+      bv[e] = col + e < g.N ? b : 0.f;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int m = (tid >> 4) + 16 * c, q = (tid & 15) * 8;
+    const int64_t row = m0 + m, col = n0 + q;
+    if (row >= g.M || col >= g.N) continue;
+    if (EPI == GEMM_EPI_RELU_MASK_BF16 && !(vec_m && col + 8 <= g.N))
+      for (int e = 0; e < 8; ++e) mk[c].v[e] = col + e < g.N ? g.mask[row * g.ldm + col + e] : (uint16_t)0;
+    const floatx4 lo = *reinterpret_cast<const floatx4 *>(Ct + m * kCtPitch + q);
+    const floatx4 hi = *reinterpret_cast<const floatx4 *>(Ct + m * kCtPitch + q + 4);
+    U16x8 o;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      float x = e < 4 ? lo[e] : hi[e - 4];
+      if (EPI == GEMM_EPI_BIAS_RELU_BF16) {
+        x += bv[e];
+        x = fmaxf(x, 0.f);
+      } else {
+        x = bf2f(mk[c].v[e]) > 0.f ? x : 0.f;
+      }
+      o.v[e] = f2bf(x);
+    }
+    if (vec && col + 8 <= g.N) {
+      *reinterpret_cast<U16x8 *>(C + row * g.ldc + col) = o;
+    } else {
+      for (int e = 0; e < 8 && col + e < g.N; ++e) C[row * g.ldc + col + e] = o.v[e];
+    }
+  }
+}
+
 template <int EPI>
 __global__ void __launch_bounds__(kGemmThreads, 2) gemm_nt_kernel(GemmArgs g, int64_t tiles_m, int64_t tiles_n) {
   __shared__ __attribute__((aligned(16))) uint16_t S[2][(TM + TN) * NKP];
+  static_assert(sizeof(S) >= sizeof(float) * TM * kCtPitch, "epilogue tile must fit in the operand buffers");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t nb = (int64_t)gridDim.x, lin = blockIdx.x;
   const int64_t q = nb / kXcds, rem = nb % kXcds, x = lin % kXcds, i = lin / kXcds;
@@ -285,7 +379,7 @@ __global__ void __launch_bounds__(kGemmThreads, 2) gemm_nt_kernel(GemmArgs g, in
     __syncthreads();
     buf ^= 1;
   }
-  gemm_epilogue<EPI>(g, acc, m0, n0, wm, wn, lane, z);
+  gemm_epilogue_lds<EPI>(g, acc, m0, n0, wm, wn, lane, z, reinterpret_cast<float *>(&S[0][0]));
 }
 
 // sum of `splits` FP32 slabs [M][ldc] in slab order -> out (FP32, ld = ldo)
@@ -389,10 +483,52 @@ __global__ void head_dgrad_kernel(const float *__restrict__ dZ, const uint16_t *
   dH[e] = f2bf(bf2f(H[e]) > 0.f ? g : 0.f);
 }
 
-// column sums over row chunks: part[c][j] = sum_{r in chunk c} f(r, j) for
-//   mode 0: BF16 matrix X[R][J]           (bias gradients of the hidden layers)
-//   mode 1: dZ (FP32 [R][2]) x H (BF16 [R][K]): j = o*K + k -> dZ[r][o] H[r][k]  (dW3)
-//   mode 2: FP32 matrix [R][J]            (bias gradient of the head)
+// A 64-row x 64-column tile of a BF16 [R][C] matrix is formed, optionally
+// written row-major to `out`, and written feature-major to outT [C][ldo]
+// (entries r >= R zero) through LDS, all with 16-byte accesses:
+//   TT_COPY       the tile of `in`
+//   TT_GATHER     rows `rows[r]` of `in` (a batch gathered from the data)
+//   TT_HEAD_DGRAD the head's input gradient from the activations `in` = H:
+//                 (dZ[r][0] W3[0][k] + dZ[r][1] W3[1][k]) * [H[r][k] > 0]
+// Needs C and ldo multiples of 8 and 16-byte aligned in, out, outT.
+__global__ void __launch_bounds__(256) tile_t_kernel(int mode, TileTArgs a) {
+  __shared__ uint32_t t[64][33];   // 64 rows of 64 BF16 (+ one word of padding)
+  const int64_t r0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 64;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int id = threadIdx.x + 256 * c, rl = id >> 3, cc = (id & 7) * 8;
+    const int64_t r = r0 + rl, col = c0 + cc;
+    U16x8 v = {};
+    if (r < a.R && col < a.C) {
+      const int64_t src = (mode == TT_GATHER ? (int64_t)a.rows[r] : r) * a.C + col;
+      v = *reinterpret_cast<const U16x8 *>(a.in + src);
+      if (mode == TT_HEAD_DGRAD) {
+        const float g0 = a.dz[2 * r], g1 = a.dz[2 * r + 1];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const float g = g0 * bf2f(a.w3[col + j]) + g1 * bf2f(a.w3[a.C + col + j]);
+          v.v[j] = f2bf(bf2f(v.v[j]) > 0.f ? g : 0.f);
+        }
+      }
+      if (a.out) *reinterpret_cast<U16x8 *>(a.out + r * a.C + col) = v;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) t[rl][cc / 2 + j] = (uint32_t)v.v[2 * j] | ((uint32_t)v.v[2 * j + 1] << 16);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int id = threadIdx.x + 256 * c, kl = id >> 3, rc = (id & 7) * 8;
+    const int64_t k = c0 + kl, rr = r0 + rc;
+    if (k < a.C && rr < a.ldo) {
+      U16x8 o;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) o.v[j] = (uint16_t)(t[rc + j][kl >> 1] >> ((kl & 1) * 16));
+      *reinterpret_cast<U16x8 *>(a.outT + k * a.ldo + rr) = o;
+    }
+  }
+}
+
 // out[j] = sum over the L entries of row j of a BF16 [J][L] matrix: each
 // thread sums its 8-element chunks (stride = block size) in order, then a
 // fixed tree over the block; deterministic
@@ -446,6 +582,10 @@ __global__ void colsum8_kernel(int mode, const uint16_t *__restrict__ X, const f
   for (int j = 0; j < 8; ++j) part[chunk * J + j0 + j] = acc[j];
 }
 
+// column sums over row chunks: part[c][j] = sum_{r in chunk c} f(r, j) for
+//   mode 0: BF16 matrix X[R][J]           (bias gradients of the hidden layers)
+//   mode 1: dZ (FP32 [R][2]) x H (BF16 [R][K]): j = o*K + k -> dZ[r][o] H[r][k]  (dW3)
+//   mode 2: FP32 matrix [R][J]            (bias gradient of the head)
 __global__ void colsum_kernel(int mode, const void *__restrict__ Xp, const float *__restrict__ dZ,
                               int64_t R, int64_t J, int64_t K, int64_t rows_per_chunk,
                               float *__restrict__ part) {
@@ -556,6 +696,19 @@ hipError_t launch_transpose_bf16(const uint16_t *in, int64_t R, int64_t C, uint1
   if (ldo < R || (C + 63) / 64 > 65535 || (ldo + 63) / 64 > INT32_MAX) return hipErrorInvalidValue;
   transpose_bf16_kernel<<<dim3((unsigned)((ldo + 63) / 64), (unsigned)((C + 63) / 64)), 256, 0, s>>>(in, R, C, out,
                                                                                                     ldo);
+  return hipGetLastError();
+}
+
+bool tile_t_ok(const TileTArgs &a) {
+  auto al = [](const void *p) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  return a.C % 8 == 0 && a.ldo % 8 == 0 && a.ldo >= a.R && al(a.in) && al(a.out) && al(a.outT) && a.outT;
+}
+
+hipError_t launch_tile_t(int mode, const TileTArgs &a, hipStream_t s) {
+  if (!tile_t_ok(a)) return hipErrorInvalidValue;
+  if (a.ldo == 0 || a.C == 0) return hipSuccess;
+  if ((a.C + 63) / 64 > 65535 || (a.ldo + 63) / 64 > INT32_MAX) return hipErrorInvalidValue;
+  tile_t_kernel<<<dim3((unsigned)((a.ldo + 63) / 64), (unsigned)((a.C + 63) / 64)), 256, 0, s>>>(mode, a);
   return hipGetLastError();
 }
 

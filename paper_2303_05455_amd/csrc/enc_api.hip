@@ -118,23 +118,77 @@ int wgrad(ivhd_enc *e, const uint16_t *AT, int64_t M, const uint16_t *BT, int64_
   return IVHD_OK;
 }
 
+// feature-major copy outT [C][Rp] of in [R][C] (16-byte tile path when it
+// applies, else the element transposer)
+int feature_major(const uint16_t *in, int64_t R, int64_t C, int64_t ldo, uint16_t *outT, hipStream_t s) {
+  TileTArgs t;
+  t.in = in;
+  t.R = R;
+  t.C = C;
+  t.ldo = ldo;
+  t.outT = outT;
+  if (tile_t_ok(t)) {
+    HIPCHK(launch_tile_t(TT_COPY, t, s));
+  } else {
+    HIPCHK(launch_transpose_bf16(in, R, C, outT, ldo, s));
+  }
+  return IVHD_OK;
+}
+
+// batch input rows into e->xb: rows[r] of src when rows is given, else the R
+// rows of src; with the 16-byte path the feature-major copy e->xbT is
+// written in the same pass (*xbT_ready)
+int stage_batch(ivhd_enc *e, const uint16_t *src, const int32_t *rows, int64_t R, bool *xbT_ready) {
+  hipStream_t s = e->stream;
+  TileTArgs t;
+  t.in = src;
+  t.rows = rows;
+  t.R = R;
+  t.C = e->n_in;
+  t.ldo = (R + 7) / 8 * 8;
+  t.out = e->xb;
+  t.outT = e->xbT;
+  *xbT_ready = tile_t_ok(t);
+  if (*xbT_ready) {
+    HIPCHK(launch_tile_t(rows ? TT_GATHER : TT_COPY, t, s));
+  } else if (rows) {
+    HIPCHK(launch_gather_rows(src, e->n_in, rows, R, e->xb, s));
+  } else {
+    HIPCHK(hipMemcpyAsync(e->xb, src, (size_t)R * e->n_in * sizeof(uint16_t), hipMemcpyDeviceToDevice, s));
+  }
+  return IVHD_OK;
+}
+
 // one step on the batch already in e->xb (R rows) with local edge plan `plan`
-int train_step_rows(ivhd_enc *e, int64_t R, ivhd_edges *plan, float c, float eps, float lr, float scale,
-                    double *d_loss) {
+int train_step_rows(ivhd_enc *e, int64_t R, bool xbT_ready, ivhd_edges *plan, float c, float eps, float lr,
+                    float scale, double *d_loss) {
   hipStream_t s = e->stream;
   const int64_t Rp = (R + 7) / 8 * 8;
   int rc = forward_rows(e, e->xb, R, e->z);
   if (rc) return rc;
-  HIPCHK(launch_transpose_bf16(e->xb, R, e->n_in, e->xbT, Rp, s));
-  HIPCHK(launch_transpose_bf16(e->a1, R, e->h1, e->a1T, Rp, s));
-  HIPCHK(launch_transpose_bf16(e->w16 + e->oW2, e->h2, e->h1, e->w2T, e->h2, s));
+  if (!xbT_ready && (rc = feature_major(e->xb, R, e->n_in, Rp, e->xbT, s))) return rc;
+  if ((rc = feature_major(e->a1, R, e->h1, Rp, e->a1T, s))) return rc;
+  if ((rc = feature_major(e->w16 + e->oW2, e->h2, e->h1, e->h2, e->w2T, s))) return rc;
   if (d_loss && (rc = ivhd_edges_stress(plan, e->z, c, d_loss))) return rc;
   if ((rc = ivhd_edges_grad(plan, e->z, c, eps, nullptr, e->dz))) return rc;
-  // head
-  HIPCHK(launch_head_dgrad(e->dz, e->w16 + e->oW3, e->a2, R, e->h2, e->d2, s));
+  // head: d2 = input gradient of the head, row-major and feature-major
+  TileTArgs hd;
+  hd.in = e->a2;
+  hd.dz = e->dz;
+  hd.w3 = e->w16 + e->oW3;
+  hd.R = R;
+  hd.C = e->h2;
+  hd.ldo = Rp;
+  hd.out = e->d2;
+  hd.outT = e->d2T;
+  if (tile_t_ok(hd)) {
+    HIPCHK(launch_tile_t(TT_HEAD_DGRAD, hd, s));
+  } else {
+    HIPCHK(launch_head_dgrad(e->dz, e->w16 + e->oW3, e->a2, R, e->h2, e->d2, s));
+    HIPCHK(launch_transpose_bf16(e->d2, R, e->h2, e->d2T, Rp, s));
+  }
   HIPCHK(launch_colsum(1, e->a2, e->dz, R, 2 * (int64_t)e->h2, e->h2, e->ws, e->g + e->oW3, s));
   HIPCHK(launch_colsum(2, e->dz, nullptr, R, 2, 2, e->ws, e->g + e->ob3, s));
-  HIPCHK(launch_transpose_bf16(e->d2, R, e->h2, e->d2T, Rp, s));
   HIPCHK(launch_rowsum_bf16(e->d2T, e->h2, Rp, e->g + e->ob2, s));
   // layer 2, feature-major: d1^T = (W2^T d2^T) * relu'(a1^T); columns r >= R
   // come out zero because the mask a1^T is zero there (rows of d2 past R are
@@ -305,9 +359,10 @@ int ivhd_enc_train_step(ivhd_enc *e, const uint16_t *d_xb16, int64_t R, ivhd_edg
   if (R < 1 || R > e->r_cap) return fail(IVHD_EINVAL, "R = %lld outside [1, max_rows]", (long long)R);
   if (!d_xb16 || !plan) return fail(IVHD_EINVAL, "d_xb16 and plan must not be NULL");
   if (!(lr > 0.f) || !std::isfinite(lr)) return fail(IVHD_EINVAL, "lr = %g must be > 0", (double)lr);
-  HIPCHK(hipMemcpyAsync(e->xb, d_xb16, (size_t)R * e->n_in * sizeof(uint16_t), hipMemcpyDeviceToDevice,
-                        e->stream));
-  return train_step_rows(e, R, plan, c, eps, lr, loss_scale, d_loss);
+  bool ready = false;
+  int rc = stage_batch(e, d_xb16, nullptr, R, &ready);
+  if (rc) return rc;
+  return train_step_rows(e, R, ready, plan, c, eps, lr, loss_scale, d_loss);
 }
 
 int ivhd_enc_train_epoch(ivhd_enc *e, const uint16_t *d_x16, int64_t M, const int32_t *d_nn_idx, int32_t nn,
@@ -372,8 +427,9 @@ int ivhd_enc_train_epoch(ivhd_enc *e, const uint16_t *d_x16, int64_t M, const in
   const float scale = 1.f / (float)batch;
   for (int64_t st = 0; st < steps; ++st) {
     HIPCHK(launch_batch_rows(d_nn_idx, nn, e->rn_all, rn, M, batch, a, c0, st * batch, e->rows, s));
-    HIPCHK(launch_gather_rows(d_x16, e->n_in, e->rows, R, e->xb, s));
-    if ((rc = train_step_rows(e, R, e->plan, c, eps, lr, scale, e->d_losses + st))) return rc;
+    bool ready = false;
+    if ((rc = stage_batch(e, d_x16, e->rows, R, &ready))) return rc;
+    if ((rc = train_step_rows(e, R, ready, e->plan, c, eps, lr, scale, e->d_losses + st))) return rc;
   }
   if (h_loss) {
     double *tmp = new (std::nothrow) double[steps];

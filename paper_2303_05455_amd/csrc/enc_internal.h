@@ -42,6 +42,19 @@ int64_t colsum_workspace(int64_t R, int64_t J);
 // each out row zero (ldo >= R)
 hipError_t launch_transpose_bf16(const uint16_t *in, int64_t R, int64_t C, uint16_t *out, int64_t ldo,
                                  hipStream_t s);
+// tile transposer with a fused producer (see tile_t_kernel for the modes)
+enum { TT_COPY = 0, TT_GATHER = 1, TT_HEAD_DGRAD = 2 };
+struct TileTArgs {
+  const uint16_t *in = nullptr;     // [R][C] (TT_GATHER: the data, rows[r] selects)
+  const int32_t *rows = nullptr;    // TT_GATHER
+  const float *dz = nullptr;        // TT_HEAD_DGRAD: [R][2]
+  const uint16_t *w3 = nullptr;     // TT_HEAD_DGRAD: [2][C]
+  int64_t R = 0, C = 0, ldo = 0;
+  uint16_t *out = nullptr;          // [R][C] row-major copy, or NULL
+  uint16_t *outT = nullptr;         // [C][ldo]
+};
+bool tile_t_ok(const TileTArgs &a);
+hipError_t launch_tile_t(int mode, const TileTArgs &a, hipStream_t s);
 // out[j] = sum of row j of the BF16 matrix X [J][L] (fixed order)
 hipError_t launch_rowsum_bf16(const uint16_t *X, int64_t J, int64_t L, float *out, hipStream_t s);
 hipError_t launch_colsum(int mode, const void *X, const float *dZ, int64_t R, int64_t J, int64_t K, float *ws,

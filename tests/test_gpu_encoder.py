@@ -84,10 +84,11 @@ def _setup(pkg, n_in, h1, h2, B, nn, rn, seed):
     return X, p, lnn, lrn, R
 
 
-# (51, 2, 1): 204 batch rows, not a multiple of 8 (the feature-major copies
-# are padded with zeros to 208)
+# (45, .., 51, 2, 1): 204 batch rows, not a multiple of 8 (the feature-major
+# copies are padded with zeros to 208), and an input width that is not a
+# multiple of 8 (element-wise staging of the batch input)
 @pytest.mark.parametrize("n_in,h1,h2,B,nn,rn", [(40, 32, 24, 50, 2, 1), (784, 512, 512, 256, 5, 1),
-                                               (48, 40, 16, 51, 2, 1)])
+                                               (45, 40, 16, 51, 2, 1)])
 def test_training_step_matches_the_reference(pkg, n_in, h1, h2, B, nn, rn):
     m, api, ag, par = pkg
     X, p, lnn, lrn, R = _setup(pkg, n_in, h1, h2, B, nn, rn, 11)
