@@ -448,18 +448,34 @@ __global__ void gather_rows_kernel(const uint16_t *__restrict__ X, int64_t N, co
   out[e] = X[(int64_t)rows[r] * N + k];
 }
 
-// Z[r][o] = b3[o] + sum_k H[r][k] W3[o][k], o < 2 (one wavefront per row)
+// Z[r][o] = b3[o] + sum_k H[r][k] W3[o][k], o < 2 (one wavefront per row;
+// with vec, K % 8 == 0 and 16-byte aligned H and W3, each lane takes 8
+// consecutive k per 16-byte load)
 __global__ void __launch_bounds__(256) head_forward_kernel(const uint16_t *__restrict__ H, int64_t R, int K,
                                                            const uint16_t *__restrict__ W3,
-                                                           const float *__restrict__ b3, float *__restrict__ Z) {
+                                                           const float *__restrict__ b3, float *__restrict__ Z,
+                                                           bool vec) {
   const int lane = threadIdx.x & 63;
   const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= R) return;
   float s0 = 0.f, s1 = 0.f;
-  for (int k = lane; k < K; k += 64) {
-    const float h = bf2f(H[r * K + k]);
-    s0 += h * bf2f(W3[k]);
-    s1 += h * bf2f(W3[K + k]);
+  if (vec) {
+    for (int k = 8 * lane; k < K; k += 512) {
+      const U16x8 h = *reinterpret_cast<const U16x8 *>(H + r * K + k);
+      const U16x8 w0 = *reinterpret_cast<const U16x8 *>(W3 + k);
+      const U16x8 w1 = *reinterpret_cast<const U16x8 *>(W3 + K + k);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        s0 += bf2f(h.v[j]) * bf2f(w0.v[j]);
+        s1 += bf2f(h.v[j]) * bf2f(w1.v[j]);
+      }
+    }
+  } else {
+    for (int k = lane; k < K; k += 64) {
+      const float h = bf2f(H[r * K + k]);
+      s0 += h * bf2f(W3[k]);
+      s1 += h * bf2f(W3[K + k]);
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -556,59 +572,70 @@ __global__ void __launch_bounds__(kBlock) rowsum_bf16_kernel(const uint16_t *__r
   if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
-// first level of the column sums of a BF16 source, eight columns per
-// thread (16-byte loads): mode 0 sums X[r][j]; mode 1 sums
-// dZ[r][j / K] * X[r][j % K] for j < 2K.  Needs J, K multiples of 8 and a
-// 16-byte aligned X.  Thread (chunk, g) sums rows chunk*rows_per_chunk..
-// of columns 8g..8g+7 in row order into part[chunk][J].
-__global__ void colsum8_kernel(int mode, const uint16_t *__restrict__ X, const float *__restrict__ dZ, int64_t R,
-                               int64_t J, int64_t K, int64_t rows_per_chunk, float *__restrict__ part) {
-  const int64_t groups = J / 8;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t chunk = t / groups, j0 = (t % groups) * 8;
-  const int64_t r0 = chunk * rows_per_chunk;
-  if (r0 >= R) return;
-  const int64_t r1 = r0 + rows_per_chunk < R ? r0 + rows_per_chunk : R;
-  const int64_t half = mode == 1 ? j0 / K : 0, col = mode == 1 ? j0 % K : j0, ld = mode == 1 ? K : J;
-  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
-  for (int64_t r = r0; r < r1; ++r) {
-    const U16x8 v = *reinterpret_cast<const U16x8 *>(X + r * ld + col);
-    const float w = mode == 1 ? dZ[2 * r + half] : 1.f;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) acc[j] += mode == 1 ? w * bf2f(v.v[j]) : bf2f(v.v[j]);
-  }
-#pragma unroll
-  for (int j = 0; j < 8; ++j) part[chunk * J + j0 + j] = acc[j];
-}
-
 // column sums over row chunks: part[c][j] = sum_{r in chunk c} f(r, j) for
-//   mode 0: BF16 matrix X[R][J]           (bias gradients of the hidden layers)
+//   mode 0: BF16 matrix X[R][J]
 //   mode 1: dZ (FP32 [R][2]) x H (BF16 [R][K]): j = o*K + k -> dZ[r][o] H[r][k]  (dW3)
-//   mode 2: FP32 matrix [R][J]            (bias gradient of the head)
-__global__ void colsum_kernel(int mode, const void *__restrict__ Xp, const float *__restrict__ dZ,
-                              int64_t R, int64_t J, int64_t K, int64_t rows_per_chunk,
-                              float *__restrict__ part) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= J) return;
-  const int64_t r0 = (int64_t)blockIdx.y * rows_per_chunk;
-  const int64_t r1 = r0 + rows_per_chunk < R ? r0 + rows_per_chunk : R;
-  auto val = [&](int64_t r) -> float {
-    if (mode == 0) return bf2f(static_cast<const uint16_t *>(Xp)[r * J + j]);
-    if (mode == 1) return dZ[2 * r + j / K] * bf2f(static_cast<const uint16_t *>(Xp)[r * K + j % K]);
-    return static_cast<const float *>(Xp)[r * J + j];
-  };
-  // four running sums (loads in flight), combined in a fixed order
-  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-  int64_t r = r0;
-  for (; r + 4 <= r1; r += 4) {
-    s0 += val(r);
-    s1 += val(r + 1);
-    s2 += val(r + 2);
-    s3 += val(r + 3);
+//   mode 2: FP32 matrix [R][J]            (bias gradient of the head, later levels)
+// A block of 8 x 32 threads covers 32 V-column groups of one chunk of
+// kColsumRows rows: row lane ty sums rows ty, ty + 8, ... in order, then
+// the eight lane sums are added in order ty = 0..7 (deterministic).  V = 8
+// needs J (and K) multiples of 8 and a 16-byte aligned source.
+template <int V>
+__global__ void __launch_bounds__(256) colsum_kernel(int mode, const void *__restrict__ Xp,
+                                                    const float *__restrict__ dZ, int64_t R, int64_t J, int64_t K,
+                                                    float *__restrict__ part) {
+  __shared__ float red[8][32 * V + 1];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int64_t j0 = ((int64_t)blockIdx.x * 32 + tx) * V;
+  const int64_t r0 = (int64_t)blockIdx.y * kColsumRows;
+  const int64_t r1 = r0 + kColsumRows < R ? r0 + kColsumRows : R;
+  float acc[V];
+#pragma unroll
+  for (int e = 0; e < V; ++e) acc[e] = 0.f;
+  if (j0 < J) {
+    const int64_t half = mode == 1 ? j0 / K : 0, col = mode == 1 ? j0 % K : j0, ld = mode == 1 ? K : J;
+#pragma unroll 4
+    for (int64_t r = r0 + ty; r < r1; r += 8) {
+      float x[V];
+      if (mode == 2) {
+        const float *X = static_cast<const float *>(Xp) + r * J + j0;
+        if (V == 8) {
+          const floatx4 lo = *reinterpret_cast<const floatx4 *>(X), hi = *reinterpret_cast<const floatx4 *>(X + 4);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            x[e] = lo[e];
+            x[e + 4] = hi[e];
+          }
+        } else {
+          x[0] = X[0];
+        }
+      } else {
+        const uint16_t *X = static_cast<const uint16_t *>(Xp) + r * ld + col;
+        const float w = mode == 1 ? dZ[2 * r + half] : 1.f;
+        if (V == 8) {
+          const U16x8 v = *reinterpret_cast<const U16x8 *>(X);
+#pragma unroll
+          for (int e = 0; e < V; ++e) x[e] = mode == 1 ? w * bf2f(v.v[e]) : bf2f(v.v[e]);
+        } else {
+          x[0] = mode == 1 ? w * bf2f(X[0]) : bf2f(X[0]);
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < V; ++e) acc[e] += x[e];
+    }
   }
-  for (; r < r1; ++r) s0 += val(r);
-  part[(int64_t)blockIdx.y * J + j] = (s0 + s1) + (s2 + s3);
+#pragma unroll
+  for (int e = 0; e < V; ++e) red[ty][tx * V + e] = acc[e];
+  __syncthreads();
+  if (ty == 0 && j0 < J) {
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      float t = red[0][tx * V + e];
+#pragma unroll
+      for (int q = 1; q < 8; ++q) t += red[q][tx * V + e];
+      part[(int64_t)blockIdx.y * J + j0 + e] = t;
+    }
+  }
 }
 
 // Adam with bias correction 1/(1 - beta^t); refreshes the BF16 copy
@@ -733,7 +760,9 @@ hipError_t launch_gather_rows(const uint16_t *X, int64_t N, const int32_t *rows,
 
 hipError_t launch_head_forward(const uint16_t *H, int64_t R, int K, const uint16_t *W3, const float *b3, float *Z,
                                hipStream_t s) {
-  head_forward_kernel<<<grid_for(R, 4), 256, 0, s>>>(H, R, K, W3, b3, Z);
+  const bool vec = K % 8 == 0 && (reinterpret_cast<uintptr_t>(H) & 15) == 0 &&
+                   (reinterpret_cast<uintptr_t>(W3) & 15) == 0;
+  head_forward_kernel<<<grid_for(R, 4), 256, 0, s>>>(H, R, K, W3, b3, Z, vec);
   return hipGetLastError();
 }
 
@@ -748,9 +777,9 @@ int64_t colsum_workspace(int64_t R, int64_t J) {
   return (c0 + (c0 + kColsumRows - 1) / kColsumRows) * J;
 }
 
-// Column sums as a tree: each level sums kColsumRows consecutive rows per
-// thread into partials [ceil(rows / kColsumRows)][J], until one row is left
-// (written to out).  Levels ping-pong between two regions of ws.
+// Column sums as a tree: each level sums kColsumRows consecutive rows into
+// partials [ceil(rows / kColsumRows)][J], until one row is left (written to
+// out).  Levels ping-pong between two regions of ws.
 hipError_t launch_colsum(int mode, const void *X, const float *dZ, int64_t R, int64_t J, int64_t K, float *ws,
                          float *out, hipStream_t s) {
   if (R < 1 || (R + kColsumRows - 1) / kColsumRows > 65535) return hipErrorInvalidValue;
@@ -759,16 +788,16 @@ hipError_t launch_colsum(int mode, const void *X, const float *dZ, int64_t R, in
   const void *src = X;
   int64_t rows = R;
   for (int level = 0;; ++level) {
+    const int m = level == 0 ? mode : 2;
     const int64_t chunks = (rows + kColsumRows - 1) / kColsumRows;
     float *dst = chunks == 1 ? out : buf[level & 1];
-    const bool vec8 = level == 0 && mode != 2 && J % 8 == 0 && K % 8 == 0 &&
-                      (reinterpret_cast<uintptr_t>(src) & 15) == 0;
+    const bool vec8 = J % 8 == 0 && (m != 1 || K % 8 == 0) && (reinterpret_cast<uintptr_t>(src) & 15) == 0;
     if (vec8)
-      colsum8_kernel<<<grid_for(chunks * (J / 8)), kBlock, 0, s>>>(mode, static_cast<const uint16_t *>(src), dZ,
-                                                                  rows, J, K, kColsumRows, dst);
+      colsum_kernel<8><<<dim3((unsigned)((J / 8 + 31) / 32), (unsigned)chunks), 256, 0, s>>>(m, src, dZ, rows, J,
+                                                                                           K, dst);
     else
-      colsum_kernel<<<dim3(grid_for(J), (unsigned)chunks), kBlock, 0, s>>>(level == 0 ? mode : 2, src, dZ, rows,
-                                                                           J, K, kColsumRows, dst);
+      colsum_kernel<1><<<dim3((unsigned)((J + 31) / 32), (unsigned)chunks), 256, 0, s>>>(m, src, dZ, rows, J, K,
+                                                                                       dst);
     if (chunks == 1) break;
     src = dst;
     rows = chunks;

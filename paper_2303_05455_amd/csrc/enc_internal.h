@@ -36,7 +36,7 @@ hipError_t launch_head_dgrad(const float *dZ, const uint16_t *W3, const uint16_t
 // column sums over R rows as a fixed-order tree of kColsumRows-row partial
 // sums (deterministic); see colsum_kernel for the modes.  ws must hold
 // colsum_workspace(R, J) floats.
-constexpr int kColsumRows = 32;
+constexpr int kColsumRows = 256;
 int64_t colsum_workspace(int64_t R, int64_t J);
 // out [C][ldo] = transpose of the BF16 matrix in [R][C], entries r >= R of
 // each out row zero (ldo >= R)
