@@ -158,6 +158,63 @@ __device__ __forceinline__ void store_frag(const StepFrag &F, _Float16 *sQh, _Fl
   *reinterpret_cast<halfx8 *>(sCl + r * HP + kc) = F.cl;
 }
 
+// End of a query block: the two running lists of each row are merged
+// (through LDS, sS holding at least 2 QB KP words), the survivors are
+// re-ranked by their exact FP32 distances and the best k written out.
+template <int KP>
+__device__ __forceinline__ void finish_rows(float *sS, float (&ks)[KP], int32_t (&ki)[KP], int my_row, int half,
+                                            int64_t my_q, int64_t nq, const float *__restrict__ Q,
+                                            const float *__restrict__ X, int N, int k,
+                                            int32_t *__restrict__ out_idx, float *__restrict__ out_dist) {
+  __syncthreads();
+  float *mS = sS;                                // [QB][KP] scores
+  int32_t *mI = (int32_t *)(sS + QB * KP);       // [QB][KP] indices
+  if (half == 1) {
+#pragma unroll
+    for (int p = 0; p < KP; ++p) { mS[my_row * KP + p] = ks[p]; mI[my_row * KP + p] = ki[p]; }
+  }
+  __syncthreads();
+  if (half == 0 && my_q < nq) {
+#pragma unroll
+    for (int p = 0; p < KP; ++p) list_insert<KP>(ks, ki, mS[my_row * KP + p], mI[my_row * KP + p]);
+    // exact FP32 distances of the survivors, sorted in this row's LDS slots
+    // (a rolled loop: unrolled it would hold 3 KP values in registers for the
+    // whole kernel and cut its occupancy)
+    float *rs = mS + my_row * KP;
+    int32_t *ri = mI + my_row * KP;
+    const float *qrow = Q + my_q * N;
+#pragma unroll
+    for (int p = 0; p < KP; ++p) ri[p] = ki[p];
+#pragma unroll 1
+    for (int p = 0; p < KP; ++p) {
+      const int32_t c = ri[p];
+      float d = FLT_MAX;
+      if (c != INT32_MAX) {
+        const float *xr = X + (int64_t)c * N;
+        d = 0.f;
+        for (int kk = 0; kk < N; ++kk) {
+          const float t = qrow[kk] - xr[kk];
+          d += t * t;
+        }
+      }
+      // insertion into the sorted prefix rs[0..p)
+      int q = p;
+      while (q > 0 && pair_less(d, c, rs[q - 1], ri[q - 1])) {
+        rs[q] = rs[q - 1];
+        ri[q] = ri[q - 1];
+        --q;
+      }
+      rs[q] = d;
+      ri[q] = c;
+    }
+#pragma unroll 1
+    for (int p = 0; p < k; ++p) {
+      out_idx[my_q * k + p] = ri[p] == INT32_MAX ? -1 : ri[p];
+      if (out_dist) out_dist[my_q * k + p] = rs[p];
+    }
+  }
+}
+
 // self_mode: 0 = no exclusion, 1 = query q excludes candidate q, 2 = self[q]
 template <int KP>
 __global__ void __launch_bounds__(kKnnThreads)
@@ -265,54 +322,125 @@ knn_kernel(const float *__restrict__ X, int64_t M, int N, const float *__restric
     }
   }
 
-  // merge the two lists of each row (through LDS), then re-rank exactly
-  __syncthreads();
-  float *mS = sS;                                // [QB][KP] scores
-  int32_t *mI = (int32_t *)(sS + QB * KP);       // [QB][KP] indices
-  if (half == 1) {
+  finish_rows<KP>(sS, ks, ki, my_row, half, my_q, nq, Q, X, N, k, out_idx, out_dist);
+}
+
+// Narrow data (padded width Np = 32 NS <= 128): each wave keeps its 32
+// query rows' hi / lo fragments for all NS K steps in registers for the whole
+// sweep, so only the candidate tile is staged, once per tile: its rows for
+// the next tile are loaded into registers while this tile is multiplied and
+// ranked, and a tile costs two barriers instead of two per K step.  Same
+// MFMA sequence per score (K steps in order, hi.hi, hi.lo, lo.hi), so the
+// scores, and the answers, are those of knn_kernel.
+constexpr int kSmallPitch = 4 * TKK + 8;   // candidate tile pitch in halves (NS <= 4)
+
+template <int KP, int NS>
+__global__ void __launch_bounds__(kKnnThreads, 2)
+knn_small_kernel(const float *__restrict__ X, int64_t M, int N, const float *__restrict__ Q, int64_t nq,
+                 const _Float16 *__restrict__ Xh, const _Float16 *__restrict__ Xl,
+                 const _Float16 *__restrict__ Qh, const _Float16 *__restrict__ Ql, float inv_scale2,
+                 int self_mode, const int32_t *__restrict__ self, const float *__restrict__ cnorm, int k,
+                 int32_t *__restrict__ out_idx, float *__restrict__ out_dist) {
+  constexpr int Np = NS * TKK;
+  __shared__ __attribute__((aligned(16))) float sS[QB * SP];
+  __shared__ __attribute__((aligned(16))) _Float16 sCh[CB * kSmallPitch];
+  __shared__ __attribute__((aligned(16))) _Float16 sCl[CB * kSmallPitch];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t q0 = (int64_t)blockIdx.x * QB;
+  const int my_row = tid >> 1;
+  const int half = tid & 1;
+  const int64_t my_q = q0 + my_row;
+  int64_t my_self = -1;
+  if (my_q < nq) my_self = self_mode == 1 ? my_q : (self_mode == 2 ? (int64_t)self[my_q] : -1);
+
+  float ks[KP];
+  int32_t ki[KP];
 #pragma unroll
-    for (int p = 0; p < KP; ++p) { mS[my_row * KP + p] = ks[p]; mI[my_row * KP + p] = ki[p]; }
+  for (int p = 0; p < KP; ++p) { ks[p] = FLT_MAX; ki[p] = INT32_MAX; }
+
+  const int kq = (lane >> 4) * 8;
+  // this wave's query operands: rows 32 wave + 16 rb + lane % 16
+  halfx8 ah[NS][2], al[NS][2];
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb) {
+    const int64_t q = q0 + 32 * wave + 16 * rb + (lane & 15);
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      ah[t][rb] = q < nq ? *reinterpret_cast<const halfx8 *>(Qh + q * Np + TKK * t + kq) : halfx8{};
+      al[t][rb] = q < nq ? *reinterpret_cast<const halfx8 *>(Ql + q * Np + TKK * t + kq) : halfx8{};
+    }
   }
-  __syncthreads();
-  if (half == 0 && my_q < nq) {
+  // candidate rows: thread holds row tid / 4, features 8 (tid % 4) + 32 t
+  const int cr = tid >> 2, ckc = (tid & 3) * 8;
+  halfx8 ch[NS], cl[NS];
+  auto load_cand = [&](int64_t c0) {
+    const bool ok = c0 + cr < M;
 #pragma unroll
-    for (int p = 0; p < KP; ++p) list_insert<KP>(ks, ki, mS[my_row * KP + p], mI[my_row * KP + p]);
-    // exact FP32 distances of the survivors, sorted in this row's LDS slots
-    // (a rolled loop: unrolled it would hold 3 KP values in registers for the
-    // whole kernel and cut its occupancy)
-    float *rs = mS + my_row * KP;
-    int32_t *ri = mI + my_row * KP;
-    const float *qrow = Q + my_q * N;
+    for (int t = 0; t < NS; ++t) {
+      ch[t] = ok ? *reinterpret_cast<const halfx8 *>(Xh + (c0 + cr) * Np + TKK * t + ckc) : halfx8{};
+      cl[t] = ok ? *reinterpret_cast<const halfx8 *>(Xl + (c0 + cr) * Np + TKK * t + ckc) : halfx8{};
+    }
+  };
+  load_cand(0);
+  for (int64_t c0 = 0; c0 < M; c0 += CB) {
 #pragma unroll
-    for (int p = 0; p < KP; ++p) ri[p] = ki[p];
-#pragma unroll 1
-    for (int p = 0; p < KP; ++p) {
-      const int32_t c = ri[p];
-      float d = FLT_MAX;
-      if (c != INT32_MAX) {
-        const float *xr = X + (int64_t)c * N;
-        d = 0.f;
-        for (int kk = 0; kk < N; ++kk) {
-          const float t = qrow[kk] - xr[kk];
-          d += t * t;
+    for (int t = 0; t < NS; ++t) {
+      *reinterpret_cast<halfx8 *>(sCh + cr * kSmallPitch + TKK * t + ckc) = ch[t];
+      *reinterpret_cast<halfx8 *>(sCl + cr * kSmallPitch + TKK * t + ckc) = cl[t];
+    }
+    __syncthreads();   // tile staged; every thread has finished ranking the previous tile
+    if (c0 + CB < M) load_cand(c0 + CB);
+    floatx4 acc[2][4];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      halfx8 bh[4], bl[4];
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        const int r = 16 * cb + (lane & 15);
+        bh[cb] = *reinterpret_cast<const halfx8 *>(sCh + r * kSmallPitch + TKK * t + kq);
+        bl[cb] = *reinterpret_cast<const halfx8 *>(sCl + r * kSmallPitch + TKK * t + kq);
+      }
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[t][rb], bh[cb], acc[rb][cb], 0, 0, 0);
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[t][rb], bl[cb], acc[rb][cb], 0, 0, 0);
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[t][rb], bh[cb], acc[rb][cb], 0, 0, 0);
         }
-      }
-      // insertion into the sorted prefix rs[0..p)
-      int q = p;
-      while (q > 0 && pair_less(d, c, rs[q - 1], ri[q - 1])) {
-        rs[q] = rs[q - 1];
-        ri[q] = ri[q - 1];
-        --q;
-      }
-      rs[q] = d;
-      ri[q] = c;
     }
-#pragma unroll 1
-    for (int p = 0; p < k; ++p) {
-      out_idx[my_q * k + p] = ri[p] == INT32_MAX ? -1 : ri[p];
-      if (out_dist) out_dist[my_q * k + p] = rs[p];
+    // scores: D[i][j] of a 16x16 block sits in lane j + 16 (i / 4), register i % 4
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      const int col = 16 * cb + (lane & 15);
+      const int64_t c = c0 + col;
+      const float cn = c < M ? cnorm[c] : 0.f;
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 32 * wave + 16 * rb + 4 * (lane >> 4) + r;
+          sS[row * SP + col] = cn - 2.f * (acc[rb][cb][r] * inv_scale2);
+        }
+    }
+    __syncthreads();   // scores complete; every wave has finished reading the candidate tile
+    if (my_q < nq) {
+      for (int m = 0; m < CB / 2; ++m) {
+        const int col = 2 * m + half;
+        const int64_t c = c0 + col;
+        if (c >= M || c == my_self) continue;
+        list_insert<KP>(ks, ki, sS[my_row * SP + col], (int32_t)c);
+      }
     }
   }
+  finish_rows<KP>(sS, ks, ki, my_row, half, my_q, nq, Q, X, N, k, out_idx, out_dist);
 }
 
 // ---- inverted-file (approximate) search ------------------------------------
@@ -585,8 +713,23 @@ hipError_t launch_knn_kp(const float *X, int64_t M, int N, const float *Q, int64
                          hipStream_t s) {
   static_assert(2 * QB * KP <= QB * SP, "merge buffers must fit in the score tile");
   const unsigned grid = (unsigned)((nq + QB - 1) / QB);
-  knn_kernel<KP><<<grid, kKnnThreads, 0, s>>>(X, M, N, Q, nq, Xh, Xl, Qh, Ql, Np, inv_scale2, self_mode, self,
-                                               cnorm, k, idx, dist);
+#define IVHD_SMALL_ARGS X, M, N, Q, nq, Xh, Xl, Qh, Ql, inv_scale2, self_mode, self, cnorm, k, idx, dist
+  // (KP = 32 with four K steps would spill registers: the general kernel)
+  if (Np == TKK) {
+    knn_small_kernel<KP, 1><<<grid, kKnnThreads, 0, s>>>(IVHD_SMALL_ARGS);
+  } else if (Np == 2 * TKK) {
+    knn_small_kernel<KP, 2><<<grid, kKnnThreads, 0, s>>>(IVHD_SMALL_ARGS);
+  } else if (Np == 3 * TKK) {
+    knn_small_kernel<KP, 3><<<grid, kKnnThreads, 0, s>>>(IVHD_SMALL_ARGS);
+  } else if constexpr (KP < 32) {
+    if (Np == 4 * TKK) knn_small_kernel<KP, 4><<<grid, kKnnThreads, 0, s>>>(IVHD_SMALL_ARGS);
+    else knn_kernel<KP><<<grid, kKnnThreads, 0, s>>>(X, M, N, Q, nq, Xh, Xl, Qh, Ql, Np, inv_scale2, self_mode,
+                                                      self, cnorm, k, idx, dist);
+  } else {
+    knn_kernel<KP><<<grid, kKnnThreads, 0, s>>>(X, M, N, Q, nq, Xh, Xl, Qh, Ql, Np, inv_scale2, self_mode, self,
+                                                 cnorm, k, idx, dist);
+  }
+#undef IVHD_SMALL_ARGS
   return hipGetLastError();
 }
 

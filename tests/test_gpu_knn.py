@@ -43,9 +43,12 @@ def _check_rows(X, rows, got, want, rel=2e-6):
     return bad
 
 
+# padded widths 32, 64, 96, 128 (register-resident queries; with k + 4 > 16
+# at 128 the general kernel) and 800 (general kernel), every list length
 @pytest.mark.parametrize("M,N,k,seed", [(3000, 32, 2, 0), (1000, 100, 5, 1), (513, 7, 10, 2),
                                         (200, 784, 20, 3), (777, 2, 3, 4), (40, 16, 28, 5),
-                                        (5, 3, 4, 6)])
+                                        (5, 3, 4, 6), (1500, 50, 3, 7), (900, 90, 12, 8),
+                                        (600, 120, 25, 9), (700, 60, 28, 10)])
 def test_knn_build_matches_oracle(ivhd, M, N, k, seed):
     rng = np.random.default_rng(seed)
     X = rng.normal(size=(M, N)).astype(np.float32)
