@@ -215,26 +215,69 @@ __device__ __forceinline__ void finish_rows(float *sS, float (&ks)[KP], int32_t 
   }
 }
 
+// Wide data: a block owns 128 queries and sweeps the candidates in tiles of
+// CBW = 128; wave (wq, wc) computes the 64 x 64 quarter rows 64 wq.., columns
+// 64 wc.. of each tile, so every staged operand byte feeds twice the MFMAs
+// of a 64-candidate tile.  The operand rows of K step s + 1 are loaded into
+// registers during the MFMAs of step s.
+constexpr int CBW = 128;        // candidates per tile (wide kernel)
+constexpr int SPW = CBW + 1;    // its score tile pitch (floats)
+
+struct WideFrag {
+  halfx8 qh[2], ql[2], ch[2], cl[2];   // 128 query and 128 candidate rows x 8 features per thread
+};
+
+__device__ __forceinline__ void load_wide(WideFrag &F, const _Float16 *__restrict__ Qh,
+                                          const _Float16 *__restrict__ Ql, int64_t nq, int64_t q0,
+                                          const _Float16 *__restrict__ Xh, const _Float16 *__restrict__ Xl,
+                                          int64_t M, int64_t c0, int Np, int k0) {
+  const int kc = (threadIdx.x & 3) * 8;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int r = (threadIdx.x + kKnnThreads * c) >> 2;
+    const bool okq = q0 + r < nq, okc = c0 + r < M;
+    F.qh[c] = okq ? *reinterpret_cast<const halfx8 *>(Qh + (q0 + r) * Np + k0 + kc) : halfx8{};
+    F.ql[c] = okq ? *reinterpret_cast<const halfx8 *>(Ql + (q0 + r) * Np + k0 + kc) : halfx8{};
+    F.ch[c] = okc ? *reinterpret_cast<const halfx8 *>(Xh + (c0 + r) * Np + k0 + kc) : halfx8{};
+    F.cl[c] = okc ? *reinterpret_cast<const halfx8 *>(Xl + (c0 + r) * Np + k0 + kc) : halfx8{};
+  }
+}
+
+__device__ __forceinline__ void store_wide(const WideFrag &F, _Float16 *sQh, _Float16 *sQl, _Float16 *sCh,
+                                           _Float16 *sCl) {
+  const int kc = (threadIdx.x & 3) * 8;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int r = (threadIdx.x + kKnnThreads * c) >> 2;
+    *reinterpret_cast<halfx8 *>(sQh + r * HP + kc) = F.qh[c];
+    *reinterpret_cast<halfx8 *>(sQl + r * HP + kc) = F.ql[c];
+    *reinterpret_cast<halfx8 *>(sCh + r * HP + kc) = F.ch[c];
+    *reinterpret_cast<halfx8 *>(sCl + r * HP + kc) = F.cl[c];
+  }
+}
+
 // self_mode: 0 = no exclusion, 1 = query q excludes candidate q, 2 = self[q]
 template <int KP>
-__global__ void __launch_bounds__(kKnnThreads)
+__global__ void __launch_bounds__(kKnnThreads, 2)
 knn_kernel(const float *__restrict__ X, int64_t M, int N, const float *__restrict__ Q, int64_t nq,
            const _Float16 *__restrict__ Xh, const _Float16 *__restrict__ Xl, const _Float16 *__restrict__ Qh,
            const _Float16 *__restrict__ Ql, int Np, float inv_scale2, int self_mode,
            const int32_t *__restrict__ self, const float *__restrict__ cnorm, int k,
            int32_t *__restrict__ out_idx, float *__restrict__ out_dist) {
   // one LDS area: the operand tiles during the K loop, then the score tile
-  __shared__ __attribute__((aligned(16))) float smem[QB * SP];
-  static_assert((2 * QB + 2 * CB) * HP * 2 <= QB * SP * 4, "operand tiles must fit in the score tile");
+  __shared__ __attribute__((aligned(16))) float smem[QB * SPW];
+  static_assert((2 * QB + 2 * CBW) * HP * 2 <= QB * SPW * 4, "operand tiles must fit in the score tile");
+  static_assert(2 * QB * 32 <= QB * SPW, "merge buffers must fit in the score tile");
   _Float16 *sQh = reinterpret_cast<_Float16 *>(smem);
   _Float16 *sQl = sQh + QB * HP;
   _Float16 *sCh = sQl + QB * HP;
-  _Float16 *sCl = sCh + CB * HP;
+  _Float16 *sCl = sCh + CBW * HP;
   float *sS = smem;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
+  const int wq = 64 * (wave >> 1), wc = 64 * (wave & 1);
   const int64_t q0 = (int64_t)blockIdx.x * QB;
 
   // scan ownership: two threads per query row, interleaved columns
@@ -250,78 +293,75 @@ knn_kernel(const float *__restrict__ X, int64_t M, int N, const float *__restric
   for (int p = 0; p < KP; ++p) { ks[p] = FLT_MAX; ki[p] = INT32_MAX; }
 
   const int kq = (lane >> 4) * 8;
-  static_assert(QB * (TKK / 8) == 2 * kKnnThreads && CB * (TKK / 8) == kKnnThreads, "fragment shape");
-  StepFrag F;
-  load_frag(F, Qh, Ql, nq, q0, Xh, Xl, M, 0, Np, 0);
-  for (int64_t c0 = 0; c0 < M; c0 += CB) {
-    floatx4 acc[2][4];
+  static_assert(QB * (TKK / 8) == 2 * kKnnThreads && CBW * (TKK / 8) == 2 * kKnnThreads, "fragment shape");
+  WideFrag F;
+  load_wide(F, Qh, Ql, nq, q0, Xh, Xl, M, 0, Np, 0);
+  for (int64_t c0 = 0; c0 < M; c0 += CBW) {
+    floatx4 acc[4][4];
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     for (int k0 = 0; k0 < Np; k0 += TKK) {
       __syncthreads();   // the previous step's operands, or the previous tile's scores, are consumed
-      store_frag(F, sQh, sQl, sCh, sCl);
+      store_wide(F, sQh, sQl, sCh, sCl);
       __syncthreads();
       {  // prefetch the next step: the next K slice, or the first of the next tile
         int64_t nc0 = c0;
         int nk0 = k0 + TKK;
         if (nk0 >= Np) {
           nk0 = 0;
-          nc0 = c0 + CB;
+          nc0 = c0 + CBW;
         }
-        if (nc0 < M) load_frag(F, Qh, Ql, nq, q0, Xh, Xl, M, nc0, Np, nk0);
+        if (nc0 < M) load_wide(F, Qh, Ql, nq, q0, Xh, Xl, M, nc0, Np, nk0);
       }
-      halfx8 ah[2], al[2], bh[4], bl[4];
+      halfx8 ah[4], al[4];
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb) {
-        const int r = 32 * wave + 16 * rb + (lane & 15);
+      for (int rb = 0; rb < 4; ++rb) {
+        const int r = wq + 16 * rb + (lane & 15);
         ah[rb] = *reinterpret_cast<const halfx8 *>(sQh + r * HP + kq);
         al[rb] = *reinterpret_cast<const halfx8 *>(sQl + r * HP + kq);
       }
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) {
-        const int r = 16 * cb + (lane & 15);
-        bh[cb] = *reinterpret_cast<const halfx8 *>(sCh + r * HP + kq);
-        bl[cb] = *reinterpret_cast<const halfx8 *>(sCl + r * HP + kq);
-      }
+        const int r = wc + 16 * cb + (lane & 15);
+        const halfx8 bh = *reinterpret_cast<const halfx8 *>(sCh + r * HP + kq);
+        const halfx8 bl = *reinterpret_cast<const halfx8 *>(sCl + r * HP + kq);
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[rb], bh[cb], acc[rb][cb], 0, 0, 0);
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[rb], bl[cb], acc[rb][cb], 0, 0, 0);
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[rb], bh[cb], acc[rb][cb], 0, 0, 0);
+        for (int rb = 0; rb < 4; ++rb) {
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[rb], bh, acc[rb][cb], 0, 0, 0);
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[rb], bl, acc[rb][cb], 0, 0, 0);
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[rb], bh, acc[rb][cb], 0, 0, 0);
         }
+      }
     }
     __syncthreads();   // operands dead: the area becomes the score tile
 
     // scores: D[i][j] of a 16x16 block sits in lane j + 16 (i / 4), register i % 4
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) {
-      const int col = 16 * cb + (lane & 15);
+      const int col = wc + 16 * cb + (lane & 15);
       const int64_t c = c0 + col;
       const float cn = c < M ? cnorm[c] : 0.f;
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
+      for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = 32 * wave + 16 * rb + 4 * (lane >> 4) + r;
-          sS[row * SP + col] = cn - 2.f * (acc[rb][cb][r] * inv_scale2);
+          const int row = wq + 16 * rb + 4 * (lane >> 4) + r;
+          sS[row * SPW + col] = cn - 2.f * (acc[rb][cb][r] * inv_scale2);
         }
     }
     __syncthreads();
     if (my_q < nq) {
-      for (int m = 0; m < CB / 2; ++m) {
+      for (int m = 0; m < CBW / 2; ++m) {
         const int col = 2 * m + half;
         const int64_t c = c0 + col;
         if (c >= M || c == my_self) continue;
-        list_insert<KP>(ks, ki, sS[my_row * SP + col], (int32_t)c);
+        list_insert<KP>(ks, ki, sS[my_row * SPW + col], (int32_t)c);
       }
     }
   }
-
   finish_rows<KP>(sS, ks, ki, my_row, half, my_q, nq, Q, X, N, k, out_idx, out_dist);
 }
 
