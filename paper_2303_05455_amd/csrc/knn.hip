@@ -15,11 +15,13 @@
 // about 5x the throughput of the FP32 matrix path.
 //
 // A block of 256 threads (4 waves) owns 128 queries and sweeps all
-// candidates in tiles of 64, K in steps of 32 staged in LDS (K contiguous per
-// row: one lane's operand, 8 consecutive k, is one 16-byte read).  The
+// candidates: for padded widths up to 128 in tiles of 64 with the queries'
+// operands held in registers (knn_small_kernel), above that in tiles of 128,
+// K in steps of 32 staged in LDS (knn_kernel); K is contiguous per LDS row,
+// so one lane's operand, 8 consecutive k, is one 16-byte read.  The
 // ranking score |x_c|^2 - 2 q.x_c (|q|^2 is the same for the whole row) goes
-// to LDS (aliasing the operand buffers, which are dead by then), where two
-// threads per query row keep running top-KP lists in registers.  At the end
+// to an LDS score tile, where two threads per query row keep running top-KP
+// lists in registers.  At the end
 // the two lists are merged and the KP survivors are re-ranked by their exact
 // FP32 distance sum_k (q_k - x_k)^2, which removes the cancellation error of
 // the expanded form; KP >= k + 4 leaves room for candidates the score
@@ -100,62 +102,6 @@ __global__ void split_kernel(const float *__restrict__ X, int64_t M, int N, int 
   const _Float16 h = (_Float16)x;
   hi[e] = h;
   lo[e] = (_Float16)(x - (float)h);
-}
-
-// rows r0..r0+ROWS-1 of a [rows][Np] half array, features k0..k0+31, into LDS
-// (pitch HP); rows past the end read as zeros
-template <int ROWS>
-__device__ __forceinline__ void stage_rows(_Float16 *__restrict__ lds, const _Float16 *__restrict__ P, int64_t rows,
-                                           int Np, int64_t r0, int k0) {
-  constexpr int kChunks = ROWS * (TKK / 8);   // 16-byte chunks
-#pragma unroll
-  for (int c = 0; c < (kChunks + kKnnThreads - 1) / kKnnThreads; ++c) {
-    const int id = threadIdx.x + kKnnThreads * c;
-    if (kChunks % kKnnThreads == 0 || id < kChunks) {
-      const int r = id >> 2, kc = (id & 3) * 8;
-      halfx8 v = {};
-      if (r0 + r < rows) v = *reinterpret_cast<const halfx8 *>(P + (r0 + r) * Np + k0 + kc);
-      *reinterpret_cast<halfx8 *>(lds + r * HP + kc) = v;
-    }
-  }
-}
-
-// One K step of operand rows held in registers: the global loads of step
-// s + 1 are issued before the MFMAs of step s (software pipelining), so their
-// latency hides behind the matrix work instead of stalling after a barrier.
-struct StepFrag {
-  halfx8 qh[2], ql[2], ch, cl;   // 128 query rows and 64 candidate rows x 8 features per thread
-};
-
-__device__ __forceinline__ void load_frag(StepFrag &F, const _Float16 *__restrict__ Qh, const _Float16 *__restrict__ Ql,
-                                          int64_t nq, int64_t q0, const _Float16 *__restrict__ Xh,
-                                          const _Float16 *__restrict__ Xl, int64_t M, int64_t c0, int Np, int k0) {
-  const int kc = (threadIdx.x & 3) * 8;
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    const int r = (threadIdx.x + kKnnThreads * c) >> 2;
-    const bool ok = q0 + r < nq;
-    F.qh[c] = ok ? *reinterpret_cast<const halfx8 *>(Qh + (q0 + r) * Np + k0 + kc) : halfx8{};
-    F.ql[c] = ok ? *reinterpret_cast<const halfx8 *>(Ql + (q0 + r) * Np + k0 + kc) : halfx8{};
-  }
-  const int r = threadIdx.x >> 2;
-  const bool ok = c0 + r < M;
-  F.ch = ok ? *reinterpret_cast<const halfx8 *>(Xh + (c0 + r) * Np + k0 + kc) : halfx8{};
-  F.cl = ok ? *reinterpret_cast<const halfx8 *>(Xl + (c0 + r) * Np + k0 + kc) : halfx8{};
-}
-
-__device__ __forceinline__ void store_frag(const StepFrag &F, _Float16 *sQh, _Float16 *sQl, _Float16 *sCh,
-                                           _Float16 *sCl) {
-  const int kc = (threadIdx.x & 3) * 8;
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    const int r = (threadIdx.x + kKnnThreads * c) >> 2;
-    *reinterpret_cast<halfx8 *>(sQh + r * HP + kc) = F.qh[c];
-    *reinterpret_cast<halfx8 *>(sQl + r * HP + kc) = F.ql[c];
-  }
-  const int r = threadIdx.x >> 2;
-  *reinterpret_cast<halfx8 *>(sCh + r * HP + kc) = F.ch;
-  *reinterpret_cast<halfx8 *>(sCl + r * HP + kc) = F.cl;
 }
 
 // End of a query block: the two running lists of each row are merged
@@ -513,39 +459,44 @@ __global__ void split_gather_kernel(const float *__restrict__ X, int64_t M, int 
   lo[e] = (_Float16)(x - (float)h);
 }
 
-// like stage_rows, with row r taken from rows_of[r0 + r] (r0 + r < n)
-template <int ROWS>
-__device__ __forceinline__ void stage_rows_indexed(_Float16 *__restrict__ lds, const _Float16 *__restrict__ P,
-                                                   const int32_t *__restrict__ rows_of, int64_t n, int Np,
-                                                   int64_t r0, int k0) {
-  constexpr int kChunks = ROWS * (TKK / 8);
+// one K step of the list kernel's operands in registers (loaded a step ahead):
+// 128 query rows (ids pq[qbeg + r] while qbeg + r < qend) and 64 contiguous
+// list rows c0 + r while < pend, 8 features per chunk
+struct IvfFrag {
+  halfx8 qh[2], ql[2], ch, cl;
+};
+
+__device__ __forceinline__ void load_ivf(IvfFrag &F, const _Float16 *__restrict__ Qh,
+                                         const _Float16 *__restrict__ Ql, const int32_t *__restrict__ pq,
+                                         int64_t qbeg, int64_t qend, const _Float16 *__restrict__ Xh,
+                                         const _Float16 *__restrict__ Xl, int64_t c0, int64_t pend, int Np, int k0) {
+  const int kc = (threadIdx.x & 3) * 8;
 #pragma unroll
-  for (int c = 0; c < (kChunks + kKnnThreads - 1) / kKnnThreads; ++c) {
-    const int id = threadIdx.x + kKnnThreads * c;
-    if (kChunks % kKnnThreads == 0 || id < kChunks) {
-      const int r = id >> 2, kc = (id & 3) * 8;
-      halfx8 v = {};
-      if (r0 + r < n) v = *reinterpret_cast<const halfx8 *>(P + (int64_t)rows_of[r0 + r] * Np + k0 + kc);
-      *reinterpret_cast<halfx8 *>(lds + r * HP + kc) = v;
-    }
+  for (int c = 0; c < 2; ++c) {
+    const int r = (threadIdx.x + kKnnThreads * c) >> 2;
+    const bool ok = qbeg + r < qend;
+    const int64_t row = ok ? (int64_t)pq[qbeg + r] : 0;
+    F.qh[c] = ok ? *reinterpret_cast<const halfx8 *>(Qh + row * Np + k0 + kc) : halfx8{};
+    F.ql[c] = ok ? *reinterpret_cast<const halfx8 *>(Ql + row * Np + k0 + kc) : halfx8{};
   }
+  const int r = threadIdx.x >> 2;
+  const bool ok = c0 + r < pend;
+  F.ch = ok ? *reinterpret_cast<const halfx8 *>(Xh + (c0 + r) * Np + k0 + kc) : halfx8{};
+  F.cl = ok ? *reinterpret_cast<const halfx8 *>(Xl + (c0 + r) * Np + k0 + kc) : halfx8{};
 }
 
-// contiguous rows [r0, r0 + ROWS) of P, valid while < rend
-template <int ROWS>
-__device__ __forceinline__ void stage_rows_range(_Float16 *__restrict__ lds, const _Float16 *__restrict__ P,
-                                                 int64_t rend, int Np, int64_t r0, int k0) {
-  constexpr int kChunks = ROWS * (TKK / 8);
+__device__ __forceinline__ void store_ivf(const IvfFrag &F, _Float16 *sQh, _Float16 *sQl, _Float16 *sCh,
+                                          _Float16 *sCl) {
+  const int kc = (threadIdx.x & 3) * 8;
 #pragma unroll
-  for (int c = 0; c < (kChunks + kKnnThreads - 1) / kKnnThreads; ++c) {
-    const int id = threadIdx.x + kKnnThreads * c;
-    if (kChunks % kKnnThreads == 0 || id < kChunks) {
-      const int r = id >> 2, kc = (id & 3) * 8;
-      halfx8 v = {};
-      if (r0 + r < rend) v = *reinterpret_cast<const halfx8 *>(P + (r0 + r) * Np + k0 + kc);
-      *reinterpret_cast<halfx8 *>(lds + r * HP + kc) = v;
-    }
+  for (int c = 0; c < 2; ++c) {
+    const int r = (threadIdx.x + kKnnThreads * c) >> 2;
+    *reinterpret_cast<halfx8 *>(sQh + r * HP + kc) = F.qh[c];
+    *reinterpret_cast<halfx8 *>(sQl + r * HP + kc) = F.ql[c];
   }
+  const int r = threadIdx.x >> 2;
+  *reinterpret_cast<halfx8 *>(sCh + r * HP + kc) = F.ch;
+  *reinterpret_cast<halfx8 *>(sCl + r * HP + kc) = F.cl;
 }
 
 template <int KP>
@@ -584,6 +535,9 @@ ivf_list_kernel(const float *__restrict__ X, int N, const float *__restrict__ Q,
   for (int p = 0; p < KP; ++p) { ks[p] = FLT_MAX; ki[p] = INT32_MAX; }
 
   const int kq = (lane >> 4) * 8;
+  static_assert(QB * (TKK / 8) == 2 * kKnnThreads && CB * (TKK / 8) == kKnnThreads, "fragment shape");
+  IvfFrag F;
+  if (pbeg < pend) load_ivf(F, Qh, Ql, pq, qbeg, qend, Xh, Xl, pbeg, pend, Np, 0);
   for (int64_t c0 = pbeg; c0 < pend; c0 += CB) {
     floatx4 acc[2][4];
 #pragma unroll
@@ -591,12 +545,18 @@ ivf_list_kernel(const float *__restrict__ X, int N, const float *__restrict__ Q,
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < Np; k0 += TKK) {
+      __syncthreads();   // the previous step's operands, or the previous tile's scores, are consumed
+      store_ivf(F, sQh, sQl, sCh, sCl);
       __syncthreads();
-      stage_rows_indexed<QB>(sQh, Qh, pq, qend, Np, qbeg, k0);
-      stage_rows_indexed<QB>(sQl, Ql, pq, qend, Np, qbeg, k0);
-      stage_rows_range<CB>(sCh, Xh, pend, Np, c0, k0);
-      stage_rows_range<CB>(sCl, Xl, pend, Np, c0, k0);
-      __syncthreads();
+      {  // prefetch the next K slice, or the first of the next tile
+        int64_t nc0 = c0;
+        int nk0 = k0 + TKK;
+        if (nk0 >= Np) {
+          nk0 = 0;
+          nc0 = c0 + CB;
+        }
+        if (nc0 < pend) load_ivf(F, Qh, Ql, pq, qbeg, qend, Xh, Xl, nc0, pend, Np, nk0);
+      }
       halfx8 ah[2], al[2], bh[4], bl[4];
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb) {
