@@ -4,11 +4,15 @@
 // gemm_bf16: C[M][N] = sum_k opA[m][k] opB[k][n]
 //   opA[m][k] = A[m*lda + k]  (ta = 0)  or  A[k*lda + m]  (ta = 1)
 //   opB[k][n] = B[k*ldb + n]  (tb = 0)  or  B[n*ldb + k]  (tb = 1)
-// Tiles of 128 x 128 per block of 256 threads (4 waves, 64 x 64 each), K in
-// steps of 32 staged in LDS with K contiguous per row, so one lane's MFMA
+// Tiles of 128 x 128 per block of 256 threads (4 waves, 64 x 64 each),
+// operands staged in LDS with K contiguous per row, so one lane's MFMA
 // operand (8 consecutive k) is a single 16-byte LDS read.  The instruction
 // is v_mfma_f32_16x16x32_bf16: lane l supplies A[l%16][8(l/16)..+8) and
 // B[8(l/16)..+8)[l%16], and receives D[4(l/16)+r][l%16], r = 0..3.
+// Two kernels: gemm_nt_kernel when both operands are K-contiguous (ta = 0,
+// tb = 1) with 16-byte rows (every GEMM of the training step is arranged
+// so), K steps of 64 double buffered; gemm_kernel for every other layout,
+// K steps of 32.
 // Epilogues: FP32 store (split-K partials: blockIdx.z selects the K range
 // and the output slab), bias + ReLU -> BF16, or (dgrad) multiply by the
 // ReLU derivative read from the forward activation -> BF16.

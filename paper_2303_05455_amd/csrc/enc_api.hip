@@ -11,6 +11,10 @@
 //   dH1  = (dH2 W2) . [H1 > 0]            dW2 = dH2^T H1     db2 = sum dH2
 //                                         dW1 = dH1^T X_b    db1 = sum dH1
 //   Adam on all parameters with the gradients scaled by s, then BF16 copies.
+// The backward GEMMs read feature-major copies ([features][rows], rows
+// padded to a multiple of 8 with zeros) of X_b, H1 and dH2 and produce dH1
+// feature-major, so both operands of every GEMM are K-contiguous; db1 and
+// db2 are row sums of those copies.
 #include <cmath>
 #include <mutex>
 #include <new>
