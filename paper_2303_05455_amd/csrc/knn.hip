@@ -40,7 +40,7 @@ constexpr int QB = 128;        // queries per block
 constexpr int CB = 64;         // candidates per tile
 constexpr int TKK = 32;        // features per staged step
 constexpr int HP = TKK + 8;    // LDS row pitch in halves (80 bytes, 16-byte aligned rows)
-constexpr int SP = CB + 1;     // score tile pitch (floats)
+constexpr int SP = CB + 4;     // score tile pitch (floats; rows 16-byte aligned)
 constexpr int kKnnThreads = 256;
 constexpr int kSplitMaxExp = 14;   // scaled magnitudes stay below 2^14
 
@@ -102,6 +102,31 @@ __global__ void split_kernel(const float *__restrict__ X, int64_t M, int N, int 
   const _Float16 h = (_Float16)x;
   hi[e] = h;
   lo[e] = (_Float16)(x - (float)h);
+}
+
+// Ranks the CW scores of one thread's half row (sS row `row`, candidates
+// cbase..cbase+CW-1, in order) into its list.  A group of four whose
+// smallest score lies above the list's last entry is passed over at once:
+// none of them could enter the list, so the list ends as if each had been
+// offered.  (Lists of 32 keep a one-by-one scan of alternate columns: the
+// group test costs registers they do not have.)
+template <int KP, int CW>
+__device__ __forceinline__ void scan_half_row(const float *__restrict__ row, int64_t cbase, int64_t M,
+                                              int64_t my_self, float (&ks)[KP], int32_t (&ki)[KP]) {
+#pragma unroll 1
+  for (int m = 0; m < CW; m += 4) {
+    floatx4 v = *reinterpret_cast<const floatx4 *>(row + m);
+    const float lo = fminf(fminf(v.x, v.y), fminf(v.z, v.w));
+    if (lo > ks[KP - 1]) continue;
+#pragma unroll 1
+    for (int e = 0; e < 4; ++e) {   // one insertion body, the group rotated through it
+      const float se = v.x;
+      v = v.yzwx;
+      const int64_t c = cbase + m + e;
+      if (c >= M || c == my_self) continue;
+      list_insert<KP>(ks, ki, se, (int32_t)c);
+    }
+  }
 }
 
 // End of a query block: the two running lists of each row are merged
@@ -167,7 +192,7 @@ __device__ __forceinline__ void finish_rows(float *sS, float (&ks)[KP], int32_t 
 // of a 64-candidate tile.  The operand rows of K step s + 1 are loaded into
 // registers during the MFMAs of step s.
 constexpr int CBW = 128;        // candidates per tile (wide kernel)
-constexpr int SPW = CBW + 1;    // its score tile pitch (floats)
+constexpr int SPW = CBW + 4;    // its score tile pitch (floats; rows 16-byte aligned)
 
 struct WideFrag {
   halfx8 qh[2], ql[2], ch[2], cl[2];   // 128 query and 128 candidate rows x 8 features per thread
@@ -226,7 +251,8 @@ knn_kernel(const float *__restrict__ X, int64_t M, int N, const float *__restric
   const int wq = 64 * (wave >> 1), wc = 64 * (wave & 1);
   const int64_t q0 = (int64_t)blockIdx.x * QB;
 
-  // scan ownership: two threads per query row, interleaved columns
+  // scan ownership: two threads per query row (halves of the columns, or
+  // alternate columns for 32-entry lists)
   const int my_row = tid >> 1;
   const int half = tid & 1;
   const int64_t my_q = q0 + my_row;
@@ -300,12 +326,16 @@ knn_kernel(const float *__restrict__ X, int64_t M, int N, const float *__restric
     }
     __syncthreads();
     if (my_q < nq) {
-      for (int m = 0; m < CBW / 2; ++m) {
-        const int col = 2 * m + half;
-        const int64_t c = c0 + col;
-        if (c >= M || c == my_self) continue;
-        list_insert<KP>(ks, ki, sS[my_row * SPW + col], (int32_t)c);
-      }
+      if constexpr (KP >= 32) {
+        for (int m = 0; m < CBW / 2; ++m) {
+          const int col = 2 * m + half;
+          const int64_t c = c0 + col;
+          if (c >= M || c == my_self) continue;
+          list_insert<KP>(ks, ki, sS[my_row * SPW + col], (int32_t)c);
+        }
+      } else
+        scan_half_row<KP, CBW / 2>(sS + my_row * SPW + half * (CBW / 2), c0 + half * (CBW / 2), M, my_self, ks,
+                                   ki);
     }
   }
   finish_rows<KP>(sS, ks, ki, my_row, half, my_q, nq, Q, X, N, k, out_idx, out_dist);
@@ -418,12 +448,15 @@ knn_small_kernel(const float *__restrict__ X, int64_t M, int N, const float *__r
     }
     __syncthreads();   // scores complete; every wave has finished reading the candidate tile
     if (my_q < nq) {
-      for (int m = 0; m < CB / 2; ++m) {
-        const int col = 2 * m + half;
-        const int64_t c = c0 + col;
-        if (c >= M || c == my_self) continue;
-        list_insert<KP>(ks, ki, sS[my_row * SP + col], (int32_t)c);
-      }
+      if constexpr (KP >= 32) {
+        for (int m = 0; m < CB / 2; ++m) {
+          const int col = 2 * m + half;
+          const int64_t c = c0 + col;
+          if (c >= M || c == my_self) continue;
+          list_insert<KP>(ks, ki, sS[my_row * SP + col], (int32_t)c);
+        }
+      } else
+        scan_half_row<KP, CB / 2>(sS + my_row * SP + half * (CB / 2), c0 + half * (CB / 2), M, my_self, ks, ki);
     }
   }
   finish_rows<KP>(sS, ks, ki, my_row, half, my_q, nq, Q, X, N, k, out_idx, out_dist);
