@@ -6,7 +6,7 @@ IVHD edges: each batch holds `batch` source vertices, their nn neighbours
 from the kNN graph and their random neighbours of the epoch, and the loss is
 the binary-distance stress of those edges.  New points are then placed by
 one forward pass (``embed``); plain IVHD (``Context``) serves as fallback and
-as the judge of the result's kNN preservation.
+as the reference layout its kNN preservation is compared with.
 """
 from __future__ import annotations
 
