@@ -44,11 +44,13 @@ def _check_rows(X, rows, got, want, rel=2e-6):
 
 
 # padded widths 32, 64, 96, 128 (register-resident queries; with k + 4 > 16
-# at 128 the general kernel) and 800 (general kernel), every list length
+# at 128 the general kernel) and 224, 800 (general kernel), every list length
+# (k + 4 <= 8, <= 16, <= 32) on both kernels
 @pytest.mark.parametrize("M,N,k,seed", [(3000, 32, 2, 0), (1000, 100, 5, 1), (513, 7, 10, 2),
                                         (200, 784, 20, 3), (777, 2, 3, 4), (40, 16, 28, 5),
                                         (5, 3, 4, 6), (1500, 50, 3, 7), (900, 90, 12, 8),
-                                        (600, 120, 25, 9), (700, 60, 28, 10)])
+                                        (600, 120, 25, 9), (700, 60, 28, 10), (500, 90, 20, 11),
+                                        (1000, 200, 3, 12), (333, 150, 9, 13)])
 def test_knn_build_matches_oracle(ivhd, M, N, k, seed):
     rng = np.random.default_rng(seed)
     X = rng.normal(size=(M, N)).astype(np.float32)
@@ -73,9 +75,10 @@ def test_knn_ties_go_to_the_lower_index(ivhd):
     assert np.array_equal(got, oracle.knn(X, 4))
 
 
-def test_knn_query_with_self_and_distances(ivhd):
+@pytest.mark.parametrize("N", [24, 150])
+def test_knn_query_with_self_and_distances(ivhd, N):
     rng = np.random.default_rng(7)
-    X = rng.normal(size=(2000, 24)).astype(np.float32)
+    X = rng.normal(size=(2000, N)).astype(np.float32)
     rows = rng.choice(2000, 300, replace=False)
     dX = torch.from_numpy(X).cuda()
     idx, dist = ivhd.ivhd_knn_query(dX, dX[torch.from_numpy(rows).cuda()].contiguous(), 6,
