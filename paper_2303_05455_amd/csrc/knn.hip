@@ -493,10 +493,10 @@ __global__ void split_gather_kernel(const float *__restrict__ X, int64_t M, int 
 }
 
 // one K step of the list kernel's operands in registers (loaded a step ahead):
-// 128 query rows (ids pq[qbeg + r] while qbeg + r < qend) and 64 contiguous
+// 128 query rows (ids pq[qbeg + r] while qbeg + r < qend) and 128 contiguous
 // list rows c0 + r while < pend, 8 features per chunk
 struct IvfFrag {
-  halfx8 qh[2], ql[2], ch, cl;
+  halfx8 qh[2], ql[2], ch[2], cl[2];
 };
 
 __device__ __forceinline__ void load_ivf(IvfFrag &F, const _Float16 *__restrict__ Qh,
@@ -511,11 +511,10 @@ __device__ __forceinline__ void load_ivf(IvfFrag &F, const _Float16 *__restrict_
     const int64_t row = ok ? (int64_t)pq[qbeg + r] : 0;
     F.qh[c] = ok ? *reinterpret_cast<const halfx8 *>(Qh + row * Np + k0 + kc) : halfx8{};
     F.ql[c] = ok ? *reinterpret_cast<const halfx8 *>(Ql + row * Np + k0 + kc) : halfx8{};
+    const bool okc = c0 + r < pend;
+    F.ch[c] = okc ? *reinterpret_cast<const halfx8 *>(Xh + (c0 + r) * Np + k0 + kc) : halfx8{};
+    F.cl[c] = okc ? *reinterpret_cast<const halfx8 *>(Xl + (c0 + r) * Np + k0 + kc) : halfx8{};
   }
-  const int r = threadIdx.x >> 2;
-  const bool ok = c0 + r < pend;
-  F.ch = ok ? *reinterpret_cast<const halfx8 *>(Xh + (c0 + r) * Np + k0 + kc) : halfx8{};
-  F.cl = ok ? *reinterpret_cast<const halfx8 *>(Xl + (c0 + r) * Np + k0 + kc) : halfx8{};
 }
 
 __device__ __forceinline__ void store_ivf(const IvfFrag &F, _Float16 *sQh, _Float16 *sQl, _Float16 *sCh,
@@ -526,14 +525,15 @@ __device__ __forceinline__ void store_ivf(const IvfFrag &F, _Float16 *sQh, _Floa
     const int r = (threadIdx.x + kKnnThreads * c) >> 2;
     *reinterpret_cast<halfx8 *>(sQh + r * HP + kc) = F.qh[c];
     *reinterpret_cast<halfx8 *>(sQl + r * HP + kc) = F.ql[c];
+    *reinterpret_cast<halfx8 *>(sCh + r * HP + kc) = F.ch[c];
+    *reinterpret_cast<halfx8 *>(sCl + r * HP + kc) = F.cl[c];
   }
-  const int r = threadIdx.x >> 2;
-  *reinterpret_cast<halfx8 *>(sCh + r * HP + kc) = F.ch;
-  *reinterpret_cast<halfx8 *>(sCl + r * HP + kc) = F.cl;
 }
 
+// the list kernel tiles like knn_kernel: 128 queries x 128 list points per
+// tile, each wave a 64 x 64 quarter
 template <int KP>
-__global__ void __launch_bounds__(kKnnThreads)
+__global__ void __launch_bounds__(kKnnThreads, 2)
 ivf_list_kernel(const float *__restrict__ X, int N, const float *__restrict__ Q, const _Float16 *__restrict__ Xh,
                 const _Float16 *__restrict__ Xl, const _Float16 *__restrict__ Qh, const _Float16 *__restrict__ Ql,
                 int Np, float inv_scale2, const float *__restrict__ pnorm, const int32_t *__restrict__ pos_id,
@@ -541,16 +541,18 @@ ivf_list_kernel(const float *__restrict__ X, int N, const float *__restrict__ Q,
                 const int32_t *__restrict__ work_list, const int32_t *__restrict__ work_chunk,
                 const int32_t *__restrict__ probes, int nprobe, const int32_t *__restrict__ self, int k,
                 int32_t *__restrict__ part_idx, float *__restrict__ part_dist) {
-  __shared__ __attribute__((aligned(16))) float smem[QB * SP];
+  __shared__ __attribute__((aligned(16))) float smem[QB * SPW];
+  static_assert((2 * QB + 2 * CBW) * HP * 2 <= QB * SPW * 4, "operand tiles must fit in the score tile");
   _Float16 *sQh = reinterpret_cast<_Float16 *>(smem);
   _Float16 *sQl = sQh + QB * HP;
   _Float16 *sCh = sQl + QB * HP;
-  _Float16 *sCl = sCh + CB * HP;
+  _Float16 *sCl = sCh + CBW * HP;
   float *sS = smem;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
+  const int wq = 64 * (wave >> 1), wc = 64 * (wave & 1);
   const int32_t c = work_list[blockIdx.x];
   const int64_t qbeg = (int64_t)pptr[c] + (int64_t)work_chunk[blockIdx.x] * QB;
   const int64_t qend = pptr[c + 1];
@@ -568,13 +570,13 @@ ivf_list_kernel(const float *__restrict__ X, int N, const float *__restrict__ Q,
   for (int p = 0; p < KP; ++p) { ks[p] = FLT_MAX; ki[p] = INT32_MAX; }
 
   const int kq = (lane >> 4) * 8;
-  static_assert(QB * (TKK / 8) == 2 * kKnnThreads && CB * (TKK / 8) == kKnnThreads, "fragment shape");
+  static_assert(QB * (TKK / 8) == 2 * kKnnThreads && CBW * (TKK / 8) == 2 * kKnnThreads, "fragment shape");
   IvfFrag F;
   if (pbeg < pend) load_ivf(F, Qh, Ql, pq, qbeg, qend, Xh, Xl, pbeg, pend, Np, 0);
-  for (int64_t c0 = pbeg; c0 < pend; c0 += CB) {
-    floatx4 acc[2][4];
+  for (int64_t c0 = pbeg; c0 < pend; c0 += CBW) {
+    floatx4 acc[4][4];
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < Np; k0 += TKK) {
@@ -586,53 +588,51 @@ ivf_list_kernel(const float *__restrict__ X, int N, const float *__restrict__ Q,
         int nk0 = k0 + TKK;
         if (nk0 >= Np) {
           nk0 = 0;
-          nc0 = c0 + CB;
+          nc0 = c0 + CBW;
         }
         if (nc0 < pend) load_ivf(F, Qh, Ql, pq, qbeg, qend, Xh, Xl, nc0, pend, Np, nk0);
       }
-      halfx8 ah[2], al[2], bh[4], bl[4];
+      halfx8 ah[4], al[4];
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb) {
-        const int r = 32 * wave + 16 * rb + (lane & 15);
+      for (int rb = 0; rb < 4; ++rb) {
+        const int r = wq + 16 * rb + (lane & 15);
         ah[rb] = *reinterpret_cast<const halfx8 *>(sQh + r * HP + kq);
         al[rb] = *reinterpret_cast<const halfx8 *>(sQl + r * HP + kq);
       }
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) {
-        const int r = 16 * cb + (lane & 15);
-        bh[cb] = *reinterpret_cast<const halfx8 *>(sCh + r * HP + kq);
-        bl[cb] = *reinterpret_cast<const halfx8 *>(sCl + r * HP + kq);
-      }
+        const int r = wc + 16 * cb + (lane & 15);
+        const halfx8 bh = *reinterpret_cast<const halfx8 *>(sCh + r * HP + kq);
+        const halfx8 bl = *reinterpret_cast<const halfx8 *>(sCl + r * HP + kq);
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[rb], bh[cb], acc[rb][cb], 0, 0, 0);
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[rb], bl[cb], acc[rb][cb], 0, 0, 0);
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[rb], bh[cb], acc[rb][cb], 0, 0, 0);
+        for (int rb = 0; rb < 4; ++rb) {
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[rb], bh, acc[rb][cb], 0, 0, 0);
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[rb], bl, acc[rb][cb], 0, 0, 0);
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[rb], bh, acc[rb][cb], 0, 0, 0);
         }
+      }
     }
     __syncthreads();
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) {
-      const int col = 16 * cb + (lane & 15);
+      const int col = wc + 16 * cb + (lane & 15);
       const float cn = c0 + col < pend ? pnorm[c0 + col] : 0.f;
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
+      for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = 32 * wave + 16 * rb + 4 * (lane >> 4) + r;
-          sS[row * SP + col] = cn - 2.f * (acc[rb][cb][r] * inv_scale2);
+          const int row = wq + 16 * rb + 4 * (lane >> 4) + r;
+          sS[row * SPW + col] = cn - 2.f * (acc[rb][cb][r] * inv_scale2);
         }
     }
     __syncthreads();
     if (have_q) {
-      for (int m = 0; m < CB / 2; ++m) {
+      for (int m = 0; m < CBW / 2; ++m) {
         const int col = 2 * m + half;
         if (c0 + col >= pend) continue;
         const int32_t id = pos_id[c0 + col];
         if (id == my_self) continue;
-        list_insert<KP>(ks, ki, sS[my_row * SP + col], id);
+        list_insert<KP>(ks, ki, sS[my_row * SPW + col], id);
       }
     }
   }
@@ -648,31 +648,64 @@ ivf_list_kernel(const float *__restrict__ X, int N, const float *__restrict__ Q,
   if (half == 0 && have_q) {
 #pragma unroll
     for (int p = 0; p < KP; ++p) list_insert<KP>(ks, ki, mS[my_row * KP + p], mI[my_row * KP + p]);
-    float *rs = mS + my_row * KP;
-    int32_t *ri = mI + my_row * KP;
-    const float *qrow = Q + (int64_t)my_q * N;
+  }
+  __syncthreads();   // the other half's list has been read
+  if (half == 0) {
 #pragma unroll
-    for (int p = 0; p < KP; ++p) ri[p] = ki[p];
+    for (int p = 0; p < KP; ++p) mI[my_row * KP + p] = have_q ? ki[p] : INT32_MAX;
+  }
+  __syncthreads();
+  // exact FP32 distances of every row's survivors, spread over the whole
+  // block (a list holds few points, so this is a large share of the work);
+  // features in order, 16-byte loads where the rows allow
+  const bool vec4 = N % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0 &&
+                    (reinterpret_cast<uintptr_t>(Q) & 15) == 0;
 #pragma unroll 1
-    for (int p = 0; p < KP; ++p) {
-      const int32_t id = ri[p];
-      float d = FLT_MAX;
-      if (id != INT32_MAX) {
-        const float *xr = X + (int64_t)id * N;
-        d = 0.f;
+  for (int t = tid; t < QB * KP; t += kKnnThreads) {
+    const int32_t id = mI[t];
+    float d = FLT_MAX;
+    if (id != INT32_MAX) {
+      const float *qr = Q + (int64_t)pq[qbeg + t / KP] * N, *xr = X + (int64_t)id * N;
+      d = 0.f;
+      if (vec4) {
+        for (int kk = 0; kk < N; kk += 4) {
+          const float4 u = *reinterpret_cast<const float4 *>(qr + kk);
+          const float4 v = *reinterpret_cast<const float4 *>(xr + kk);
+          float e = u.x - v.x;
+          d += e * e;
+          e = u.y - v.y;
+          d += e * e;
+          e = u.z - v.z;
+          d += e * e;
+          e = u.w - v.w;
+          d += e * e;
+        }
+      } else {
         for (int kk = 0; kk < N; ++kk) {
-          const float t = qrow[kk] - xr[kk];
-          d += t * t;
+          const float e = qr[kk] - xr[kk];
+          d += e * e;
         }
       }
+    }
+    mS[t] = d;
+  }
+  __syncthreads();
+  if (half == 0 && have_q) {
+    float *rs = mS + my_row * KP;
+    int32_t *ri = mI + my_row * KP;
+    // the row's survivors sorted by (distance, id)
+#pragma unroll 1
+    for (int p = 1; p < KP; ++p) {
+      const float dv = rs[p];
+      const int32_t iv = ri[p];
       int q = p;
-      while (q > 0 && pair_less(d, id, rs[q - 1], ri[q - 1])) {
+      while (q > 0 && pair_less(dv, iv, rs[q - 1], ri[q - 1])) {
         rs[q] = rs[q - 1];
         ri[q] = ri[q - 1];
         --q;
       }
-      rs[q] = d;
-      ri[q] = id;
+      rs[q] = dv;
+      ri[q] = iv;
     }
     // this list's probe slot of the query
     int slot = 0;
