@@ -129,9 +129,70 @@ __device__ __forceinline__ void scan_half_row(const float *__restrict__ row, int
   }
 }
 
+// Exact FP32 squared distances of a block's (row, survivor) pairs: mI
+// [QB][KP] holds the survivors' ids (INT32_MAX: none), mS receives the
+// distances; the pairs are spread over the whole block, the features taken in
+// order with 16-byte loads where the rows allow.  qrow_of(r) is the query
+// row of block row r.
+template <int KP, typename QRowOf>
+__device__ __forceinline__ void rerank_pairs(float *__restrict__ mS, const int32_t *__restrict__ mI,
+                                             const float *__restrict__ Q, const float *__restrict__ X, int N,
+                                             QRowOf qrow_of) {
+  const bool vec4 = N % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0 &&
+                    (reinterpret_cast<uintptr_t>(Q) & 15) == 0;
+#pragma unroll 1
+  for (int t = threadIdx.x; t < QB * KP; t += kKnnThreads) {
+    const int32_t id = mI[t];
+    float d = FLT_MAX;
+    if (id != INT32_MAX) {
+      const float *qr = Q + qrow_of(t / KP) * N, *xr = X + (int64_t)id * N;
+      d = 0.f;
+      if (vec4) {
+        for (int kk = 0; kk < N; kk += 4) {
+          const float4 u = *reinterpret_cast<const float4 *>(qr + kk);
+          const float4 v = *reinterpret_cast<const float4 *>(xr + kk);
+          float e = u.x - v.x;
+          d += e * e;
+          e = u.y - v.y;
+          d += e * e;
+          e = u.z - v.z;
+          d += e * e;
+          e = u.w - v.w;
+          d += e * e;
+        }
+      } else {
+        for (int kk = 0; kk < N; ++kk) {
+          const float e = qr[kk] - xr[kk];
+          d += e * e;
+        }
+      }
+    }
+    mS[t] = d;
+  }
+}
+
+// a row's KP (distance, id) pairs sorted in place, ascending
+template <int KP>
+__device__ __forceinline__ void sort_row(float *__restrict__ rs, int32_t *__restrict__ ri) {
+#pragma unroll 1
+  for (int p = 1; p < KP; ++p) {
+    const float dv = rs[p];
+    const int32_t iv = ri[p];
+    int q = p;
+    while (q > 0 && pair_less(dv, iv, rs[q - 1], ri[q - 1])) {
+      rs[q] = rs[q - 1];
+      ri[q] = ri[q - 1];
+      --q;
+    }
+    rs[q] = dv;
+    ri[q] = iv;
+  }
+}
+
 // End of a query block: the two running lists of each row are merged
 // (through LDS, sS holding at least 2 QB KP words), the survivors are
-// re-ranked by their exact FP32 distances and the best k written out.
+// re-ranked by their exact FP32 distances (the whole block computing them)
+// and the best k written out.
 template <int KP>
 __device__ __forceinline__ void finish_rows(float *sS, float (&ks)[KP], int32_t (&ki)[KP], int my_row, int half,
                                             int64_t my_q, int64_t nq, const float *__restrict__ Q,
@@ -148,36 +209,20 @@ __device__ __forceinline__ void finish_rows(float *sS, float (&ks)[KP], int32_t 
   if (half == 0 && my_q < nq) {
 #pragma unroll
     for (int p = 0; p < KP; ++p) list_insert<KP>(ks, ki, mS[my_row * KP + p], mI[my_row * KP + p]);
-    // exact FP32 distances of the survivors, sorted in this row's LDS slots
-    // (a rolled loop: unrolled it would hold 3 KP values in registers for the
-    // whole kernel and cut its occupancy)
+  }
+  __syncthreads();   // the other half's list has been read
+  if (half == 0) {
+#pragma unroll
+    for (int p = 0; p < KP; ++p) mI[my_row * KP + p] = my_q < nq ? ki[p] : INT32_MAX;
+  }
+  __syncthreads();
+  const int64_t q0 = my_q - my_row;
+  rerank_pairs<KP>(mS, mI, Q, X, N, [&](int r) { return q0 + r; });
+  __syncthreads();
+  if (half == 0 && my_q < nq) {
     float *rs = mS + my_row * KP;
     int32_t *ri = mI + my_row * KP;
-    const float *qrow = Q + my_q * N;
-#pragma unroll
-    for (int p = 0; p < KP; ++p) ri[p] = ki[p];
-#pragma unroll 1
-    for (int p = 0; p < KP; ++p) {
-      const int32_t c = ri[p];
-      float d = FLT_MAX;
-      if (c != INT32_MAX) {
-        const float *xr = X + (int64_t)c * N;
-        d = 0.f;
-        for (int kk = 0; kk < N; ++kk) {
-          const float t = qrow[kk] - xr[kk];
-          d += t * t;
-        }
-      }
-      // insertion into the sorted prefix rs[0..p)
-      int q = p;
-      while (q > 0 && pair_less(d, c, rs[q - 1], ri[q - 1])) {
-        rs[q] = rs[q - 1];
-        ri[q] = ri[q - 1];
-        --q;
-      }
-      rs[q] = d;
-      ri[q] = c;
-    }
+    sort_row<KP>(rs, ri);
 #pragma unroll 1
     for (int p = 0; p < k; ++p) {
       out_idx[my_q * k + p] = ri[p] == INT32_MAX ? -1 : ri[p];
@@ -655,58 +700,14 @@ ivf_list_kernel(const float *__restrict__ X, int N, const float *__restrict__ Q,
     for (int p = 0; p < KP; ++p) mI[my_row * KP + p] = have_q ? ki[p] : INT32_MAX;
   }
   __syncthreads();
-  // exact FP32 distances of every row's survivors, spread over the whole
-  // block (a list holds few points, so this is a large share of the work);
-  // features in order, 16-byte loads where the rows allow
-  const bool vec4 = N % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0 &&
-                    (reinterpret_cast<uintptr_t>(Q) & 15) == 0;
-#pragma unroll 1
-  for (int t = tid; t < QB * KP; t += kKnnThreads) {
-    const int32_t id = mI[t];
-    float d = FLT_MAX;
-    if (id != INT32_MAX) {
-      const float *qr = Q + (int64_t)pq[qbeg + t / KP] * N, *xr = X + (int64_t)id * N;
-      d = 0.f;
-      if (vec4) {
-        for (int kk = 0; kk < N; kk += 4) {
-          const float4 u = *reinterpret_cast<const float4 *>(qr + kk);
-          const float4 v = *reinterpret_cast<const float4 *>(xr + kk);
-          float e = u.x - v.x;
-          d += e * e;
-          e = u.y - v.y;
-          d += e * e;
-          e = u.z - v.z;
-          d += e * e;
-          e = u.w - v.w;
-          d += e * e;
-        }
-      } else {
-        for (int kk = 0; kk < N; ++kk) {
-          const float e = qr[kk] - xr[kk];
-          d += e * e;
-        }
-      }
-    }
-    mS[t] = d;
-  }
+  // exact FP32 distances of every row's survivors over the whole block (a
+  // list holds few points, so this is a large share of the work)
+  rerank_pairs<KP>(mS, mI, Q, X, N, [&](int r) { return (int64_t)pq[qbeg + r]; });
   __syncthreads();
   if (half == 0 && have_q) {
     float *rs = mS + my_row * KP;
     int32_t *ri = mI + my_row * KP;
-    // the row's survivors sorted by (distance, id)
-#pragma unroll 1
-    for (int p = 1; p < KP; ++p) {
-      const float dv = rs[p];
-      const int32_t iv = ri[p];
-      int q = p;
-      while (q > 0 && pair_less(dv, iv, rs[q - 1], ri[q - 1])) {
-        rs[q] = rs[q - 1];
-        ri[q] = ri[q - 1];
-        --q;
-      }
-      rs[q] = dv;
-      ri[q] = iv;
-    }
+    sort_row<KP>(rs, ri);
     // this list's probe slot of the query
     int slot = 0;
     for (int p = 0; p < nprobe; ++p)
