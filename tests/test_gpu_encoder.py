@@ -69,6 +69,34 @@ def test_gemm_matches_fp64_on_identical_bf16_operands(pkg, M, N, K, ta, tb, epi,
         assert np.all(np.abs(got - want) <= tol)
 
 
+@pytest.mark.parametrize("epi", [0, 1, 2])
+def test_gemm_on_operands_not_16_byte_aligned(pkg, epi):
+    # K-contiguous operands whose base sits 2 bytes past a 16-byte boundary:
+    # the element-wise staging must give the same bound as the vector path
+    m, api, _, _ = pkg
+    M, N, K = 200, 72, 96
+    rng = np.random.default_rng(epi + 40)
+    A = mlp.bf16_round(rng.normal(size=(M, K)))
+    B = mlp.bf16_round(rng.normal(size=(N, K)))
+    ref = A @ B.T
+    bound = np.abs(A) @ np.abs(B.T)
+    bias = rng.normal(size=N).astype(np.float32)
+    mask = mlp.bf16_round(rng.normal(size=(M, N)))
+    a_buf = _bits(np.concatenate([[0.0], A.ravel()]))   # element 1 onwards: 2 bytes past the base
+    b_buf = _bits(np.concatenate([[0.0], B.ravel()]))
+    out = api.ivhd_gemm_bf16(a_buf[1:], b_buf[1:], M, N, K, lda=K, ldb=K, trans_a=False, trans_b=True,
+                             epilogue=epi, bias=torch.from_numpy(bias).cuda() if epi == 1 else None,
+                             mask=_bits(mask) if epi == 2 else None, ldm=N)
+    torch.cuda.synchronize()
+    if epi == 0:
+        assert np.all(np.abs(out.cpu().numpy().astype(np.float64) - ref) <= 1e-5 * bound + 1e-30)
+    else:
+        got = mlp.from_bf16_bits(out.cpu().numpy())
+        want = np.maximum(ref + bias, 0) if epi == 1 else np.where(mask > 0, ref, 0.0)
+        tol = 1e-5 * (bound + np.abs(bias) if epi == 1 else bound) + 2.0 ** -8 * np.abs(want) + 1e-30
+        assert np.all(np.abs(got - want) <= tol)
+
+
 def _setup(pkg, n_in, h1, h2, B, nn, rn, seed):
     m, api, ag, par = pkg
     rng = np.random.default_rng(seed)
