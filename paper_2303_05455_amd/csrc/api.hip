@@ -116,7 +116,7 @@ void free_ctx(ivhd_ctx *c) {
     if (c->g_chunk[k]) (void)hipGraphExecDestroy(c->g_chunk[k]);
   }
   void *bufs[] = {c->perm, c->inv, c->nn_own, c->ya, c->yb, c->v, c->tmp, c->nn_csc.ptr, c->nn_csc.src,
-                  c->rn_csc.ptr, c->rn_csc.src, c->sc.cnt, c->sc.tmp, c->sc.part, c->sc.big, c->rn_idx,
+                  c->rn_csc.ptr, c->rn_csc.src, c->sc.cnt, c->sc.tmp, c->sc.part, c->sc.big, c->sc.rank, c->rn_idx,
                   c->epoch, c->flags, c->fbuf, c->heavy, c->partials, c->d_E, c->ha, c->hb, c->vb,
                   c->adapt, c->ke_part, c->s2, c->adam};
   for (void *b : bufs)
@@ -193,11 +193,11 @@ int enqueue_draw(ivhd_ctx *c, hipStream_t s) {
   int32_t *cnt = c->det() ? c->sc.cnt : nullptr;
   HIPCHK(launch_epoch_begin(c->epoch, cnt, M, c->flags, s));
   HIPCHK(launch_rn_sample(c->nn_user, M, c->p.nn, c->p.rn, c->p.seed, c->epoch, c->perm, c->inv, c->rn_idx, cnt,
-                          s));
+                          c->det() ? c->sc.rank : nullptr, s));
   if (c->det()) {
     HIPCHK(launch_scan(c->sc.cnt, M, c->sc.part, c->rn_csc.ptr, s));
-    HIPCHK(launch_scatter_sort(c->rn_idx, M, c->p.rn, c->rn_csc.ptr, c->sc.cnt, c->sc.tmp, c->sc.big, c->flags,
-                               c->rn_csc.src, s));
+    HIPCHK(launch_place_sort(c->rn_idx, M, c->p.rn, c->rn_csc.ptr, c->sc.rank, c->sc.tmp, c->sc.big, c->flags,
+                             c->rn_csc.src, s));
   }
   return IVHD_OK;
 }
@@ -423,6 +423,7 @@ int ivhd_init(ivhd_ctx **out, const ivhd_params *p, const int32_t *d_nn_idx, flo
     if (p->mode == IVHD_MODE_DET) {
       ALLOC(c->rn_csc.ptr, M + 1, "rn in-edge offsets");
       ALLOC(c->rn_csc.src, M * p->rn, "rn in-edge sources");
+      ALLOC(c->sc.rank, M * p->rn, "rn arrival ranks");
     }
   }
   if (p->mode == IVHD_MODE_ATOMIC) ALLOC(c->fbuf, M, "force accumulator");

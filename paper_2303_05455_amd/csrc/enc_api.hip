@@ -420,7 +420,7 @@ int ivhd_enc_train_epoch(ivhd_enc *e, const uint16_t *d_x16, int64_t M, const in
   // the epoch's random neighbours (same draw as the loop's, epoch = training epoch)
   if (rn > 0) {
     HIPCHK(hipMemcpyAsync(e->d_epoch, &epoch, sizeof epoch, hipMemcpyHostToDevice, s));
-    HIPCHK(launch_rn_sample(d_nn_idx, M, nn, rn, seed, e->d_epoch, nullptr, nullptr, e->rn_all, nullptr, s));
+    HIPCHK(launch_rn_sample(d_nn_idx, M, nn, rn, seed, e->d_epoch, nullptr, nullptr, e->rn_all, nullptr, nullptr, s));
     HIPCHK(hipStreamSynchronize(s));   // epoch lives on the host stack
   }
   // visiting order: s_b = (a b + c0) mod M with gcd(a, M) = 1, a bijection

@@ -56,7 +56,8 @@ __global__ void epoch_begin_kernel(int64_t *epoch, int32_t *cnt, int64_t M, int3
 __global__ void rn_sample_kernel(const int32_t *__restrict__ nn_idx, int64_t M, int nn, int rn,
                                  uint64_t seed, const int64_t *__restrict__ epoch_p,
                                  const int32_t *__restrict__ perm, const int32_t *__restrict__ inv,
-                                 int32_t *__restrict__ rn_idx, int32_t *__restrict__ cnt) {
+                                 int32_t *__restrict__ rn_idx, int32_t *__restrict__ cnt,
+                                 int32_t *__restrict__ rank) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= M) return;
   const int64_t i = perm ? (int64_t)perm[p] : p;
@@ -77,7 +78,10 @@ __global__ void rn_sample_kernel(const int32_t *__restrict__ nn_idx, int64_t M, 
       if (!clash) break;
     }
     rn_idx[p * rn + r] = pick;
-    if (cnt) atomicAdd(&cnt[pick], 1);
+    if (cnt) {
+      const int32_t before = atomicAdd(&cnt[pick], 1);
+      if (rank) rank[p * rn + r] = before;
+    }
   }
 }
 
@@ -264,6 +268,17 @@ __global__ void scatter_kernel(const int32_t *__restrict__ idx, int64_t M, int k
   tmp[slot] = (int32_t)(e / k);
 }
 
+// tmp[ptr[j] + rank[e]] = e / k for every edge e -> j (slots distinct by
+// construction of the ranks)
+__global__ void place_kernel(const int32_t *__restrict__ idx, int64_t M, int k, const int32_t *__restrict__ ptr,
+                             const int32_t *__restrict__ rank, int32_t *__restrict__ tmp) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * k) return;
+  const int32_t j = idx[e];
+  if (j < 0) return;
+  tmp[ptr[j] + rank[e]] = (int32_t)(e / k);
+}
+
 __global__ void sort_small_kernel(const int32_t *__restrict__ ptr, const int32_t *__restrict__ tmp,
                                   int64_t M, int32_t *__restrict__ big, int32_t *flags,
                                   int32_t *__restrict__ out) {
@@ -342,9 +357,9 @@ hipError_t launch_epoch_begin(int64_t *epoch, int32_t *cnt, int64_t M, int32_t *
 
 hipError_t launch_rn_sample(const int32_t *nn_idx, int64_t M, int nn, int rn, uint64_t seed,
                             const int64_t *epoch, const int32_t *perm, const int32_t *inv, int32_t *rn_idx,
-                            int32_t *cnt, hipStream_t s) {
+                            int32_t *cnt, int32_t *rank, hipStream_t s) {
   if (rn == 0) return hipSuccess;
-  rn_sample_kernel<<<grid_for(M), kBlock, 0, s>>>(nn_idx, M, nn, rn, seed, epoch, perm, inv, rn_idx, cnt);
+  rn_sample_kernel<<<grid_for(M), kBlock, 0, s>>>(nn_idx, M, nn, rn, seed, epoch, perm, inv, rn_idx, cnt, rank);
   return hipGetLastError();
 }
 
@@ -420,6 +435,15 @@ hipError_t launch_transpose(const int32_t *idx, int64_t rows, int k, int64_t nta
   if (e != hipSuccess) return e;
   scatter_kernel<<<grid_for(rows * k), kBlock, 0, s>>>(idx, rows, k, cnt, tmp);
   sort_small_kernel<<<grid_for(ntargets), kBlock, 0, s>>>(ptr, tmp, ntargets, big, flags, src_out);
+  sort_big_kernel<<<kBigSortBlocks, kBlock, 0, s>>>(ptr, tmp, big, flags, src_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_place_sort(const int32_t *idx, int64_t M, int k, const int32_t *ptr, const int32_t *rank,
+                             int32_t *tmp, int32_t *big, int32_t *flags, int32_t *src_out, hipStream_t s) {
+  if (k == 0) return hipSuccess;
+  place_kernel<<<grid_for(M * k), kBlock, 0, s>>>(idx, M, k, ptr, rank, tmp);
+  sort_small_kernel<<<grid_for(M), kBlock, 0, s>>>(ptr, tmp, M, big, flags, src_out);
   sort_big_kernel<<<kBigSortBlocks, kBlock, 0, s>>>(ptr, tmp, big, flags, src_out);
   return hipGetLastError();
 }

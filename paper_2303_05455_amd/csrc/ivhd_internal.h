@@ -64,6 +64,7 @@ struct CscScratch {
   int32_t *tmp = nullptr;        // [capacity]: unsorted sources
   int32_t *part = nullptr;       // [ceil((M+1)/kScanChunk)] block partial sums
   int32_t *big = nullptr;        // [M]: targets with a segment above kSmallSegment
+  int32_t *rank = nullptr;       // [M*rn]: each rn draw's arrival rank among its target's in-edges
 };
 
 // ---- graph.hip ----
@@ -73,10 +74,12 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t value, hipStream_t s);
 // Begins a random-neighbour epoch: epoch += 1; when cnt != NULL zeroes cnt[0..M] and flags[FLAG_BIG_COUNT].
 hipError_t launch_epoch_begin(int64_t *epoch, int32_t *cnt, int64_t M, int32_t *flags, hipStream_t s);
 // rn draw for epoch *epoch (caller ids; with perm/inv stored as internal ids in
-// internal row order); when cnt != NULL also counts in-degrees into cnt.
+// internal row order); when cnt != NULL also counts in-degrees into cnt and,
+// when rank != NULL, stores each draw's arrival rank at its target (the
+// count before it).
 hipError_t launch_rn_sample(const int32_t *nn_idx, int64_t M, int nn, int rn, uint64_t seed,
                             const int64_t *epoch, const int32_t *perm, const int32_t *inv, int32_t *rn_idx,
-                            int32_t *cnt, hipStream_t s);
+                            int32_t *cnt, int32_t *rank, hipStream_t s);
 // connected components (parent -> smallest id of the component)
 hipError_t launch_cc_init(int32_t *parent, int64_t M, hipStream_t s);
 hipError_t launch_cc_round(const int32_t *nn_idx, int64_t M, int nn, int32_t *parent, int32_t *changed,
@@ -102,6 +105,10 @@ hipError_t launch_range_check(const int32_t *idx, int64_t n, int32_t hi, int32_t
 hipError_t launch_transpose(const int32_t *idx, int64_t rows, int k, int64_t ntargets, int32_t *ptr, int32_t *cnt,
                             int32_t *part, int32_t *tmp, int32_t *big, int32_t *flags, int32_t *src_out,
                             hipStream_t s);
+// Placement by arrival rank (tmp[ptr[j] + rank[e]] = source of edge e, no
+// atomics) + canonical sort: src_out segments end sorted ascending.
+hipError_t launch_place_sort(const int32_t *idx, int64_t M, int k, const int32_t *ptr, const int32_t *rank,
+                             int32_t *tmp, int32_t *big, int32_t *flags, int32_t *src_out, hipStream_t s);
 // Scatter + canonical sort: csc.src segments end sorted ascending.
 hipError_t launch_scatter_sort(const int32_t *idx, int64_t M, int k, const int32_t *ptr,
                                int32_t *cursor, int32_t *tmp, int32_t *big, int32_t *flags,
