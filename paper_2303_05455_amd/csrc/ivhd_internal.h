@@ -15,7 +15,8 @@ constexpr int kScanChunk = kBlock * kScanItems;
 constexpr int kSmallSegment = 32;    // in-edge segments up to this size are sorted per thread
 constexpr int kBigSortBlocks = 256;  // blocks that share the list of large segments
 constexpr int kHeavyDegree = 24;     // nn in-degree above which a vertex gets a whole wavefront
-constexpr int kHeavyPerBlock = kBlock / 64;
+constexpr int kDetBlock = 64;        // threads per block of the deterministic step kernel (one wavefront)
+constexpr int kHeavyPerBlock = kDetBlock / 64;
 constexpr int kXcds = 8;             // MI355X: 8 XCDs, workgroups dealt round-robin
 
 // device flag slots
@@ -160,7 +161,7 @@ struct StepArgs {
   const int32_t *heavy;   // vertices whose nn in-degree exceeds kHeavyDegree
   int32_t n_heavy;
   int32_t heavy_blocks;   // leading blocks of a launch that serve the heavy vertices (multiple of kXcds)
-  int32_t light_tiles;    // tiles of kBlock consecutive vertices
+  int32_t light_tiles;    // tiles of kDetBlock consecutive vertices
   int32_t tiles_per_xcd;  // consecutive tiles given to each XCD
   int64_t M;
   int nn, rn;
@@ -172,7 +173,7 @@ struct StepArgs {
 inline void set_launch_shape(StepArgs &a) {
   const int32_t hb = (a.n_heavy + kHeavyPerBlock - 1) / kHeavyPerBlock;
   a.heavy_blocks = (hb + kXcds - 1) / kXcds * kXcds;
-  a.light_tiles = (int32_t)((a.M + kBlock - 1) / kBlock);
+  a.light_tiles = (int32_t)((a.M + kDetBlock - 1) / kDetBlock);
   a.tiles_per_xcd = (a.light_tiles + kXcds - 1) / kXcds;
 }
 unsigned det_grid(const StepArgs &a);   // blocks of one deterministic launch

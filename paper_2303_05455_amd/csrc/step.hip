@@ -200,12 +200,12 @@ __device__ __forceinline__ double apply_update(const StepArgs &A, int64_t i, flo
   return 0.0;
 }
 
-// fixed-order block sum of one double per thread (256 threads)
+// fixed-order block sum of one double per thread (kDetBlock threads)
 __device__ __forceinline__ void block_sum_store(double x, double *out) {
-  __shared__ double lds[kBlock];
+  __shared__ double lds[kDetBlock];
   lds[threadIdx.x] = x;
   __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
+  for (int s = kDetBlock / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
     __syncthreads();
   }
@@ -216,7 +216,7 @@ __device__ __forceinline__ void block_sum_store(double x, double *out) {
 // A.h = A.y; otherwise one iteration (force + update).  No thread leaves
 // before the ADAPT block sum.
 template <bool GRAD, bool L1, int OPT>
-__global__ void __launch_bounds__(kBlock) det_kernel(StepArgs A, float2 *out) {
+__global__ void __launch_bounds__(kDetBlock) det_kernel(StepArgs A, float2 *out) {
   double ke = 0.0;
   if ((int32_t)blockIdx.x < A.heavy_blocks) {
     const int lane = threadIdx.x & 63;
@@ -240,7 +240,7 @@ __global__ void __launch_bounds__(kBlock) det_kernel(StepArgs A, float2 *out) {
     // keeping the positions its vertices gather from in its own L2
     const int32_t lb = (int32_t)blockIdx.x - A.heavy_blocks;
     const int32_t tile = (lb % kXcds) * A.tiles_per_xcd + lb / kXcds;
-    const int64_t i = (int64_t)tile * kBlock + threadIdx.x;
+    const int64_t i = (int64_t)tile * kDetBlock + threadIdx.x;
     if (tile < A.light_tiles && i < A.M) {
       const int32_t ns = A.nn_ptr[i], ne = A.nn_ptr[i + 1];
       if (ne - ns <= kHeavyDegree) {   // else served by a heavy wavefront
@@ -337,6 +337,8 @@ __global__ void __launch_bounds__(kDecideThreads) adapt_decide_kernel(const doub
                                                                       AdaptState *st) {
   __shared__ double lds[kDecideThreads];
   double x = 0.0;
+  // the loads of eight terms fly together; they are still added in order
+#pragma unroll 8
   for (int p = threadIdx.x; p < nparts; p += kDecideThreads) x += part[p];
   lds[threadIdx.x] = x;
   __syncthreads();
@@ -406,10 +408,10 @@ hipError_t launch_heavy_list(const int32_t *nn_ptr, int64_t M, int32_t *list, in
 template <bool L1>
 void launch_det_opt(const StepArgs &a, unsigned g, hipStream_t s) {
   switch (a.opt) {
-    case OPT_NEST: det_kernel<false, L1, OPT_NEST><<<g, kBlock, 0, s>>>(a, nullptr); break;
-    case OPT_ADAPT: det_kernel<false, L1, OPT_ADAPT><<<g, kBlock, 0, s>>>(a, nullptr); break;
-    case OPT_ADAM: det_kernel<false, L1, OPT_ADAM><<<g, kBlock, 0, s>>>(a, nullptr); break;
-    default: det_kernel<false, L1, OPT_PLAIN><<<g, kBlock, 0, s>>>(a, nullptr); break;
+    case OPT_NEST: det_kernel<false, L1, OPT_NEST><<<g, kDetBlock, 0, s>>>(a, nullptr); break;
+    case OPT_ADAPT: det_kernel<false, L1, OPT_ADAPT><<<g, kDetBlock, 0, s>>>(a, nullptr); break;
+    case OPT_ADAM: det_kernel<false, L1, OPT_ADAM><<<g, kDetBlock, 0, s>>>(a, nullptr); break;
+    default: det_kernel<false, L1, OPT_PLAIN><<<g, kDetBlock, 0, s>>>(a, nullptr); break;
   }
 }
 
@@ -428,8 +430,8 @@ hipError_t launch_step_atomic(const StepArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_grad_det(const StepArgs &a, float2 *out, hipStream_t s) {
-  if (a.l1) det_kernel<true, true, OPT_PLAIN><<<det_grid(a), kBlock, 0, s>>>(a, out);
-  else det_kernel<true, false, OPT_PLAIN><<<det_grid(a), kBlock, 0, s>>>(a, out);
+  if (a.l1) det_kernel<true, true, OPT_PLAIN><<<det_grid(a), kDetBlock, 0, s>>>(a, out);
+  else det_kernel<true, false, OPT_PLAIN><<<det_grid(a), kDetBlock, 0, s>>>(a, out);
   return hipGetLastError();
 }
 
