@@ -46,7 +46,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
-STEP_SOURCE = os.path.join(ROOT, "paper_2303_05455_amd", "csrc", "step.hip")
+# the det step kernel's source and the constants that shape its launch (block
+# size, hub threshold, vertex order): the stored traffic figure belongs to them
+STEP_SOURCES = [os.path.join(ROOT, "paper_2303_05455_amd", "csrc", f) for f in ("step.hip", "ivhd_internal.h",
+                                                                              "order.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_det_C3_traffic.md")
 METRIC = "edge-updates/sec (M·(nn+rn)·iters/s) at M=1.4M + achieved HBM GB/s"
 # adaptive-b threshold on |dT| (the kinetic energy change per step), per point
@@ -59,8 +62,11 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def source_digest(path=None) -> str:
-    return hashlib.sha1(open(path or STEP_SOURCE, "rb").read()).hexdigest()[:12]
+def source_digest(paths=None) -> str:
+    h = hashlib.sha1()
+    for p in (paths or STEP_SOURCES):
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:12]
 
 
 def stored_traffic():

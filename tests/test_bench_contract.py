@@ -32,9 +32,9 @@ def test_stored_traffic_belongs_to_the_current_kernel(tmp_path, monkeypatch):
     src = tmp_path / "step.hip"
     src.write_text("// kernel source\n")
     prof = tmp_path / "traffic.md"
-    monkeypatch.setattr(bench, "STEP_SOURCE", str(src))
+    monkeypatch.setattr(bench, "STEP_SOURCES", [str(src)])
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(prof))
-    prof.write_text(f"source_sha1: {bench.source_digest(str(src))}\nhbm_bytes_per_launch: 4.5e+08\n")
+    prof.write_text(f"source_sha1: {bench.source_digest([str(src)])}\nhbm_bytes_per_launch: 4.5e+08\n")
     assert bench.stored_traffic() == pytest.approx(4.5e8)
     src.write_text("// kernel source, edited\n")
     assert bench.stored_traffic() is None
@@ -44,4 +44,4 @@ def test_stored_traffic_belongs_to_the_current_kernel(tmp_path, monkeypatch):
 
 def test_committed_traffic_profile_matches_the_step_kernel():
     import bench
-    assert bench.stored_traffic() is not None, "profiles/step_det_C3_traffic.md is stale for csrc/step.hip"
+    assert bench.stored_traffic() is not None, "profiles/step_det_C3_traffic.md is stale for the det kernel"
