@@ -21,7 +21,8 @@
 //     kHeavyDegree a whole wavefront: the 64 lanes stride over its edge list
 //     and a fixed xor-butterfly adds their partial sums;
 //   * the other blocks give each remaining vertex one thread, which issues
-//     its in-edge gathers four at a time so several loads are in flight.
+//     its in-edge gathers eight (then four) at a time so several loads are
+//     in flight.
 // Both orders of summation are fixed, so results are bitwise reproducible.
 //
 // Atomic mode: pass 1, one thread per vertex, walks its out-edges, keeps its
@@ -74,13 +75,26 @@ __device__ __forceinline__ float2 rn_term(float2 yi, float2 yo, float c, float e
   return make_float2(s * dx, s * dy);
 }
 
-// in-edge segment [s, e) of a light vertex, four gathers in flight at a time;
-// the terms are still added one by one in ascending order
+// in-edge segment [s, e) of a light vertex, eight (then four) gathers in
+// flight at a time; the terms are still added one by one in ascending order
 template <bool RN, bool L1>
 __device__ __forceinline__ void gather_segment(const float2 *__restrict__ y, const int32_t *__restrict__ src,
                                                int32_t s, int32_t e, float2 yi, float c, float eps,
                                                float &fx, float &fy) {
   int32_t p = s;
+  for (; p + 8 <= e; p += 8) {
+    int32_t j[8];
+    float2 yv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) j[u] = src[p + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) yv[u] = y[j[u]];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const float2 t = RN ? rn_term<L1>(yi, yv[u], c, eps) : nn_term<L1>(yi, yv[u]);
+      fx += t.x; fy += t.y;
+    }
+  }
   for (; p + 4 <= e; p += 4) {
     const int32_t j0 = src[p], j1 = src[p + 1], j2 = src[p + 2], j3 = src[p + 3];
     const float2 y0 = y[j0], y1 = y[j1], y2 = y[j2], y3 = y[j3];
