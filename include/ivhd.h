@@ -61,7 +61,7 @@ typedef enum ivhd_mode {
 /* ivhd_params.flags */
 #define IVHD_FLAG_REORDER 1   /* keep the vertices internally grouped by connected
                                  component of the nn graph (smallest id first), and
-                                 inside a component by nn in-degree capped at 41,
+                                 inside a component by nn in-degree capped at 81,
                                  ties by id (a locality and load-balance order; the
                                  results are the same up to floating-point summation
                                  order, and the caller always sees its own order)  */

@@ -14,7 +14,7 @@ constexpr int kScanItems = 8;        // items per thread in the block scan
 constexpr int kScanChunk = kBlock * kScanItems;
 constexpr int kSmallSegment = 32;    // in-edge segments up to this size are sorted per thread
 constexpr int kBigSortBlocks = 256;  // blocks that share the list of large segments
-constexpr int kHeavyDegree = 40;     // nn in-degree above which a vertex gets a whole wavefront
+constexpr int kHeavyDegree = 80;     // nn in-degree above which a vertex gets a whole wavefront
 constexpr int kDetBlock = 64;        // threads per block of the deterministic step kernel (one wavefront)
 constexpr int kHeavyPerBlock = kDetBlock / 64;
 constexpr int kXcds = 8;             // MI355X: 8 XCDs, workgroups dealt round-robin

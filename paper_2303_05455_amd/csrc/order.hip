@@ -13,7 +13,7 @@
 // keeps every nn gather of a tile inside one component's stretch of Y, which
 // the XCD-aware tile mapping of the step kernel then keeps in one L2.
 //
-// The order is a stable LSD radix sort of the key (root << 6) | capped degree
+// The order is a stable LSD radix sort of the key (root << 7) | capped degree
 // over the ids 0..M-1, so it is a pure function of the nn lists.
 #include <hipcub/hipcub.hpp>
 
@@ -22,7 +22,7 @@
 namespace ivhd {
 namespace {
 
-constexpr int kDegreeBits = 6;
+constexpr int kDegreeBits = 7;
 static_assert(kHeavyDegree + 1 < (1 << kDegreeBits), "degree cap must fit the key's low bits");
 
 __global__ void order_keys_kernel(const int32_t *__restrict__ root, const int32_t *__restrict__ indeg,
