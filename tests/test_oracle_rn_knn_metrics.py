@@ -131,3 +131,84 @@ def test_knn_gain_is_zero_for_identical_neighbourhoods():
     rng = np.random.default_rng(10)
     X = rng.normal(size=(100, 2)); lab = rng.integers(0, 3, 100)
     assert oracle.g_nn(X, X, lab, 5) == 0.0
+
+
+def _coranking_q_nx(X, Y):
+    """Q_NX(k) for every k from the co-ranking matrix (Lee and Verleysen
+    2009): Q[a, b] counts the pairs (i, j) whose rank is a in X and b in Y;
+    Q_NX(k) is the sum of its top-left k x k block over kM.  Ranks by pure
+    Python loops, ties broken by index as in the rank definition."""
+    M = len(X)
+
+    def ranks(Z):
+        Z = np.asarray(Z, dtype=np.float64)
+        d = [[float(((Z[i] - Z[j]) ** 2).sum()) for j in range(M)] for i in range(M)]
+        return [[sum(1 for l in range(M) if d[i][l] < d[i][j] or (d[i][l] == d[i][j] and l < j))
+                 for j in range(M)] for i in range(M)]
+    rX, rY = ranks(X), ranks(Y)
+    Q = np.zeros((M, M), dtype=np.int64)
+    for i in range(M):
+        for j in range(M):
+            if i != j:
+                Q[rX[i][j], rY[i][j]] += 1
+    return [Q[1:k + 1, 1:k + 1].sum() / (k * M) for k in range(M)]
+
+
+def test_auc_of_a_hand_computed_four_point_layout():
+    # X = 0, 1, 3, 7 on a line; Y swaps the places of points 1 and 2.
+    # k = 1: the nearest neighbours are {1}, {0}, {1}, {2} in X and {2}, {2}, {0}, {1}
+    #        in Y, no agreement: Q = 0, R = (3 * 0 - 1) / (3 - 1) = -1/2.
+    # k = 2: both sides give {1,2}, {0,2}, {0,1}, {1,2}: Q = 1, R = (3 - 2) / (3 - 2) = 1.
+    # AUC = (R(1)/1 + R(2)/2) / (1 + 1/2) = 0.  Weights k (0.5), equal weights
+    # (0.25), N in place of N - 1 in R (1/3) or a range up to k = N - 1 all differ.
+    X = np.array([[0.0], [1.0], [3.0], [7.0]])
+    Y = np.array([[0.0], [3.0], [1.0], [7.0]])
+    assert oracle.q_nx(X, Y, 1) == 0.0 and oracle.q_nx(X, Y, 2) == 1.0
+    assert oracle.auc_rnx(X, Y) == pytest.approx(0.0, abs=1e-15)
+    # one more point (x = y = 15) so that the value is not zero.  Orders by hand:
+    # k = 1: X {1},{0},{1},{2},{3}, Y {2},{2},{0},{1},{3}: one agreement, Q = 1/5,
+    #        R = (4/5 - 1) / 3 = -1/15;
+    # k = 2: agreements 2, 2, 2, 2, 1: Q = 9/10, R = (18/5 - 2) / 2 = 4/5;
+    # k = 3: every set agrees: Q = 1, R = 1.
+    # AUC = (-1/15 + 4/10 + 1/3) / (1 + 1/2 + 1/3) = (2/3) / (11/6) = 4/11.
+    X5 = np.array([[0.0], [1.0], [3.0], [7.0], [15.0]])
+    Y5 = np.array([[0.0], [3.0], [1.0], [7.0], [15.0]])
+    assert [oracle.q_nx(X5, Y5, k) for k in (1, 2, 3)] == pytest.approx([0.2, 0.9, 1.0], abs=1e-15)
+    assert oracle.auc_rnx(X5, Y5) == pytest.approx(4 / 11, abs=1e-15)
+
+
+def test_auc_matches_the_coranking_matrix_on_random_layouts():
+    rng = np.random.default_rng(11)
+    for M in (9, 14):
+        X = rng.normal(size=(M, 4))
+        Y = X[:, :2] + 0.7 * rng.normal(size=(M, 2))
+        q = _coranking_q_nx(X, Y)
+        num = sum(((M - 1) * q[k] - k) / (M - 1 - k) / k for k in range(1, M - 1))
+        den = sum(1.0 / k for k in range(1, M - 1))
+        assert oracle.auc_rnx(X, Y) == pytest.approx(num / den, abs=1e-13)
+        for k in (1, 3, M - 2):
+            assert oracle.q_nx(X, Y, k) == pytest.approx(q[k], abs=1e-15)
+
+
+def test_auc_of_random_layouts_is_near_zero():
+    rng = np.random.default_rng(12)
+    X = rng.normal(size=(30, 3))
+    aucs = [oracle.auc_rnx(X, rng.normal(size=(30, 2))) for _ in range(20)]
+    assert abs(np.mean(aucs)) < 0.05
+    # a layout that keeps the structure scores well above that
+    assert oracle.auc_rnx(X, X[:, :2]) > 0.3
+
+
+def test_knn_gain_of_a_hand_computed_layout():
+    # X = 0, 1, 3, 7 with classes A, B, A, B: the nearest neighbour of every
+    # point is of the other class.  Y = 0, 10, 1, 11 pairs each point with its
+    # own class.  k = 1: every point gains one same-class neighbour, G = +1.
+    # k = 2: same-class counts are 1, 0, 1, 1 in X and 1, 1, 1, 1 in Y, so
+    # G = (0 + 1 + 0 + 0) / 4 / 2 = 1/8.  Exchanging X and Y flips the sign.
+    X = np.array([[0.0], [1.0], [3.0], [7.0]])
+    Y = np.array([[0.0, 0.0], [10.0, 0.0], [1.0, 0.0], [11.0, 0.0]])
+    lab = np.array([0, 1, 0, 1])
+    assert oracle.g_nn(X, Y, lab, 1) == 1.0
+    assert oracle.g_nn(X, Y, lab, 2) == 0.125
+    assert oracle.g_nn(Y, X, lab, 1) == -1.0
+    assert oracle.g_nn(Y, X, lab, 2) == -0.125
