@@ -34,7 +34,7 @@ _LIB_PATH = os.path.join(_HERE, "libivhd_oracle.so")
 _lock = threading.Lock()
 _lib = None
 
-GCC_FLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math"]
+GCC_FLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-fno-fast-math"]
 
 
 def build(force: bool = True) -> str:
@@ -70,6 +70,8 @@ def _load():
         lib.orc_run.argtypes = [i64, vp, vp, i32, vp, i32, vp, dbl, dbl, dbl, dbl, u64,
                                 i64, i64, i64, i32, i32, vp, vp]
         lib.orc_run.restype = None
+        lib.orc_run_threads.argtypes = lib.orc_run.argtypes + [i32]
+        lib.orc_run_threads.restype = None
         lib.orc_run_adaptive.argtypes = [i64, vp, vp, i32, vp, i32, vp, dbl, vp, dbl, dbl, u64,
                                          i64, i64, i64, dbl, dbl, dbl, i32, vp, vp, vp, vp,
                                          vp, vp]
@@ -160,9 +162,12 @@ def step(Y, V, f, a: float, b: float):
 
 def run(Y0, V0, nn_idx, *, rn: int, a: float, b: float, c: float, eps: float = 1e-12,
         seed: int = 0, R: int = 0, n0: int = 0, T: int = 1, nesterov: bool = False,
-        metric: str = "l2"):
+        metric: str = "l2", threads: int = 0):
     """T iterations of the loop from (Y0, V0) at iteration n0 (with
     ``nesterov`` the force is taken at Y + a V).
+
+    ``threads`` > 0 runs the same iterations on that many OpenMP threads
+    (per-vertex gather in edge order: the same result bit for bit).
 
     Returns (Y, V, rn_idx) in FP64; rn_idx is the last epoch's draw.
     """
@@ -173,9 +178,12 @@ def run(Y0, V0, nn_idx, *, rn: int, a: float, b: float, c: float, eps: float = 1
     rn_idx = np.zeros((M, rn), dtype=np.int32)
     f = np.empty((M, 2), dtype=np.float64)
     Yh = np.empty((M, 2), dtype=np.float64)
-    _load().orc_run(M, _ptr(Y), _ptr(V), nn, _ptr(nn_idx), rn, _ptr(rn_idx), a, b, c, eps,
-                    seed & 0xFFFFFFFFFFFFFFFF, R, n0, T, int(nesterov), METRICS[metric],
-                    _ptr(f), _ptr(Yh))
+    args = (M, _ptr(Y), _ptr(V), nn, _ptr(nn_idx), rn, _ptr(rn_idx), a, b, c, eps,
+            seed & 0xFFFFFFFFFFFFFFFF, R, n0, T, int(nesterov), METRICS[metric], _ptr(f), _ptr(Yh))
+    if threads > 0:
+        _load().orc_run_threads(*args, int(threads))
+    else:
+        _load().orc_run(*args)
     return Y, V, rn_idx
 
 

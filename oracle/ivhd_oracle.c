@@ -53,9 +53,19 @@
  *            OOPSLA 2014; Vigna's public-domain reference), keyed by
  *            (seed, epoch, vertex, slot, try).
  *
- * Build: gcc -O2 -std=c11 -fPIC -shared -ffp-contract=off -fno-fast-math
+ * Threaded loop (orc_run_threads): the same iterations with the force of
+ * each step gathered per vertex by OpenMP threads.  Vertex v adds the terms
+ * of its incident edges in the order of the edge list above (source row,
+ * then slot), which is exactly the order in which orc_force adds them to
+ * f[v]; each term is computed from the same operands in the same order, so
+ * the result equals orc_run bit for bit for any thread count.  It exists
+ * only to time the oracle on every host core.
+ *
+ * Build: gcc -O2 -std=c11 -fPIC -shared -fopenmp -ffp-contract=off -fno-fast-math
  */
 #include <math.h>
+#include <omp.h>
+#include <stdlib.h>
 #include <stddef.h>
 #include <stdint.h>
 #include <string.h>
@@ -283,4 +293,117 @@ void orc_run_adam(int64_t M, double *Y, double *Mo, double *S, int32_t nn, const
             Y[i] = Y[i] - lr * (Mo[i] / c1) / (eps_a + sqrt(S[i] / c2));
         }
     }
+}
+
+/* Incidence lists of the edges of one draw: for every vertex v, the ids of
+ * the edges that touch it, ascending.  Edge id = row * (nn + rn) + slot,
+ * slots 0..nn-1 for nn, nn..nn+rn-1 for rn; absent slots are left out.
+ * ptr: M + 1 entries, ids: 2 * M * (nn + rn) entries.                    */
+static void incidence(int64_t M, int32_t nn, const int32_t *nn_idx, int32_t rn,
+                      const int32_t *rn_idx, int64_t *ptr, int64_t *ids)
+{
+    const int64_t w = nn + rn;
+    for (int64_t v = 0; v <= M; ++v) ptr[v] = 0;
+    for (int64_t i = 0; i < M; ++i)
+        for (int32_t q = 0; q < w; ++q) {
+            int64_t o = q < nn ? nn_idx[i * nn + q] : rn_idx[i * rn + (q - nn)];
+            if (o < 0) continue;
+            ptr[i + 1] += 1;
+            ptr[o + 1] += 1;
+        }
+    for (int64_t v = 0; v < M; ++v) ptr[v + 1] += ptr[v];
+    int64_t *fill = (int64_t *)malloc((size_t)M * sizeof(int64_t));
+    for (int64_t v = 0; v < M; ++v) fill[v] = ptr[v];
+    /* edges visited in id order, so every list ends up ascending */
+    for (int64_t i = 0; i < M; ++i)
+        for (int32_t q = 0; q < w; ++q) {
+            int64_t o = q < nn ? nn_idx[i * nn + q] : rn_idx[i * rn + (q - nn)];
+            if (o < 0) continue;
+            ids[fill[i]++] = i * w + q;
+            ids[fill[o]++] = i * w + q;
+        }
+    free(fill);
+}
+
+/* f = -1/2 grad E by a per-vertex gather over the incidence lists: the
+ * term F of edge (i, o) is computed as in orc_force and added at i,
+ * subtracted at o.                                                        */
+static void force_gather(int64_t M, const double *Y, int32_t nn, const int32_t *nn_idx,
+                         int32_t rn, const int32_t *rn_idx, double c, double eps,
+                         int32_t metric, const int64_t *ptr, const int64_t *ids, double *f)
+{
+    const int64_t w = nn + rn;
+#pragma omp parallel for schedule(static)
+    for (int64_t v = 0; v < M; ++v) {
+        double fx = 0.0, fy = 0.0;
+        for (int64_t p = ptr[v]; p < ptr[v + 1]; ++p) {
+            const int64_t e = ids[p], i = e / w;
+            const int32_t q = (int32_t)(e % w);
+            const int rnd = q >= nn;
+            const int64_t o = rnd ? rn_idx[i * rn + (q - nn)] : nn_idx[i * nn + q];
+            double dx = Y[2 * i] - Y[2 * o];
+            double dy = Y[2 * i + 1] - Y[2 * o + 1];
+            double Fx, Fy;
+            if (!rnd) {
+                if (metric == 0) {
+                    Fx = -dx;
+                    Fy = -dy;
+                } else {
+                    double d = fabs(dx) + fabs(dy);
+                    Fx = -d * sgn(dx);
+                    Fy = -d * sgn(dy);
+                }
+            } else if (metric == 0) {
+                double d = sqrt(dx * dx + dy * dy);
+                double s = c * (1.0 - d) / (d > eps ? d : eps);
+                Fx = s * dx;
+                Fy = s * dy;
+            } else {
+                double d = fabs(dx) + fabs(dy);
+                Fx = c * (1.0 - d) * sgn(dx);
+                Fy = c * (1.0 - d) * sgn(dy);
+            }
+            if (i == v) {
+                fx += Fx;
+                fy += Fy;
+            } else {
+                fx -= Fx;
+                fy -= Fy;
+            }
+        }
+        f[2 * v] = fx;
+        f[2 * v + 1] = fy;
+    }
+}
+
+/* orc_run on nthreads OpenMP threads (same arguments, same result). */
+void orc_run_threads(int64_t M, double *Y, double *V, int32_t nn, const int32_t *nn_idx,
+                     int32_t rn, int32_t *rn_idx, double a, double b, double c, double eps,
+                     uint64_t seed, int64_t R, int64_t n0, int64_t T, int32_t nesterov,
+                     int32_t metric, double *f, double *Yh, int32_t nthreads)
+{
+    const int64_t cap = 2 * M * (int64_t)(nn + rn);
+    int64_t *ptr = (int64_t *)malloc((size_t)(M + 1) * sizeof(int64_t));
+    int64_t *ids = (int64_t *)malloc((size_t)(cap > 0 ? cap : 1) * sizeof(int64_t));
+    omp_set_num_threads(nthreads > 0 ? nthreads : 1);
+    for (int64_t n = n0; n < n0 + T; ++n) {
+        if (n == n0 || (R > 0 && n % R == 0)) {
+            orc_rn_sample(M, nn, nn_idx, rn, seed, R > 0 ? n / R : 0, rn_idx);
+            incidence(M, nn, nn_idx, rn, rn_idx, ptr, ids);
+        }
+        const double *Yf = Y;
+        if (nesterov) {
+#pragma omp parallel for schedule(static)
+            for (int64_t i = 0; i < 2 * M; ++i) Yh[i] = Y[i] + a * V[i];
+            Yf = Yh;
+        }
+        force_gather(M, Yf, nn, nn_idx, rn, rn_idx, c, eps, metric, ptr, ids, f);
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < 2 * M; ++i) {
+            V[i] = a * V[i] + b * f[i];
+            Y[i] = Y[i] + V[i];
+        }
+    }
+    free(ptr);
+    free(ids);
 }
