@@ -14,8 +14,9 @@ The JSON line also carries
                 with HIP events around back-to-back launches, against 8 TB/s;
                 `traffic` = HBM-side bytes per launch from rocprofv3 counters
                 when profiles/ holds figures taken on the current kernel source
-  cpu_baseline  the FP64 oracle (plain C, one thread) timed on a bounded
-                sample of the same workload shape (N = 1 only)
+  cpu_baseline  the FP64 oracle (plain C) timed on a bounded sample of the
+                same workload shape, on every host thread and on one
+                (N = 1 only)
 
 Other workloads (one JSON line each, not the headline):
   --config C2   the loop at the MNIST shape (70,000 x 784, nn = 5)
@@ -94,7 +95,19 @@ def events():
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
+def host_threads() -> int:
+    """Threads the oracle may use: OMP_NUM_THREADS when set, else the CPUs
+    this process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    return len(os.sched_getaffinity(0))
+
+
 def cpu_baseline(cfg, iters, seed=0):
+    """The FP64 oracle loop timed on the host: one thread over ``iters``
+    iterations and every host thread (the threaded loop, equal to the
+    one-thread loop bit for bit) over 4 * ``iters``."""
     import oracle
     import synth
     rng = np.random.default_rng([seed, cfg.cfg_id, 99])
@@ -103,18 +116,29 @@ def cpu_baseline(cfg, iters, seed=0):
     nn_idx = synth.random_neighbour_graph(cfg.M, cfg.nn, rng, labels=labels, hub_alpha=1.2)
     Y0 = synth.init_positions(cfg.M, rng)
     oracle.build(force=False)
+    kw = dict(rn=cfg.rn, a=cfg.a, b=cfg.b, c=cfg.c, seed=cfg.seed, R=cfg.R)
+    V0 = np.zeros_like(Y0, dtype=np.float64)
     t0 = time.perf_counter()
-    oracle.run(Y0, np.zeros_like(Y0, dtype=np.float64), nn_idx, rn=cfg.rn, a=cfg.a, b=cfg.b,
-               c=cfg.c, seed=cfg.seed, R=cfg.R, T=iters)
-    dt = time.perf_counter() - t0
+    oracle.run(Y0, V0, nn_idx, T=iters, **kw)
+    dt1 = time.perf_counter() - t0
+    nt = host_threads()
+    iters_n = 4 * iters
+    t0 = time.perf_counter()
+    oracle.run(Y0, V0, nn_idx, T=iters_n, threads=nt, **kw)
+    dtn = time.perf_counter() - t0
+    shape = (f"at M={cfg.M:,}, nn={cfg.nn}, rn={cfg.rn}, R={cfg.R} on a same-shape synthetic graph "
+             f"(in-cluster targets with Pareto popularity; the oracle never takes the GPU's kNN graph)")
     return {
-        "value": cfg.M * (cfg.nn + cfg.rn) * iters / dt,
+        "value": cfg.M * (cfg.nn + cfg.rn) * iters_n / dtn,
         "unit": "edge-updates/s",
-        "cores": 1,
+        "cores": nt,
         "kind": "oracle",
-        "sample": (f"plain-C FP64 oracle loop, one thread, {iters} of the {cfg.T} iterations at "
-                   f"M={cfg.M:,}, nn={cfg.nn}, rn={cfg.rn}, R={cfg.R} on a same-shape synthetic "
-                   f"graph ({dt:.1f} s)"),
+        "sample": (f"plain-C FP64 oracle loop on {nt} OpenMP threads (per-vertex gather, bitwise equal to "
+                   f"the one-thread loop), {iters_n} of the {cfg.T} iterations {shape} ({dtn:.1f} s)"),
+        "one_thread": {
+            "value": cfg.M * (cfg.nn + cfg.rn) * iters / dt1, "unit": "edge-updates/s", "cores": 1,
+            "sample": f"the one-thread edge-by-edge loop, {iters} iterations, same graph ({dt1:.1f} s)",
+        },
     }
 
 
@@ -565,7 +589,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="C3")
     ap.add_argument("--mode", default="both", choices=["det", "atomic", "both"])
-    ap.add_argument("--cpu-iters", type=int, default=200)
+    ap.add_argument("--cpu-iters", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the Nesterov / l1 / adaptive lines")
     ap.add_argument("--no-graphs", action="store_true")

@@ -86,10 +86,10 @@ uint64_t orc_splitmix64(uint64_t x)
  *     j   = h mod (M - 1), shifted past i (so j != i, uniform on the rest)
  * A try is rejected when j is an nn out-neighbour of i or was already drawn
  * for i; the try with t = 255 is accepted whatever it gives.            */
-void orc_rn_sample(int64_t M, int32_t nn, const int32_t *nn_idx, int32_t rn,
-                   uint64_t seed, int64_t epoch, int32_t *rn_out)
+static void rn_sample_rows(int64_t M, int32_t nn, const int32_t *nn_idx, int32_t rn,
+                           uint64_t seed, int64_t epoch, int32_t *rn_out, int64_t i0, int64_t i1)
 {
-    for (int64_t i = 0; i < M; ++i) {
+    for (int64_t i = i0; i < i1; ++i) {
         for (int32_t r = 0; r < rn; ++r) {
             int64_t pick = -1;
             for (int t = 0; t < 256; ++t) {
@@ -109,6 +109,12 @@ void orc_rn_sample(int64_t M, int32_t nn, const int32_t *nn_idx, int32_t rn,
             rn_out[i * rn + r] = (int32_t)pick;
         }
     }
+}
+
+void orc_rn_sample(int64_t M, int32_t nn, const int32_t *nn_idx, int32_t rn,
+                   uint64_t seed, int64_t epoch, int32_t *rn_out)
+{
+    rn_sample_rows(M, nn, nn_idx, rn, seed, epoch, rn_out, 0, M);
 }
 
 static double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
@@ -388,7 +394,12 @@ void orc_run_threads(int64_t M, double *Y, double *V, int32_t nn, const int32_t 
     omp_set_num_threads(nthreads > 0 ? nthreads : 1);
     for (int64_t n = n0; n < n0 + T; ++n) {
         if (n == n0 || (R > 0 && n % R == 0)) {
-            orc_rn_sample(M, nn, nn_idx, rn, seed, R > 0 ? n / R : 0, rn_idx);
+            /* every vertex's draw is a function of (seed, epoch, vertex) alone */
+            const int64_t chunk = 4096;
+#pragma omp parallel for schedule(static)
+            for (int64_t i0 = 0; i0 < M; i0 += chunk)
+                rn_sample_rows(M, nn, nn_idx, rn, seed, R > 0 ? n / R : 0, rn_idx, i0,
+                               i0 + chunk < M ? i0 + chunk : M);
             incidence(M, nn, nn_idx, rn, rn_idx, ptr, ids);
         }
         const double *Yf = Y;
