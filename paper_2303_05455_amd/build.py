@@ -1,9 +1,11 @@
 """Compile the HIP sources of libivhd for gfx950 (in place, next to this file).
 
-    python -m paper_2303_05455_amd.build
+    python -m paper_2303_05455_amd.build [--incremental]
 
 Every .hip file under csrc/ is compiled to an object in _build/ (in
-parallel), then linked into ``libivhd.so``.  Packed-FP32 instruction
+parallel), then linked into ``libivhd.so``.  ``--incremental`` recompiles
+only the sources whose object is older than the source or than any header
+(csrc/*.h, include/*.h).  Packed-FP32 instruction
 selection is disabled on purpose (``-packed-fp32-ops``).
 """
 from __future__ import annotations
@@ -39,11 +41,26 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def _stale(src: str, newest_header: float) -> bool:
+    obj = os.path.join(BUILD, os.path.basename(src).replace(".hip", ".o"))
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return t < os.path.getmtime(src) or t < newest_header
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     sources = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(sources))) as ex:
-        objs = list(ex.map(_compile, sources))
+    todo = sources
+    if incremental:
+        headers = glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
+        newest = max((os.path.getmtime(h) for h in headers), default=0.0)
+        todo = [s for s in sources if _stale(s, newest)]
+    if todo:
+        with cf.ThreadPoolExecutor(max_workers=min(8, len(todo))) as ex:
+            list(ex.map(_compile, todo))
+    objs = [os.path.join(BUILD, os.path.basename(s).replace(".hip", ".o")) for s in sources]
     tmp = LIB + f".tmp{os.getpid()}"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -56,5 +73,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv[1:])
     sys.exit(0)
