@@ -242,6 +242,21 @@ int ivhd_grad_edges(const float *d_y, int64_t M, const int32_t *d_nn_idx, int32_
                     const int32_t *d_rn_idx, int32_t rn, float c, float eps, float *d_grad,
                     double *h_E, void *stream);
 
+/* ivhd_grad_edges_noalloc: ivhd_grad_edges for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, same kernels and the
+ * same results bit for bit; it calls no hipMalloc or hipFree.  Its
+ * temporaries (transposed lists, hub list, flags, FP64 stress partials)
+ * live in one 64 MiB device array per GPU that the library holds until the
+ * process ends.  Limit: about 4 (5 + nn + rn + max(nn, rn)) M bytes must
+ * fit in 64 MiB (M up to about 1,670,000 at nn = 2, rn = 1, and 1,040,000
+ * at nn = 5, rn = 1); larger inputs get IVHD_EINVAL before any device work.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one
+ * GPU (from other threads or streams) race.  Synchronises the stream.     */
+int ivhd_grad_edges_noalloc(const float *d_y, int64_t M, const int32_t *d_nn_idx, int32_t nn,
+                            const int32_t *d_rn_idx, int32_t rn, float c, float eps, float *d_grad,
+                            double *h_E, void *stream);
+
 /* ---- input preparation: exact kNN graph (brute force, FP32) ------------- */
 
 /* ivhd_knn_build: the nn nearest neighbours of every row of X, the kNN graph

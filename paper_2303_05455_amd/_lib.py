@@ -54,6 +54,7 @@ SIGNATURES = {
     "ivhd_edges_grad": (i32, [vp, vp, f32, f32, vp, vp]),
     "ivhd_edges_destroy": (i32, [vp]),
     "ivhd_grad_edges": (i32, [vp, i64, vp, i32, vp, i32, f32, f32, vp, ctypes.POINTER(f64), vp]),
+    "ivhd_grad_edges_noalloc": (i32, [vp, i64, vp, i32, vp, i32, f32, f32, vp, ctypes.POINTER(f64), vp]),
     "ivhd_enc_create": (i32, [ctypes.POINTER(vp), i32, i32, i32, u64, i64, vp]),
     "ivhd_enc_num_params": (i32, [vp, ctypes.POINTER(i64)]),
     "ivhd_enc_get_params": (i32, [vp, vp, vp]),

@@ -22,7 +22,8 @@ __all__ = [
     "ivhd_get_rn", "ivhd_get_in_edges", "ivhd_get_order", "ivhd_set_state", "ivhd_set_iteration",
     "ivhd_get_iteration", "ivhd_set_graphs", "ivhd_destroy", "ivhd_last_error",
     "ivhd_version", "ivhd_knn_build", "ivhd_knn_query", "ivhd_edges_create", "ivhd_edges_stress",
-    "ivhd_edges_grad", "ivhd_edges_destroy", "ivhd_grad_edges", "ivhd_set_adaptive",
+    "ivhd_edges_grad", "ivhd_edges_destroy", "ivhd_grad_edges", "ivhd_grad_edges_noalloc",
+    "ivhd_set_adaptive",
     "ivhd_get_adaptive", "ivhd_rnn_mask", "ivhd_set_adam", "ivhd_ivf_train", "ivhd_ivf_search",
     "ivf_knn_graph",
 ]
@@ -217,6 +218,27 @@ def ivhd_grad_edges(y: torch.Tensor, nn_idx: torch.Tensor, rn_idx: Optional[torc
     check(_lib.load().ivhd_grad_edges(p_y, M, p_nn, nn, p_rn, rn, float(c), float(eps),
                                       _dev(out, torch.float32, (M, 2), "out"),
                                       ctypes.byref(E) if with_stress else None, _stream_handle(stream)))
+    return (out, E.value) if with_stress else out
+
+
+def ivhd_grad_edges_noalloc(y: torch.Tensor, nn_idx: torch.Tensor, rn_idx: Optional[torch.Tensor], c: float,
+                            eps: float = 1e-12, out: Optional[torch.Tensor] = None, with_stress: bool = False,
+                            stream: Optional[torch.cuda.Stream] = None):
+    """ivhd_grad_edges with the library's fixed per-GPU scratch instead of
+    temporary allocations (out must be given: this call allocates nothing)."""
+    M, nn = nn_idx.shape
+    p_y = _dev(y, torch.float32, (M, 2), "y")
+    p_nn = _dev(nn_idx, torch.int32, (M, nn), "nn_idx")
+    rn, p_rn = 0, None
+    if rn_idx is not None and rn_idx.numel():
+        rn = rn_idx.shape[1]
+        p_rn = _dev(rn_idx, torch.int32, (M, rn), "rn_idx")
+    if out is None:
+        raise ValueError("out must be given (ivhd_grad_edges_noalloc allocates nothing)")
+    E = ctypes.c_double()
+    check(_lib.load().ivhd_grad_edges_noalloc(p_y, M, p_nn, nn, p_rn, rn, float(c), float(eps),
+                                              _dev(out, torch.float32, (M, 2), "out"),
+                                              ctypes.byref(E) if with_stress else None, _stream_handle(stream)))
     return (out, E.value) if with_stress else out
 
 

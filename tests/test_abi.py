@@ -127,3 +127,21 @@ def test_rnn_mask_rejects_null_and_aliased_buffers(lib):
     assert lib.ivhd_rnn_mask(None, 100, 2, FAKE, 8, FAKE, None) == -1
     assert lib.ivhd_rnn_mask(FAKE, 100, 2, FAKE, 8, FAKE, None) == -1
     assert "alias" in lib.ivhd_last_error().decode()
+
+
+@pytest.mark.parametrize("M,nn,rn,frag", [
+    (1, 2, 1, "M ="), (100, 0, 1, "nn ="), (100, 2, 65, "rn ="),
+    (2_000_000, 2, 1, "above the 67108864-byte limit"), (1_100_000, 5, 1, "above the 67108864-byte limit"),
+])
+def test_grad_edges_noalloc_rejects_bad_sizes_before_device_work(lib, M, nn, rn, frag):
+    E = ctypes.c_double()
+    rc = lib.ivhd_grad_edges_noalloc(FAKE, M, FAKE, nn, FAKE, rn, 0.1, 1e-12, ctypes.c_void_p(0x2000),
+                                     ctypes.byref(E), None)
+    assert rc == -1
+    assert frag in lib.ivhd_last_error().decode()
+
+
+def test_grad_edges_noalloc_rejects_null_and_aliased_buffers(lib):
+    assert lib.ivhd_grad_edges_noalloc(FAKE, 100, None, 2, FAKE, 1, 0.1, 1e-12, FAKE, None, None) == -1
+    assert lib.ivhd_grad_edges_noalloc(FAKE, 100, FAKE, 2, FAKE, 1, 0.1, 1e-12, FAKE, None, None) == -1
+    assert "alias" in lib.ivhd_last_error().decode()
