@@ -237,31 +237,72 @@ def run_adam(Y0, nn_idx, *, rn: int, lr: float, c: float, b1: float = 0.9, b2: f
 # exact kNN (numpy, FP64)
 # ---------------------------------------------------------------------------
 
-def knn(X, k: int, queries=None, chunk: int = 512) -> np.ndarray:
+def knn(X, k: int, queries=None, chunk: int = 512, expanded_from: int = 20_000) -> np.ndarray:
     """Exact k nearest neighbours by squared Euclidean distance in FP64.
 
     Self is excluded (for the rows of ``queries``, the query's own index),
-    and ties are broken by the lower index, i.e. the order is (d, j).
+    and ties are broken by the lower index, i.e. the order is (d, j), with
+    d the direct sum over dimensions of squared differences.
+
+    From ``expanded_from`` points on, each row's candidates are first
+    narrowed with the expanded form |x|^2 + |y|^2 - 2 x.y (one BLAS product
+    in FP64) to its k + 24 smallest; those are ranked by the direct d.  The
+    narrowing is checked per row with the rounding bound of the expanded
+    form, |error| <= 4 g (|x_q|^2 + max_j |x_j|^2), g = (N + 3) u / (1 - (N + 3) u),
+    u = 2^-53 (Higham, "Accuracy and Stability of Numerical Algorithms",
+    inner products): the k-th direct distance must lie below every
+    excluded candidate's expanded value minus that bound, else the row is
+    done in full.  So the result is the same as the plain definition.
     Returns int32 [len(queries), k].
     """
     X = np.asarray(X, dtype=np.float64)
-    M = X.shape[0]
+    M, N = X.shape
     q_idx = np.arange(M) if queries is None else np.asarray(queries, dtype=np.int64)
     out = np.empty((q_idx.size, k), dtype=np.int32)
+
+    def direct(q, cand=None):
+        t = (X if cand is None else X[cand]) - X[q]
+        return np.einsum("mn,mn->m", t, t)
+
+    def full_row(q):
+        d = direct(q)
+        d[q] = np.inf
+        return np.argsort(d, kind="stable")[:k]
+
+    m = k + 24
+    if M < expanded_from or m + 1 >= M:
+        for s in range(0, q_idx.size, chunk):
+            qi = q_idx[s:s + chunk]
+            diff = X[qi][:, None, :] - X[None, :, :] if M * qi.size * N < 2e7 else None
+            if diff is not None:
+                d = np.einsum("qmn,qmn->qm", diff, diff)
+                d[np.arange(qi.size), qi] = np.inf
+                # stable sort on d keeps index order among equal distances
+                out[s:s + qi.size] = np.argsort(d, axis=1, kind="stable")[:, :k]
+            else:
+                for r, q in enumerate(qi):
+                    out[s + r] = full_row(q)
+        return out
+    sq = np.einsum("mn,mn->m", X, X)
+    n3 = (N + 3) * 2.0 ** -53
+    g = n3 / (1.0 - n3)
+    sq_max = float(sq.max())
     for s in range(0, q_idx.size, chunk):
         qi = q_idx[s:s + chunk]
-        diff = X[qi][:, None, :] - X[None, :, :] if M * qi.size * X.shape[1] < 2e7 else None
-        if diff is not None:
-            d = np.einsum("qmn,qmn->qm", diff, diff)
-        else:
-            d = np.empty((qi.size, M))
-            for r, q in enumerate(qi):
-                t = X - X[q]
-                d[r] = np.einsum("mn,mn->m", t, t)
-        d[np.arange(qi.size), qi] = np.inf
-        # stable sort on d keeps index order among equal distances
-        order = np.argsort(d, axis=1, kind="stable")[:, :k]
-        out[s:s + qi.size] = order
+        G = sq[qi][:, None] + sq[None, :] - 2.0 * (X[qi] @ X.T)
+        G[np.arange(qi.size), qi] = np.inf
+        part = np.argpartition(G, m, axis=1)[:, :m + 1]
+        for r, q in enumerate(qi):
+            c = part[r]
+            gc = G[r, c]
+            o = np.lexsort((c, gc))
+            c, gc = c[o], gc[o]
+            cand, bound_value = c[:m], gc[m]       # every other candidate has G >= bound_value
+            d = direct(q, cand)
+            o = np.lexsort((cand, d))
+            top, dk = cand[o[:k]], d[o[k - 1]]
+            err = 4.0 * g * (sq[q] + sq_max)
+            out[s + r] = top if bound_value - err > dk else full_row(q)
     return out
 
 
@@ -283,15 +324,21 @@ def rank_neighbours(Z, k: int, rows=None) -> np.ndarray:
 
     rho_ij = |{l : delta_il < delta_ij or (delta_il = delta_ij and l < j)}|,
     so all points (i included) are ordered by (distance, index) and the
-    positions 1..k are taken.  Returns int64 [len(rows), k].
+    positions 1..k are taken.  Only the points at or below the (k+1)-th
+    smallest distance can hold those positions, so just they are sorted
+    (stably, which keeps the index order among equal distances).
+    Returns int64 [len(rows), k].
     """
     M = np.asarray(Z).shape[0]
     rows = np.arange(M) if rows is None else np.asarray(rows)
     out = np.empty((rows.size, k), dtype=np.int64)
     for s in range(0, rows.size, 256):
         d = _sq_dists_rows(Z, rows[s:s + 256])
-        order = np.argsort(d, axis=1, kind="stable")
-        out[s:s + 256] = order[:, 1:k + 1]
+        for r in range(d.shape[0]):
+            tau = np.partition(d[r], k)[k]
+            cand = np.flatnonzero(d[r] <= tau)
+            order = cand[np.argsort(d[r, cand], kind="stable")]
+            out[s + r] = order[1:k + 1]
     return out
 
 

@@ -212,3 +212,26 @@ def test_knn_gain_of_a_hand_computed_layout():
     assert oracle.g_nn(X, Y, lab, 2) == 0.125
     assert oracle.g_nn(Y, X, lab, 1) == -1.0
     assert oracle.g_nn(Y, X, lab, 2) == -0.125
+
+
+def test_exact_knn_expanded_narrowing_matches_a_kd_tree():
+    # the large-input path (candidates narrowed by the expanded form, ranked
+    # by the direct distance) on an input small enough for a kd-tree
+    rng = np.random.default_rng(8)
+    X = np.repeat(rng.normal(size=(1500, 12)), 1, 0) + rng.normal(scale=0.2, size=(1500, 12))
+    k = 7
+    got = oracle.knn(X, k, expanded_from=0)
+    d, idx = cKDTree(X).query(X, k=k + 1)
+    assert np.array_equal(got, idx[:, 1:])
+    assert np.array_equal(got, oracle.knn(X, k))
+
+
+def test_exact_knn_expanded_narrowing_keeps_the_tie_order():
+    # exact duplicates and integer grids: many equal distances; both paths agree
+    rng = np.random.default_rng(9)
+    X = rng.integers(0, 4, size=(900, 3)).astype(np.float64)
+    got = oracle.knn(X, 30, expanded_from=0)
+    assert np.array_equal(got, oracle.knn(X, 30))
+    # large offsets make the expanded form lose digits: rows fall back to the direct order
+    Xo = X + 1e7
+    assert np.array_equal(oracle.knn(Xo, 30, expanded_from=0), got)
