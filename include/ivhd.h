@@ -333,6 +333,48 @@ int ivhd_knn_query(const float *d_x, int64_t M, int32_t N, const float *d_q, int
                    const int32_t *d_self, int32_t k, int32_t *d_idx, float *d_dist,
                    void *stream);
 
+/* ---- quality of a layout on a sample of points ---------------------------
+ * The criteria of the thesis's chapter "Quality metrics", evaluated for a
+ * sample of Q rows (d_rows, int32 [Q], entries in [0, M); the sample may be
+ * every row).  The order of the points around a row r is all M points (r
+ * included) by (delta_rl, l): delta the squared Euclidean distance summed in
+ * FP64, dimension by dimension, from the FP32 coordinates; ties to the lower
+ * index (the rank rho_rj of Sec. "Rank-based criteria").  Coordinates must
+ * be finite.  These calls allocate temporaries and synchronise the stream. */
+
+/* ivhd_eval_neighbours: d_idx int32 [Q][k] = the points at positions 1..k
+ * of the order around each sample row (its neighbourhood of size k, Sec.
+ * "Rank-based criteria"; position 0 is the row itself unless an identical
+ * point of lower index precedes it).  d_z float32 [M][N], 1 <= N <= 1024,
+ * 1 <= k <= min(128, M-1).                                                  */
+int ivhd_eval_neighbours(const float *d_z, int64_t M, int32_t N, const int32_t *d_rows, int64_t Q,
+                         int32_t k, int32_t *d_idx, void *stream);
+
+/* ivhd_eval_ranks: d_rank int32 [Q][kc] = rho_rj for each sample row r and
+ * each given point j = d_cand[q][c] (int32 [Q][kc], entries in [0, M)):
+ * the number of points l with (delta_rl, l) before (delta_rj, j).
+ * 1 <= kc <= 64.                                                            */
+int ivhd_eval_ranks(const float *d_z, int64_t M, int32_t N, const int32_t *d_rows, int64_t Q,
+                    const int32_t *d_cand, int32_t kc, int32_t *d_rank, void *stream);
+
+/* ivhd_eval_scores: the sample criteria at size k from neighbour lists in
+ * the data (d_nx [Q][kx], may be NULL) and in the layout (d_ny [Q][ky]),
+ * both as from ivhd_eval_neighbours:
+ *   h_out[0] = Q_NX(k) = sum_q |v_q ∩ n_q| / (k Q)   (Sec. "Rank-based
+ *              criteria"; NaN when d_nx is NULL)
+ *   h_out[1] = cf_k = share of the layout neighbours carrying the row's
+ *              label (Sec. "Neighbor hit"; d_labels int32 [M]; NaN when NULL)
+ *   h_out[2] = T(k) = 1 - 2 / (Q k (2M - 3k - 1)) sum_q sum_{j in n_q \ v_q}
+ *              (rho^X_{r_q j} - k)   (trustworthiness, Sec. "Trustworthiness
+ *              and continuity", over the sample; d_rank_y [Q][ky] = the data
+ *              ranks of the layout neighbours, as from ivhd_eval_ranks; NaN
+ *              when NULL).  With every row as the sample these are the
+ *              criteria of the whole layout.
+ * 1 <= k <= ky (and <= kx when d_nx is given), Q >= 1.                      */
+int ivhd_eval_scores(int64_t M, const int32_t *d_rows, int64_t Q, const int32_t *d_nx, int32_t kx,
+                     const int32_t *d_ny, int32_t ky, const int32_t *d_rank_y, const int32_t *d_labels,
+                     int32_t k, double *h_out, void *stream);
+
 /* ---- parametric encoder --------------------------------------------------
  * A learned map N-D -> 2-D: MLP n_in -> h1 -> h2 -> 2 with ReLU, trained on
  * the IVHD stress of its own batches' edges, so that new points are placed

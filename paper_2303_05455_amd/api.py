@@ -25,7 +25,7 @@ __all__ = [
     "ivhd_edges_grad", "ivhd_edges_destroy", "ivhd_grad_edges", "ivhd_grad_edges_noalloc",
     "ivhd_set_adaptive",
     "ivhd_get_adaptive", "ivhd_rnn_mask", "ivhd_set_adam", "ivhd_ivf_train", "ivhd_ivf_search",
-    "ivf_knn_graph",
+    "ivf_knn_graph", "ivhd_eval_neighbours", "ivhd_eval_ranks", "ivhd_eval_scores",
 ]
 
 
@@ -517,3 +517,55 @@ def ivhd_enc_destroy(enc) -> None:
 __all__ += ["ivhd_f32_to_bf16", "ivhd_gemm_bf16", "ivhd_enc_create", "ivhd_enc_num_params",
             "ivhd_enc_get_params", "ivhd_enc_set_params", "ivhd_enc_embed", "ivhd_enc_train_step",
             "ivhd_enc_train_epoch", "ivhd_enc_destroy"]
+
+
+def ivhd_eval_neighbours(z: torch.Tensor, rows: torch.Tensor, k: int, out: Optional[torch.Tensor] = None,
+                         stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """Neighbourhoods of size k (positions 1..k of the FP64 (distance, index)
+    order) of the sample rows of z (float32 [M, N]): int32 [Q, k]."""
+    M, N = z.shape
+    _dev(z, torch.float32, (M, N), "z")
+    Q = rows.shape[0]
+    _dev(rows, torch.int32, (Q,), "rows")
+    if out is None:
+        out = torch.empty((Q, k), dtype=torch.int32, device=z.device)
+    _dev(out, torch.int32, (Q, k), "out")
+    check(_lib.load().ivhd_eval_neighbours(z.data_ptr(), M, N, rows.data_ptr(), Q, k, out.data_ptr(),
+                                           _stream_handle(stream)))
+    return out
+
+
+def ivhd_eval_ranks(z: torch.Tensor, rows: torch.Tensor, cand: torch.Tensor, out: Optional[torch.Tensor] = None,
+                    stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """Ranks rho_rj of the given points cand (int32 [Q, kc]) around the
+    sample rows of z: int32 [Q, kc]."""
+    M, N = z.shape
+    _dev(z, torch.float32, (M, N), "z")
+    Q, kc = cand.shape
+    _dev(rows, torch.int32, (Q,), "rows")
+    _dev(cand, torch.int32, (Q, kc), "cand")
+    if out is None:
+        out = torch.empty((Q, kc), dtype=torch.int32, device=z.device)
+    _dev(out, torch.int32, (Q, kc), "out")
+    check(_lib.load().ivhd_eval_ranks(z.data_ptr(), M, N, rows.data_ptr(), Q, cand.data_ptr(), kc, out.data_ptr(),
+                                      _stream_handle(stream)))
+    return out
+
+
+def ivhd_eval_scores(M: int, rows: torch.Tensor, nx: Optional[torch.Tensor], ny: torch.Tensor, k: int,
+                     rank_y: Optional[torch.Tensor] = None, labels: Optional[torch.Tensor] = None,
+                     stream: Optional[torch.cuda.Stream] = None):
+    """(Q_NX(k), cf_k, T(k)) over the sample; NaN where an input is None."""
+    Q, ky = ny.shape
+    _dev(rows, torch.int32, (Q,), "rows")
+    _dev(ny, torch.int32, (Q, ky), "ny")
+    kx, p_nx = 0, None
+    if nx is not None:
+        kx = nx.shape[1]
+        p_nx = _dev(nx, torch.int32, (Q, kx), "nx")
+    p_rank = _dev(rank_y, torch.int32, (Q, ky), "rank_y") if rank_y is not None else None
+    p_lab = _dev(labels, torch.int32, (M,), "labels") if labels is not None else None
+    h = (ctypes.c_double * 3)()
+    check(_lib.load().ivhd_eval_scores(M, rows.data_ptr(), Q, p_nx, kx, ny.data_ptr(), ky, p_rank, p_lab, k,
+                                       ctypes.cast(h, ctypes.c_void_p), _stream_handle(stream)))
+    return h[0], h[1], h[2]

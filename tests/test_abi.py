@@ -145,3 +145,29 @@ def test_grad_edges_noalloc_rejects_null_and_aliased_buffers(lib):
     assert lib.ivhd_grad_edges_noalloc(FAKE, 100, None, 2, FAKE, 1, 0.1, 1e-12, FAKE, None, None) == -1
     assert lib.ivhd_grad_edges_noalloc(FAKE, 100, FAKE, 2, FAKE, 1, 0.1, 1e-12, FAKE, None, None) == -1
     assert "alias" in lib.ivhd_last_error().decode()
+
+
+def test_eval_calls_reject_bad_sizes_before_device_work(lib):
+    out = (ctypes.c_double * 3)()
+    assert lib.ivhd_eval_neighbours(FAKE, 1, 2, FAKE, 10, 1, FAKE, None) == -1
+    assert "M =" in lib.ivhd_last_error().decode()
+    assert lib.ivhd_eval_neighbours(FAKE, 100, 1025, FAKE, 10, 1, FAKE, None) == -1
+    assert "N =" in lib.ivhd_last_error().decode()
+    assert lib.ivhd_eval_neighbours(FAKE, 100, 2, FAKE, 10, 129, FAKE, None) == -1
+    assert "k =" in lib.ivhd_last_error().decode()
+    assert lib.ivhd_eval_neighbours(FAKE, 10, 2, FAKE, 10, 10, FAKE, None) == -1
+    assert lib.ivhd_eval_neighbours(FAKE, 100, 2, FAKE, 10, 5, None, None) == -1
+    assert lib.ivhd_eval_ranks(FAKE, 100, 2, FAKE, 10, FAKE, 65, FAKE, None) == -1
+    assert "kc =" in lib.ivhd_last_error().decode()
+    assert lib.ivhd_eval_ranks(FAKE, 100, 2, FAKE, 10, None, 5, FAKE, None) == -1
+    assert lib.ivhd_eval_scores(100, FAKE, 10, FAKE, 5, FAKE, 10, None, None, 11, ctypes.cast(out, ctypes.c_void_p),
+                                None) == -1
+    assert "k =" in lib.ivhd_last_error().decode()
+    assert lib.ivhd_eval_scores(100, FAKE, 10, FAKE, 5, FAKE, 10, None, None, 6, ctypes.cast(out, ctypes.c_void_p),
+                                None) == -1
+    assert "kx" in lib.ivhd_last_error().decode()
+    assert lib.ivhd_eval_scores(100, FAKE, 10, None, 0, FAKE, 10, FAKE, None, 6, ctypes.cast(out, ctypes.c_void_p),
+                                None) == -1
+    assert "d_rank_y needs d_nx" in lib.ivhd_last_error().decode()
+    assert lib.ivhd_eval_scores(100, FAKE, 0, None, 0, FAKE, 10, None, None, 6, ctypes.cast(out, ctypes.c_void_p),
+                                None) == -1
