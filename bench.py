@@ -111,10 +111,7 @@ def cpu_baseline(cfg, iters, seed=0):
     import oracle
     import synth
     rng = np.random.default_rng([seed, cfg.cfg_id, 99])
-    sizes = synth.cluster_sizes(cfg.M, cfg.K, cfg.sizes, cfg.zipf_s)
-    labels = np.repeat(np.arange(cfg.K, dtype=np.int32), sizes)[rng.permutation(cfg.M)]
-    nn_idx = synth.random_neighbour_graph(cfg.M, cfg.nn, rng, labels=labels, hub_alpha=1.2)
-    Y0 = synth.init_positions(cfg.M, rng)
+    nn_idx, _, Y0 = synth.standin_graph(cfg, rng)
     oracle.build(force=False)
     kw = dict(rn=cfg.rn, a=cfg.a, b=cfg.b, c=cfg.c, seed=cfg.seed, R=cfg.R)
     V0 = np.zeros_like(Y0, dtype=np.float64)
@@ -127,7 +124,7 @@ def cpu_baseline(cfg, iters, seed=0):
     oracle.run(Y0, V0, nn_idx, T=iters_n, threads=nt, **kw)
     dtn = time.perf_counter() - t0
     shape = (f"at M={cfg.M:,}, nn={cfg.nn}, rn={cfg.rn}, R={cfg.R} on a same-shape synthetic graph "
-             f"(in-cluster targets with Pareto popularity; the oracle never takes the GPU's kNN graph)")
+             f"(in-cluster targets with Pareto(2.2) popularity, largest in-degree near the exact graph's; the oracle never takes the GPU's kNN graph)")
     return {
         "value": cfg.M * (cfg.nn + cfg.rn) * iters_n / dtn,
         "unit": "edge-updates/s",

@@ -30,7 +30,7 @@ import numpy as np
 
 __all__ = [
     "Config", "CONFIGS", "cluster_sizes", "gaussian_mixture", "init_positions",
-    "make_inputs", "random_neighbour_graph", "rng_for",
+    "lifted_sheet", "make_inputs", "random_neighbour_graph", "rng_for", "standin_graph",
 ]
 
 
@@ -209,3 +209,35 @@ def random_neighbour_graph(M: int, nn: int, rng: np.random.Generator, *,
         mask = rng.random((M, nn)) < absent_frac
         out[mask] = -1
     return out
+
+
+def standin_graph(cfg: Config, rng: np.random.Generator, hub_alpha: float = 2.2):
+    """A kNN-shaped stand-in for a workload whose exact kNN graph is too
+    costly for the CPU: the workload's cluster labels (same sizes, shuffled),
+    ``nn`` in-cluster targets per vertex with Pareto(``hub_alpha``)
+    popularity, and the initial layout.  At the 1.4M-point shape, alpha 2.2
+    gives a largest in-degree of 888, the exact graph's being 887.
+    Returns (nn_idx int32 [M, nn], labels int32 [M], Y0 float32 [M, 2])."""
+    sizes = cluster_sizes(cfg.M, cfg.K, cfg.sizes, cfg.zipf_s)
+    labels = np.repeat(np.arange(cfg.K, dtype=np.int32), sizes)[rng.permutation(cfg.M)]
+    nn_idx = random_neighbour_graph(cfg.M, cfg.nn, rng, labels=labels, hub_alpha=hub_alpha)
+    return nn_idx, labels, init_positions(cfg.M, rng)
+
+
+def lifted_sheet(M: int, N: int, rng: np.random.Generator, *, freq: float = 3.0, noise: float = 0.01,
+                 grid: int = 4, lift_seed: int = 12345):
+    """A 2-D sheet curled into N dimensions, for inputs with local structure
+    (isotropic clusters have none): latent points u ~ U[0,1)^2, features
+    X[:, n] = sin(w_n . u + p_n) with w_n ~ N(0, freq^2 I) and p_n ~ U[0, 2 pi)
+    drawn from ``lift_seed`` (so every draw shares one sheet), plus
+    N(0, noise^2) per coordinate.  Labels: the cell of u in a grid x grid
+    partition of the square.  Returns (X float32 [M, N], labels int32 [M],
+    u float64 [M, 2])."""
+    lift = np.random.default_rng(lift_seed)
+    w = lift.normal(0.0, freq, size=(2, N))
+    p = lift.uniform(0.0, 2 * np.pi, size=N)
+    u = rng.random((M, 2))
+    X = np.sin(u @ w + p) + rng.normal(0.0, noise, size=(M, N))
+    cell = np.minimum((u * grid).astype(np.int64), grid - 1)
+    labels = (cell[:, 0] * grid + cell[:, 1]).astype(np.int32)
+    return X.astype(np.float32), labels, u
