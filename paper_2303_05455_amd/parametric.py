@@ -49,10 +49,34 @@ class ParametricIVHD:
             self.epochs_done += 1
         return self
 
-    def embed(self, x16: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    def embed(self, x16: torch.Tensor, out: Optional[torch.Tensor] = None, *, refine_iters: int = 0,
+              x: Optional[torch.Tensor] = None, nn_idx: Optional[torch.Tensor] = None, a: float = 0.9,
+              b: Optional[float] = None, rn_resample_every: int = 100, seed: int = 0,
+              mode: str = "det") -> torch.Tensor:
+        """Place the rows of x16 (BF16 bits [rows, n_in]) with one forward
+        pass; with ``refine_iters`` > 0 the placement then starts plain IVHD
+        (the fallback: the loop of ``Context`` initialised from the network's
+        layout, as the thesis starts IVHD from another method's layout) on the
+        kNN graph of these rows -- ``nn_idx`` (int32 [rows, nn]) or, when it
+        is None, the exact graph of ``x`` (float32 [rows, n_in]) -- with this
+        encoder's nn, rn and c.  b defaults to a quarter of the heavy-ball
+        stability bound 2 (1 + a) / (max in-degree + nn + 2 rn + 2)."""
         if out is None:
             out = torch.empty((x16.shape[0], 2), dtype=torch.float32, device=x16.device)
-        return api.ivhd_enc_embed(self.handle, x16, out)
+        api.ivhd_enc_embed(self.handle, x16, out)
+        if refine_iters > 0:
+            if nn_idx is None:
+                if x is None:
+                    raise ValueError("refine_iters needs nn_idx or the float32 rows x")
+                nn_idx = api.ivhd_knn_build(x.contiguous(), self.nn)
+            if b is None:
+                indeg = torch.bincount(nn_idx.reshape(-1).long().clamp(min=0), minlength=nn_idx.shape[0])
+                b = 0.25 * 2 * (1 + a) / (int(indeg.max()) + nn_idx.shape[1] + 2 * self.rn + 2)
+            ctx = api.Context(nn_idx, out, rn=self.rn, a=a, b=b, c=self.c, eps=self.eps, seed=seed,
+                              rn_resample_every=rn_resample_every, mode=mode)
+            ctx.step(refine_iters)
+            ctx.close()
+        return out
 
     def params(self) -> torch.Tensor:
         n = api.ivhd_enc_num_params(self.handle)

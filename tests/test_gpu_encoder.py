@@ -167,3 +167,63 @@ def test_training_lowers_the_batch_stress_and_separates_clusters(pkg):
     assert np.all(np.isfinite(Z))
     assert oracle.cf_k(Z, labels, 10) > 0.9
     enc.close()
+
+
+def _epoch_order(M, batch, seed, epoch):
+    """Sources of each step of a training epoch: s = (a t + c0) mod M over the
+    epoch's step slots t, a coprime to M, a and c0 from SplitMix64 of seed and
+    epoch (the definition the encoder documents)."""
+    from math import gcd
+    mask = (1 << 64) - 1
+    a = oracle.splitmix64((seed ^ oracle.splitmix64((0x5EED + epoch) & mask)) & mask) % M
+    if a == 0:
+        a = 1
+    while gcd(a, M) != 1:
+        a = 1 if a + 1 == M else a + 1
+    c0 = oracle.splitmix64((seed + 7919 * epoch) & mask) % M
+    steps = (M + batch - 1) // batch
+    t = np.arange(steps * batch, dtype=np.int64)
+    return ((a * t + c0) % M).reshape(steps, batch)
+
+
+@pytest.mark.parametrize("M,n_in,h1,h2,batch,nn,rn,absent", [(1000, 40, 32, 24, 128, 3, 1, 0.0),
+                                                            (777, 45, 40, 16, 100, 2, 2, 0.1)])
+def test_training_epochs_match_the_reference_composition(pkg, M, n_in, h1, h2, batch, nn, rn, absent):
+    # two whole epochs of ivhd_enc_train_epoch against the oracle composed step
+    # by step: the epoch's visiting order, each batch's rows (sources, their nn
+    # targets with an absent slot repeating the source, their rn targets of the
+    # epoch's draw), the batch edge lists, the reference training step
+    m, api, ag, par = pkg
+    import synth
+    rng = np.random.default_rng(M)
+    X32 = np.maximum(rng.normal(1.0, 1.0, size=(M, n_in)), 0).astype(np.float32)
+    Xb = mlp.bf16_round(X32)
+    nn_idx = synth.random_neighbour_graph(M, nn, rng, hub_alpha=1.0, absent_frac=absent)
+    seed, c, eps, lr = 5, 0.1, 1e-12, 3e-4
+    enc = par.ParametricIVHD(n_in, (h1, h2), batch=batch, nn=nn, rn=rn, c=c, lr=lr, seed=seed)
+    p = enc.params().cpu().numpy().astype(np.float64)
+    p0 = p.copy()
+    mo, vo = np.zeros_like(p), np.zeros_like(p)
+    t = 0
+    lnn, lrn = mlp.batch_edges(batch, nn, rn)
+    x16 = par.ParametricIVHD.to_bf16(torch.from_numpy(X32).cuda())
+    d_nn = torch.from_numpy(nn_idx).cuda()
+    for epoch in range(2):
+        loss_gpu = api.ivhd_enc_train_epoch(enc.handle, x16, d_nn, rn, seed, epoch, batch, c, eps, lr)
+        rn_e = oracle.rn_sample(nn_idx, rn, seed, epoch)
+        losses = []
+        for src in _epoch_order(M, batch, seed, epoch):
+            nbr = nn_idx[src]
+            nbr = np.where(nbr >= 0, nbr, src[:, None])
+            rows = np.concatenate([src, nbr.ravel(), rn_e[src].ravel()])
+            t += 1
+            p, mo, vo, _, E = mlp.train_step(p, mo, vo, t, Xb[rows], lnn, lrn, n_in, h1, h2, c=np.float32(c),
+                                             eps=np.float32(eps), lr=lr, scale=1.0 / batch)
+            losses.append(E / batch)
+        loss_ref = float(np.mean(losses))
+        print(f"epoch {epoch}: loss gpu {loss_gpu:.6f} reference {loss_ref:.6f}")
+        assert loss_gpu == pytest.approx(loss_ref, rel=2e-3)
+    pg = enc.params().cpu().numpy().astype(np.float64)
+    # the parameters moved the same way (Adam steps of size about lr per weight)
+    assert _norm_rel(pg - p0, p - p0) <= 0.05
+    enc.close()
