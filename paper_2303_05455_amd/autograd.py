@@ -17,7 +17,13 @@ from . import api
 
 class StressEdges:
     """An edge plan: transposed lists of fixed nn / rn edge lists, reused by
-    every forward and backward call.  Keeps the index tensors alive."""
+    every forward and backward call.  Keeps the index tensors alive.
+
+    The plan's kernels run on the stream that was current when it was made;
+    a call from another stream is ordered after that stream's queued work and
+    the caller's stream waits for the result, and the tensors it touches are
+    marked as used on the plan's stream (so the caching allocator does not
+    hand their memory out early)."""
 
     def __init__(self, nn_idx: torch.Tensor, rn_idx: Optional[torch.Tensor] = None, *,
                  c: float = 0.1, eps: float = 1e-12):
@@ -26,8 +32,21 @@ class StressEdges:
         self.M = nn_idx.shape[0]
         self.c, self.eps = float(c), float(eps)
         self._h = None
-        self._h = api.ivhd_edges_create(self.nn_idx, self.rn_idx)
+        self.stream = torch.cuda.current_stream(nn_idx.device)
+        self._h = api.ivhd_edges_create(self.nn_idx, self.rn_idx, stream=self.stream)
         self._E = torch.zeros((), dtype=torch.float64, device=nn_idx.device)
+
+    def _run(self, fn, *tensors):
+        cur = torch.cuda.current_stream(self.nn_idx.device)
+        if cur == self.stream:
+            return fn()
+        self.stream.wait_stream(cur)
+        r = fn()
+        for t in tensors:
+            if t is not None:
+                t.record_stream(self.stream)
+        cur.wait_stream(self.stream)
+        return r
 
     @property
     def handle(self):
@@ -38,14 +57,15 @@ class StressEdges:
     def stress64(self, y: torch.Tensor) -> torch.Tensor:
         """E(y) as a float64 device scalar (asynchronous)."""
         out = torch.empty((), dtype=torch.float64, device=y.device)
-        return api.ivhd_edges_stress(self.handle, y.contiguous(), self.c, out)
+        y = y.contiguous()
+        return self._run(lambda: api.ivhd_edges_stress(self.handle, y, self.c, out), y, out)
 
     def grad(self, y: torch.Tensor, scale: Optional[torch.Tensor] = None,
              out: Optional[torch.Tensor] = None) -> torch.Tensor:
         y = y.contiguous()
         if out is None:
             out = torch.empty_like(y)
-        return api.ivhd_edges_grad(self.handle, y, self.c, self.eps, scale, out)
+        return self._run(lambda: api.ivhd_edges_grad(self.handle, y, self.c, self.eps, scale, out), y, scale, out)
 
     def close(self):
         if self._h is not None:

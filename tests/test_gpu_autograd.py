@@ -137,3 +137,27 @@ def test_gradient_descent_on_the_loss_lowers_the_stress(m):
         losses.append(loss.item())
     assert losses[-1] < 0.5 * losses[0]
     assert all(b <= a * (1 + 1e-6) for a, b in zip(losses, losses[1:]))
+
+
+def test_forward_and_backward_on_another_torch_stream(m):
+    # the plan is made on the default stream; the loss and its gradient are
+    # then taken under a side stream, with no explicit synchronisation, and
+    # must equal the same computation on the plan's own stream
+    pkg, ag = m
+    nn_idx, rn_idx, Y = _case(20000, 5, 1, 21, hub=0.8)
+    edges = ag.StressEdges(torch.from_numpy(nn_idx).cuda(), torch.from_numpy(rn_idx).cuda(), c=0.1)
+    y_ref = torch.from_numpy(Y).cuda().requires_grad_(True)
+    loss_ref = ag.IVHDStress.apply(y_ref, edges)
+    loss_ref.backward()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        y = torch.from_numpy(Y).to("cuda", non_blocking=False).mul_(1.0).requires_grad_(True)
+        loss = ag.IVHDStress.apply(y, edges) * 3.0
+        loss.backward()
+        got_loss = loss.clone()
+        got_grad = y.grad.clone()
+    torch.cuda.synchronize()
+    assert got_loss.item() == pytest.approx(3.0 * loss_ref.item(), rel=1e-6)
+    assert torch.equal(got_grad, 3.0 * y_ref.grad)
+    edges.close()
