@@ -364,3 +364,40 @@ def test_adam_rejects_bad_use(ivhd):
     with pytest.raises(ivhd.IvhdError, match="Adam"):
         ctx.set_adaptive(True, tau=1.0)
     ctx.close()
+
+
+def test_staged_late_refinement_run_matches_the_oracle_composition():
+    # plain for T - 200 iterations, reverse-neighbour mask for 150, mask + l1
+    # at b / 2 for the last 50, each stage resuming the iteration count (so
+    # the random-neighbour schedule runs on); the same schedule composed from
+    # the oracle's run, rnn_mask and l1 metric.  Final layouts compared by
+    # their l1 stress (1e-3 relative: a 1e-7 nudge of the start moves it by
+    # 5e-6 in the oracle), Q_NX(10) and cf_10 within 0.01
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2303_05455_amd.late_stage import staged_run
+    cfg = synth.CONFIGS["C1"]
+    X, labels, Y0 = synth.make_inputs(cfg)
+    f32 = lambda x: float(np.float32(x))
+    a, b, c = f32(cfg.a), f32(cfg.b), f32(cfg.c)
+    nn_idx = oracle.knn(X, cfg.nn)
+    helper = oracle.knn(X, 4 * cfg.nn)
+    masked = oracle.rnn_mask(nn_idx, helper)
+    T, R = cfg.T, 7      # R = 7: the random neighbours are redrawn across every stage boundary
+    V = np.zeros_like(Y0, dtype=np.float64)
+    Y, V, _ = oracle.run(Y0, V, nn_idx, rn=1, a=a, b=b, c=c, seed=0, R=R, n0=0, T=T - 200)
+    Y, V, _ = oracle.run(Y, V, masked, rn=1, a=a, b=b, c=c, seed=0, R=R, n0=T - 200, T=150)
+    Yo, _, rno = oracle.run(Y, V, masked, rn=1, a=a, b=f32(b / 2), c=c, seed=0, R=R, n0=T - 50, T=50, metric="l1")
+    y = torch.from_numpy(Y0.copy()).cuda()
+    v = torch.zeros_like(y)
+    info = staged_run(torch.from_numpy(nn_idx).cuda(), y, v, T=T, helper=torch.from_numpy(helper).cuda(), rn=1,
+                      a=a, b=b, c=c, seed=0, rn_resample_every=R)
+    torch.cuda.synchronize()
+    assert np.array_equal(info["nn_masked"].cpu().numpy(), masked)
+    Yg = y.cpu().numpy()
+    Eg, Eo = oracle.stress(Yg, masked, rno, c, metric="l1"), oracle.stress(Yo, masked, rno, c, metric="l1")
+    qg, qo = oracle.q_nx(X, Yg, 10), oracle.q_nx(X, Yo, 10)
+    cfg_, cfo = oracle.cf_k(Yg, labels, 10), oracle.cf_k(Yo, labels, 10)
+    print(f"staged C1: l1 stress {Eg:.6f} / {Eo:.6f}; Q_NX(10) {qg:.4f} / {qo:.4f}; cf_10 {cfg_:.4f} / {cfo:.4f}")
+    assert abs(Eg - Eo) <= 1e-3 * Eo
+    assert abs(qg - qo) <= 0.01 and abs(cfg_ - cfo) <= 0.01
