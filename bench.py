@@ -53,8 +53,10 @@ STEP_SOURCES = [os.path.join(ROOT, "paper_2303_05455_amd", "csrc", f) for f in (
                                                                               "order.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_det_C3_traffic.md")
 METRIC = "edge-updates/sec (M·(nn+rn)·iters/s) at M=1.4M + achieved HBM GB/s"
-# adaptive-b threshold on |dT| (the kinetic energy change per step), per point
-ADAPT_TAU_PER_POINT = 1e-6
+# adaptive-b threshold on |dT| (the kinetic energy change per step), per point:
+# at the 1.4M-point shape 1e-4 accepts the first steps from rest at the
+# configured b (1e-6 and 1e-5 rejected them and shrank b 4-16x for good)
+ADAPT_TAU_PER_POINT = 1e-4
 # Adam on the loop: each coordinate moves by about lr per step
 ADAM_LR = 1e-3
 
@@ -209,7 +211,6 @@ def run_loop(args, cfg):
     M, nn, rn, R, T = cfg.M, cfg.nn, cfg.rn, cfg.R, cfg.T
     dX, labels, Y0, nn_idx, knn_s, max_in = build_graph(cfg, dev)
     knn_ivf = None if args.no_variants else ivf_report(dX, nn_idx, cfg)
-    del dX
     # heavy-ball stability: b * lambda_max < 2 (1 + a), lambda_max <= max degree + 1
     bound = 2 * (1 + cfg.a) / (max_in + nn + 2 * rn + 2)
     if cfg.b > bound:
@@ -284,13 +285,15 @@ def run_loop(args, cfg):
     # b lambda_max < 2 (1 + a) / (1 + 2 a); l1: up to twice the stiffness), so
     # those two run at b / 2.
     variants = {}
-    for name, kw, b in () if args.no_variants else (("nesterov", dict(nesterov=True), cfg.b / 2), ("l1", dict(metric="l1"), cfg.b / 2),
-                        ("adaptive", dict(), cfg.b), ("adam", dict(), cfg.b)):
+    for name, kw, b in () if args.no_variants else (("nesterov", dict(nesterov=True), cfg.b / 2),
+                                                     ("l1", dict(metric="l1"), cfg.b / 2),
+                                                     ("adaptive", dict(), cfg.b), ("adaptive_from_10b", dict(), 10 * cfg.b),
+                                                     ("adam", dict(), cfg.b)):
         y = d_y0.clone()
         v = torch.zeros_like(y)
         ctx = Context(nn_idx, y, v, rn=rn, a=cfg.a, b=b, c=cfg.c, seed=cfg.seed,
                       rn_resample_every=R, mode="det", **kw)
-        if name == "adaptive":
+        if name.startswith("adaptive"):
             ctx.set_adaptive(True, tau=ADAPT_TAU_PER_POINT * M, g1=1.05, g2=0.5)
         if name == "adam":
             ctx.set_adam(True, lr=ADAM_LR)
@@ -305,11 +308,29 @@ def run_loop(args, cfg):
         t = e0.elapsed_time(e1) / 1e3
         variants[name] = {"value": M * (nn + rn) * T / t, "us_per_iter": t * 1e6 / T, "b": b,
                           "final_stress": ctx.stress()}
-        if name == "adaptive":
+        if name.startswith("adaptive"):
             variants[name].update(ctx.adaptive())
+            variants[name]["tau"] = ADAPT_TAU_PER_POINT * M
         ctx.close()
         log(f"variant {name}: {variants[name]['value']:.4g} edge-updates/s, "
             f"{variants[name]['us_per_iter']:.2f} us/iter")
+
+    # quality of the configured run's layout (T iterations from the start), off the timed region
+    quality = None
+    if not args.no_variants:
+        y = d_y0.clone()
+        v = torch.zeros_like(y)
+        ctx = Context(nn_idx, y, v, rn=rn, a=cfg.a, b=cfg.b, c=cfg.c, seed=cfg.seed, rn_resample_every=R)
+        ctx.step(T)
+        ctx.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        quality = layout_quality(dX, y, labels)
+        quality["eval_s"] = time.perf_counter() - t0
+        log(f"layout after {T} it: Q_NX(10) {quality['q_nx10']:.4f} (random {quality['q_nx10_random']:.2g}), "
+            f"cf_2/10/100 {quality['cf2']:.4f}/{quality['cf10']:.4f}/{quality['cf100']:.4f}, "
+            f"T(10) {quality['trust10']:.4f} on {quality['rows']} rows ({quality['eval_s']:.2f} s)")
+    del dX
 
     cpu = None
     if not args.no_cpu:
@@ -348,6 +369,7 @@ def run_loop(args, cfg):
         "knn_build_s": knn_s,
         "knn_ivf": knn_ivf,
         "max_nn_in_degree": max_in,
+        "quality": quality,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -407,20 +429,15 @@ def run_stress(args, cfg):
     }
 
 
-def q_nx_gpu(Xd, Z, rows, k=10, labels=None):
-    """Q_NX(k) over sampled query rows: exact k-NN sets in N-D and in 2-D (GPU
-    builder, ties by index), averaged agreement; with labels also the
-    neighbour hit cf_k of the 2-D neighbours."""
-    import torch
-    from paper_2303_05455_amd import ivhd_knn_query
-    r = torch.from_numpy(rows.astype(np.int32)).to(Xd.device)
-    a = ivhd_knn_query(Xd, Xd[r.long()].contiguous(), k, self_idx=r).cpu().numpy()
-    Zc = Z.contiguous()
-    b = ivhd_knn_query(Zc, Zc[r.long()].contiguous(), k, self_idx=r).cpu().numpy()
-    q = float(np.mean([len(np.intersect1d(a[i], b[i])) for i in range(len(rows))]) / k)
-    if labels is None:
-        return q
-    return q, float((labels[b] == labels[rows][:, None]).mean())
+def layout_quality(dX, y, labels, n_rows=10_000, seed=5):
+    """Q_NX(10), cf_k (k = 2, 10, 100) and T(10) of a layout over a sample of
+    rows, from the library's evaluation kernels (FP64 rank order)."""
+    from paper_2303_05455_amd.evaluate import quality, sample_rows
+    M = dX.shape[0]
+    rows = sample_rows(M, n_rows, seed)
+    q = quality(dX, y, rows, labels=labels, ks=(2, 10, 100), k_qnx=(10,), k_trust=(10,))
+    return {"rows": q["rows"], "q_nx10": q["q_nx"][10], "q_nx10_random": q["q_nx_random"][10],
+            "cf2": q["cf"][2], "cf10": q["cf"][10], "cf100": q["cf"][100], "trust10": q["trust"][10]}
 
 
 def run_encoder(args, cfg):
@@ -461,8 +478,7 @@ def run_encoder(args, cfg):
     e1.record()
     torch.cuda.synchronize()
     t_embed = e0.elapsed_time(e1) / 1e3
-    rows_q = np.random.default_rng(5).choice(cfg.M_heldout, 2000, replace=False)
-    q_enc, cf_enc = q_nx_gpu(dXh, Zh, rows_q, labels=lab_h)
+    q_enc = layout_quality(dXh, Zh, lab_h)
     # plain IVHD on the held-out points (its own kNN graph, 2000 iterations)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -477,20 +493,20 @@ def run_encoder(args, cfg):
     ctx.step(2000)
     torch.cuda.synchronize()
     t_ivhd = time.perf_counter() - t0
-    q_ivhd, cf_ivhd = q_nx_gpu(dXh, y, rows_q, labels=lab_h)
+    q_ivhd = layout_quality(dXh, y, lab_h)
     ctx.close()
     # fallback: plain IVHD started from the encoder's layout, 200 iterations
-    y2 = Zh.clone()
     t0 = time.perf_counter()
-    ctx = Context(nn_h, y2, rn=cfg.rn, a=cfg.a, b=cfg.b, c=cfg.c, seed=1, rn_resample_every=100)
-    ctx.step(200)
+    y2 = enc.embed(xh16, refine_iters=200, nn_idx=nn_h, b=cfg.b, seed=1)
     torch.cuda.synchronize()
     t_fb = time.perf_counter() - t0
-    q_fb, cf_fb = q_nx_gpu(dXh, y2, rows_q, labels=lab_h)
-    ctx.close()
-    log(f"held-out {cfg.M_heldout}: encoder Q_NX(10)={q_enc:.4f} cf_10={cf_enc:.3f} in {t_embed * 1e3:.2f} ms; "
-        f"plain IVHD Q_NX(10)={q_ivhd:.4f} cf_10={cf_ivhd:.3f} in {t_ivhd:.2f} s; IVHD from encoder "
-        f"(200 it) Q_NX(10)={q_fb:.4f} cf_10={cf_fb:.3f}")
+    q_fb = layout_quality(dXh, y2, lab_h)
+    q_enc_, cf_enc = q_enc["q_nx10"], q_enc["cf10"]
+    q_ivhd_, cf_ivhd = q_ivhd["q_nx10"], q_ivhd["cf10"]
+    q_fb_, cf_fb = q_fb["q_nx10"], q_fb["cf10"]
+    log(f"held-out {cfg.M_heldout}: encoder Q_NX(10)={q_enc_:.4f} cf_10={cf_enc:.3f} in {t_embed * 1e3:.2f} ms; "
+        f"plain IVHD Q_NX(10)={q_ivhd_:.4f} cf_10={cf_ivhd:.3f} in {t_ivhd:.2f} s; IVHD from encoder "
+        f"(200 it) Q_NX(10)={q_fb_:.4f} cf_10={cf_fb:.3f}")
     return {
         "metric": "parametric IVHD: held-out embedding points/s (MLP 784-512-512-2, BF16 MFMA)",
         "value": cfg.M_heldout / t_embed, "unit": "points/s", "n_gpus": 1, "steps": steps,
@@ -504,67 +520,49 @@ def run_encoder(args, cfg):
         "train_tflops": flop_step * steps / t_train / 1e12,
         "train_mfma_frac": flop_step * steps / t_train / 1e12 / BF16_PEAK_TFLOPS,
         "loss_first_epoch": enc.losses[0], "loss_last_epoch": enc.losses[-1],
-        "embed_ms": t_embed * 1e3, "q_nx10_encoder": q_enc, "q_nx10_plain_ivhd": q_ivhd,
-        "cf10_encoder": cf_enc, "cf10_plain_ivhd": cf_ivhd, "cf10_ivhd_from_encoder_200it": cf_fb,
-        "q_nx10_random_layout": 10 / (cfg.M_heldout - 1),
-        "plain_ivhd_s": t_ivhd, "q_nx10_ivhd_from_encoder_200it": q_fb, "fallback_s": t_fb,
+        "embed_ms": t_embed * 1e3, "quality_encoder": q_enc, "quality_plain_ivhd_2000it": q_ivhd,
+        "quality_ivhd_from_encoder_200it": q_fb,
+        "plain_ivhd_s": t_ivhd, "fallback_s": t_fb,
         "knn_build_s": knn_s, "knn_ivf": knn_ivf, "max_nn_in_degree": max_in,
         "heldout_max_nn_in_degree": max_in_h,
     }
 
 
 def run_refine(args, cfg):
-    """Late-stage refinements of the thesis's improvements chapter: the
-    reverse-neighbour mask (helper graph of 4 nn) for the last 200 iterations
-    and the l1 distance for the last 50, against the plain loop with the
-    same iteration count; quality by Q_NX(10) and cf_10 on 2000 sampled
-    points, cost as the extra wall time of the refinement stages."""
+    """Late-stage refinements of the thesis's improvements chapter (the
+    reverse-neighbour mask with a helper graph of 4 nn for the last 200
+    iterations, the l1 distance for the last 50: late_stage.staged_run)
+    against the plain loop with the same iteration count; quality by the
+    sample scores, cost as the extra wall time of the refinement stages."""
     import torch
-    from paper_2303_05455_amd import Context, ivhd_knn_build, ivhd_rnn_mask
+    from paper_2303_05455_amd import Context
+    from paper_2303_05455_amd.late_stage import staged_run
     dev = torch.device("cuda:0")
     M, nn, rn, T = cfg.M, cfg.nn, cfg.rn, cfg.T
     dX, labels, Y0, nn_idx, knn_s, max_in = build_graph(cfg, dev)
-    rows = np.random.default_rng(5).choice(M, 2000, replace=False)
     kw = dict(rn=rn, a=cfg.a, b=cfg.b, c=cfg.c, seed=cfg.seed, rn_resample_every=cfg.R)
 
-    def run_plain(n_iter):
-        y = torch.from_numpy(Y0).to(dev)
-        v = torch.zeros_like(y)
-        ctx = Context(nn_idx, y, v, **kw)
-        ctx.step(n_iter)
-        torch.cuda.synchronize()
-        ctx.close()
-        return y, v
-
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    y_base, _ = run_plain(T)
+    y_base = torch.from_numpy(Y0).to(dev)
+    ctx = Context(nn_idx, y_base, torch.zeros_like(y_base), **kw)
+    ctx.step(T)
+    torch.cuda.synchronize()
+    ctx.close()
     t_base = time.perf_counter() - t0
-    q_base, cf_base = q_nx_gpu(dX, y_base, rows, labels=labels)
+    q_base = layout_quality(dX, y_base, labels)
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    y, v = run_plain(T - 200)
-    t_helper = time.perf_counter()
-    helper = ivhd_knn_build(dX, 4 * nn)
-    nn_rnn = ivhd_rnn_mask(nn_idx, helper)
+    y = torch.from_numpy(Y0).to(dev)
+    info = staged_run(nn_idx, y, torch.zeros_like(y), T=T, x=dX, **kw)
     torch.cuda.synchronize()
-    t_helper = time.perf_counter() - t_helper
-    kept = float((nn_rnn >= 0).float().mean())
-    ctx = Context(nn_rnn, y, v, **kw)
-    ctx.set_iteration(T - 200)
-    ctx.step(150)
-    ctx.close()
-    ctx = Context(nn_rnn, y, v, metric="l1", **{**kw, "b": cfg.b / 2})   # l1 is stiffer: b / 2
-    ctx.set_iteration(T - 50)
-    ctx.step(50)
-    torch.cuda.synchronize()
-    ctx.close()
     t_ref = time.perf_counter() - t0
-    q_ref, cf_ref = q_nx_gpu(dX, y, rows, labels=labels)
-    log(f"refine {cfg.name}: plain {T} it Q_NX(10)={q_base:.4f} cf_10={cf_base:.4f} in {t_base:.2f} s; "
-        f"reverse-neighbour mask (keeps {kept:.1%} of nn edges) for the last 200 it, l1 for the last 50: "
-        f"Q_NX(10)={q_ref:.4f} cf_10={cf_ref:.4f} in {t_ref:.2f} s (helper graph + mask {t_helper:.2f} s)")
+    q_ref = layout_quality(dX, y, labels)
+    kept = info["kept"]
+    log(f"refine {cfg.name}: plain {T} it Q_NX(10)={q_base['q_nx10']:.4f} cf_10={q_base['cf10']:.4f} in "
+        f"{t_base:.2f} s; reverse-neighbour mask (keeps {kept:.1%} of nn edges) for the last 200 it, l1 for "
+        f"the last 50: Q_NX(10)={q_ref['q_nx10']:.4f} cf_10={q_ref['cf10']:.4f} in {t_ref:.2f} s")
     return {
         "metric": "late-stage refinement: Q_NX(10) and cf_10 vs plain IVHD, same iteration count",
         "value": t_ref, "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": t_ref * 1e3,
@@ -573,9 +571,8 @@ def run_refine(args, cfg):
         "config": {"workload": f"{cfg.name}: M={M:,} N={cfg.N}, nn={nn}, rn={rn}, {T} iterations; helper "
                                f"kNN graph of {4 * nn}; reverse-neighbour mask for the last 200, l1 "
                                f"distance for the last 50", "M": M, "N": cfg.N, "T": T},
-        "q_nx10_plain": q_base, "cf10_plain": cf_base, "plain_s": t_base,
-        "q_nx10_refined": q_ref, "cf10_refined": cf_ref, "refined_s": t_ref,
-        "helper_and_mask_s": t_helper, "nn_edges_kept": kept, "knn_build_s": knn_s,
+        "quality_plain": q_base, "plain_s": t_base, "quality_refined": q_ref, "refined_s": t_ref,
+        "nn_edges_kept": kept, "knn_build_s": knn_s,
     }
 
 
@@ -592,6 +589,8 @@ def main():
     ap.add_argument("--no-graphs", action="store_true")
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB")
+    ap.add_argument("--no-sub", action="store_true",
+                    help="skip the differentiable-stress (C4) and encoder (C5) sub-records of the default run")
     ap.add_argument("--refine", action="store_true",
                     help="late-stage refinements (reverse-neighbour mask, l1) vs the plain loop")
     args = ap.parse_args()
@@ -616,6 +615,13 @@ def main():
         out = run_encoder(args, cfg)
     else:
         out = run_loop(args, cfg)
+        if cfg.name == "C3" and not args.no_sub:
+            # the differentiable stress and the parametric encoder at their own
+            # shapes, measured in the same run (sub-records; not the headline)
+            torch.cuda.empty_cache()
+            out["sub"] = {"C4": run_stress(args, synth.CONFIGS["C4"])}
+            torch.cuda.empty_cache()
+            out["sub"]["C5"] = run_encoder(args, synth.CONFIGS["C5"])
     print(json.dumps(out))
 
 
