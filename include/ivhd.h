@@ -53,9 +53,11 @@ typedef enum ivhd_mode {
     IVHD_MODE_DET = 0,     /* per-vertex gather over out-edges and transposed
                               in-edges, fixed order, no atomics: bitwise
                               reproducible run to run                        */
-    IVHD_MODE_ATOMIC = 1   /* per-vertex out-edge pass adding each reaction to
-                              the other end with float atomics, then an update
-                              pass; summation order varies run to run        */
+    IVHD_MODE_ATOMIC = 1   /* a pass that gathers each vertex's nn edges (both
+                              ways) and rn out-edges, adding each rn edge's
+                              reaction to the other end with float atomics,
+                              then an update pass; the order in which those
+                              reactions are summed varies run to run        */
 } ivhd_mode;
 
 /* ivhd_params.flags */

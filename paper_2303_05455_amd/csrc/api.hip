@@ -86,6 +86,7 @@ struct ivhd_ctx {
   int64_t *epoch = nullptr;
   int32_t *flags = nullptr;
   float2 *fbuf = nullptr;
+  float2 *fown = nullptr;
   int32_t *heavy = nullptr;
   int32_t n_heavy = 0;
   double *partials = nullptr;
@@ -117,7 +118,7 @@ void free_ctx(ivhd_ctx *c) {
   }
   void *bufs[] = {c->perm, c->inv, c->nn_own, c->ya, c->yb, c->v, c->tmp, c->nn_csc.ptr, c->nn_csc.src,
                   c->rn_csc.ptr, c->rn_csc.src, c->sc.cnt, c->sc.tmp, c->sc.part, c->sc.big, c->sc.rank, c->rn_idx,
-                  c->epoch, c->flags, c->fbuf, c->heavy, c->partials, c->d_E, c->ha, c->hb, c->vb,
+                  c->epoch, c->flags, c->fbuf, c->fown, c->heavy, c->partials, c->d_E, c->ha, c->hb, c->vb,
                   c->adapt, c->ke_part, c->s2, c->adam};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
@@ -170,6 +171,7 @@ StepArgs step_args(const ivhd_ctx *c, const float2 *y, float2 *y_out) {
   a.rn_ptr = c->rn_csc.ptr;
   a.rn_src = c->rn_csc.src;
   a.fbuf = c->fbuf;
+  a.fown = c->fown;
   a.flags = c->flags;
   a.gscale = nullptr;
   a.heavy = c->heavy;
@@ -426,12 +428,15 @@ int ivhd_init(ivhd_ctx **out, const ivhd_params *p, const int32_t *d_nn_idx, flo
       ALLOC(c->sc.rank, M * p->rn, "rn arrival ranks");
     }
   }
-  if (p->mode == IVHD_MODE_ATOMIC) ALLOC(c->fbuf, M, "force accumulator");
+  if (p->mode == IVHD_MODE_ATOMIC) {
+    ALLOC(c->fbuf, M, "rn reaction accumulator");
+    ALLOC(c->fown, M, "own force shares");
+  }
   if (p->flags & IVHD_FLAG_NESTEROV) {
     ALLOC(c->ha, M, "look-ahead positions");
     if (p->mode == IVHD_MODE_DET) ALLOC(c->hb, M, "second look-ahead buffer");
   }
-  if (p->mode == IVHD_MODE_DET) ALLOC(c->heavy, M, "heavy-vertex list");
+  ALLOC(c->heavy, M, "heavy-vertex list");
   c->nparts = stress_partials(M);
   ALLOC(c->partials, c->nparts, "stress partials");
   ALLOC(c->d_E, 1, "stress result");

@@ -155,7 +155,8 @@ struct StepArgs {
   const int32_t *rn_idx;  // [M][rn]
   const int32_t *nn_ptr, *nn_src;   // CSC of nn edges
   const int32_t *rn_ptr, *rn_src;   // CSC of rn edges
-  float2 *fbuf;           // atomic mode accumulator [M]
+  float2 *fbuf;           // atomic mode: accumulator of the rn reactions [M]
+  float2 *fown;           // atomic mode: each vertex's own share of its force [M]
   int32_t *flags;
   const float *gscale;    // gradient kernels: output scaled by *gscale (NULL = 1)
   const int32_t *heavy;   // vertices whose nn in-degree exceeds kHeavyDegree

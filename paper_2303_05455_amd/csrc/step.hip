@@ -25,9 +25,14 @@
 //     in flight.
 // Both orders of summation are fixed, so results are bitwise reproducible.
 //
-// Atomic mode: pass 1, one thread per vertex, walks its out-edges, keeps its
-// own share in registers and adds each reaction to the other end with a
-// float atomic; pass 2 applies the update and clears the accumulator.
+// Atomic mode: pass 1 is the deterministic kernel's walk without the rn
+// in-edges: each vertex gathers its nn edges both ways and its rn out-edges
+// (its own share, stored to fown) and adds each rn out-edge's reaction to
+// the other end's accumulator with float atomics; pass 2 adds the two,
+// applies the update and clears the accumulator.  Float atomics run at a
+// fixed rate of about 21 G/s on this chip whatever the footprint (measured),
+// so the mode keeps them to the rn edges: two per rn edge instead of two per
+// edge end.
 //
 // Variants of the thesis, chosen per context and compiled as template
 // parameters so the plain loop carries none of their cost:
@@ -112,7 +117,9 @@ __device__ __forceinline__ void gather_segment(const float2 *__restrict__ y, con
 
 // force on a light vertex: out-nn, out-rn, in-nn, in-rn, in that order.
 // Positions are gathered from A.h (Y, or the look-ahead H = Y + a V).
-template <bool L1>
+// With ARN (atomic mode) the rn in-edges are not gathered: each rn
+// out-edge's reaction goes to the other end's accumulator with float atomics.
+template <bool L1, bool ARN>
 __device__ __forceinline__ float2 light_force(const StepArgs &A, int64_t i, float2 yi, int32_t ns,
                                               int32_t ne) {
   const float2 *__restrict__ y = A.h;
@@ -129,38 +136,71 @@ __device__ __forceinline__ float2 light_force(const StepArgs &A, int64_t i, floa
     if (k >= 0) {
       const float2 t = rn_term<L1>(yi, y[k], A.c, A.eps);
       fx += t.x; fy += t.y;
+      if (ARN) {
+        unsafeAtomicAdd(&A.fbuf[k].x, -t.x);
+        unsafeAtomicAdd(&A.fbuf[k].y, -t.y);
+      }
     }
   }
   gather_segment<false, L1>(y, A.nn_src, ns, ne, yi, A.c, A.eps, fx, fy);
-  if (A.rn > 0) gather_segment<true, L1>(y, A.rn_src, A.rn_ptr[i], A.rn_ptr[i + 1], yi, A.c, A.eps, fx, fy);
+  if (!ARN && A.rn > 0)
+    gather_segment<true, L1>(y, A.rn_src, A.rn_ptr[i], A.rn_ptr[i + 1], yi, A.c, A.eps, fx, fy);
   return make_float2(fx, fy);
 }
 
 // force on a heavy vertex, computed by a whole wavefront: the vertex's edge
 // list (out-nn | out-rn | in-nn | in-rn) is split over the lanes round-robin,
 // then reduced with a fixed butterfly; every lane returns the total
-template <bool L1>
+template <bool L1, bool ARN>
 __device__ __forceinline__ float2 heavy_force(const StepArgs &A, int64_t i, float2 yi, int lane) {
   const float2 *__restrict__ y = A.h;
   const int32_t ns = A.nn_ptr[i], ne = A.nn_ptr[i + 1];
-  const int32_t rs = A.rn > 0 ? A.rn_ptr[i] : 0, re = A.rn > 0 ? A.rn_ptr[i + 1] : 0;
+  const int32_t rs = !ARN && A.rn > 0 ? A.rn_ptr[i] : 0, re = !ARN && A.rn > 0 ? A.rn_ptr[i + 1] : 0;
   const int32_t n_out = A.nn + A.rn, n_in_nn = ne - ns;
   const int32_t total = n_out + n_in_nn + (re - rs);
   float fx = 0.f, fy = 0.f;
-  for (int32_t e = lane; e < total; e += 64) {
-    float2 t;
-    if (e < A.nn) {
-      const int32_t j = A.nn_idx[i * A.nn + e];
-      t = j >= 0 ? nn_term<L1>(yi, y[j]) : make_float2(0.f, 0.f);
-    } else if (e < n_out) {
-      const int32_t k = A.rn_idx[i * A.rn + (e - A.nn)];
-      t = k >= 0 ? rn_term<L1>(yi, y[k], A.c, A.eps) : make_float2(0.f, 0.f);
-    } else if (e < n_out + n_in_nn) {
-      t = nn_term<L1>(yi, y[A.nn_src[ns + (e - n_out)]]);
-    } else {
-      t = rn_term<L1>(yi, y[A.rn_src[rs + (e - n_out - n_in_nn)]], A.c, A.eps);
+  // four of a lane's edges at a time: their index and position loads are
+  // issued together, the terms are still added in ascending edge order
+  for (int32_t e0 = lane; e0 < total; e0 += 4 * 64) {
+    int32_t other[4];
+    int kind[4];   // 0 none, 1 nn, 2 rn
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int32_t e = e0 + u * 64;
+      int32_t o = -1;
+      int k = 0;
+      if (e < total) {
+        if (e < A.nn) {
+          o = A.nn_idx[i * A.nn + e];
+          k = 1;
+        } else if (e < n_out) {
+          o = A.rn_idx[i * A.rn + (e - A.nn)];
+          k = 2;
+        } else if (e < n_out + n_in_nn) {
+          o = A.nn_src[ns + (e - n_out)];
+          k = 1;
+        } else {
+          o = A.rn_src[rs + (e - n_out - n_in_nn)];
+          k = 2;
+        }
+      }
+      other[u] = o;
+      kind[u] = o >= 0 ? k : 0;
     }
-    fx += t.x; fy += t.y;
+    float2 yo[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) yo[u] = kind[u] ? y[other[u]] : yi;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (!kind[u]) continue;
+      const float2 t = kind[u] == 1 ? nn_term<L1>(yi, yo[u]) : rn_term<L1>(yi, yo[u], A.c, A.eps);
+      fx += t.x; fy += t.y;
+      // an rn out-edge (the only rn edges listed with ARN): its reaction by atomics
+      if (ARN && kind[u] == 2) {
+        unsafeAtomicAdd(&A.fbuf[other[u]].x, -t.x);
+        unsafeAtomicAdd(&A.fbuf[other[u]].y, -t.y);
+      }
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -229,7 +269,10 @@ __device__ __forceinline__ void block_sum_store(double x, double *out) {
 // GRAD = true: out = s grad E = -2 s f with s = *gscale (1 when NULL), at
 // A.h = A.y; otherwise one iteration (force + update).  No thread leaves
 // before the ADAPT block sum.
-template <bool GRAD, bool L1, int OPT>
+// ARN = true is pass 1 of the atomic mode: each vertex's own share (its nn
+// edges both ways and its rn out-edges) goes to A.fown, the rn reactions to
+// A.fbuf by atomics; no update.
+template <bool GRAD, bool L1, int OPT, bool ARN = false>
 __global__ void __launch_bounds__(kDetBlock) det_kernel(StepArgs A, float2 *out) {
   double ke = 0.0;
   if ((int32_t)blockIdx.x < A.heavy_blocks) {
@@ -238,9 +281,11 @@ __global__ void __launch_bounds__(kDetBlock) det_kernel(StepArgs A, float2 *out)
     if (h < A.n_heavy) {   // uniform over the wavefront
       const int64_t i = A.heavy[h];
       const float2 hi = A.h[i];
-      const float2 f = heavy_force<L1>(A, i, hi, lane);
+      const float2 f = heavy_force<L1, ARN>(A, i, hi, lane);
       if (lane == 0) {
-        if (GRAD) {
+        if (ARN) {
+          A.fown[i] = f;
+        } else if (GRAD) {
           const float g = -2.f * (A.gscale ? *A.gscale : 1.f);
           out[i] = make_float2(g * f.x, g * f.y);
         } else {
@@ -259,8 +304,10 @@ __global__ void __launch_bounds__(kDetBlock) det_kernel(StepArgs A, float2 *out)
       const int32_t ns = A.nn_ptr[i], ne = A.nn_ptr[i + 1];
       if (ne - ns <= kHeavyDegree) {   // else served by a heavy wavefront
         const float2 hi = A.h[i];
-        const float2 f = light_force<L1>(A, i, hi, ns, ne);
-        if (GRAD) {
+        const float2 f = light_force<L1, ARN>(A, i, hi, ns, ne);
+        if (ARN) {
+          A.fown[i] = f;
+        } else if (GRAD) {
           const float g = -2.f * (A.gscale ? *A.gscale : 1.f);
           out[i] = make_float2(g * f.x, g * f.y);
         } else {
@@ -279,48 +326,23 @@ __global__ void heavy_list_kernel(const int32_t *__restrict__ nn_ptr, int64_t M,
   if (nn_ptr[i + 1] - nn_ptr[i] > kHeavyDegree) list[atomicAdd(count, 1)] = (int32_t)i;
 }
 
-template <bool L1>
-__global__ void __launch_bounds__(kBlock) scatter_force_kernel(StepArgs A) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= A.M) return;
-  const float2 *__restrict__ y = A.h;
-  const float2 yi = y[i];
-  float fx = 0.f, fy = 0.f;
-  for (int q = 0; q < A.nn; ++q) {
-    const int32_t j = A.nn_idx[i * A.nn + q];
-    if (j >= 0) {
-      float2 t = nn_term<L1>(yi, y[j]);
-      fx += t.x; fy += t.y;
-      unsafeAtomicAdd(&A.fbuf[j].x, -t.x);
-      unsafeAtomicAdd(&A.fbuf[j].y, -t.y);
-    }
-  }
-  for (int q = 0; q < A.rn; ++q) {
-    const int32_t k = A.rn_idx[i * A.rn + q];
-    float2 t = rn_term<L1>(yi, y[k], A.c, A.eps);
-    fx += t.x; fy += t.y;
-    unsafeAtomicAdd(&A.fbuf[k].x, -t.x);
-    unsafeAtomicAdd(&A.fbuf[k].y, -t.y);
-  }
-  unsafeAtomicAdd(&A.fbuf[i].x, fx);
-  unsafeAtomicAdd(&A.fbuf[i].y, fy);
-}
-
 // update after the scatter pass; in place (y_out == y), H rewritten in place
 template <int OPT>
 __global__ void __launch_bounds__(kBlock) atomic_update_kernel(StepArgs A) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.M) return;
-  const float2 f = A.fbuf[i];
+  const float2 fo = A.fown[i], fr = A.fbuf[i];
+  const float2 f = make_float2(fo.x + fr.x, fo.y + fr.y);
   A.fbuf[i] = make_float2(0.f, 0.f);
   (void)apply_update<OPT>(A, i, OPT == OPT_NEST ? make_float2(0.f, 0.f) : A.y[i], f);
 }
 
-__global__ void __launch_bounds__(kBlock) atomic_grad_out_kernel(float2 *fbuf, int64_t M, const float *gscale,
-                                                                float2 *out) {
+__global__ void __launch_bounds__(kBlock) atomic_grad_out_kernel(const float2 *fown, float2 *fbuf, int64_t M,
+                                                                const float *gscale, float2 *out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M) return;
-  const float2 f = fbuf[i];
+  const float2 fo = fown[i], fr = fbuf[i];
+  const float2 f = make_float2(fo.x + fr.x, fo.y + fr.y);
   fbuf[i] = make_float2(0.f, 0.f);
   const float g = -2.f * (gscale ? *gscale : 1.f);
   out[i] = make_float2(g * f.x, g * f.y);
@@ -436,8 +458,8 @@ hipError_t launch_step_det(const StepArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_step_atomic(const StepArgs &a, hipStream_t s) {
-  if (a.l1) scatter_force_kernel<true><<<grid_for(a.M), kBlock, 0, s>>>(a);
-  else scatter_force_kernel<false><<<grid_for(a.M), kBlock, 0, s>>>(a);
+  if (a.l1) det_kernel<false, true, OPT_PLAIN, true><<<det_grid(a), kDetBlock, 0, s>>>(a, nullptr);
+  else det_kernel<false, false, OPT_PLAIN, true><<<det_grid(a), kDetBlock, 0, s>>>(a, nullptr);
   if (a.opt == OPT_NEST) atomic_update_kernel<OPT_NEST><<<grid_for(a.M), kBlock, 0, s>>>(a);
   else atomic_update_kernel<OPT_PLAIN><<<grid_for(a.M), kBlock, 0, s>>>(a);
   return hipGetLastError();
@@ -450,9 +472,9 @@ hipError_t launch_grad_det(const StepArgs &a, float2 *out, hipStream_t s) {
 }
 
 hipError_t launch_grad_atomic(const StepArgs &a, float2 *out, hipStream_t s) {
-  if (a.l1) scatter_force_kernel<true><<<grid_for(a.M), kBlock, 0, s>>>(a);
-  else scatter_force_kernel<false><<<grid_for(a.M), kBlock, 0, s>>>(a);
-  atomic_grad_out_kernel<<<grid_for(a.M), kBlock, 0, s>>>(a.fbuf, a.M, a.gscale, out);
+  if (a.l1) det_kernel<false, true, OPT_PLAIN, true><<<det_grid(a), kDetBlock, 0, s>>>(a, nullptr);
+  else det_kernel<false, false, OPT_PLAIN, true><<<det_grid(a), kDetBlock, 0, s>>>(a, nullptr);
+  atomic_grad_out_kernel<<<grid_for(a.M), kBlock, 0, s>>>(a.fown, a.fbuf, a.M, a.gscale, out);
   return hipGetLastError();
 }
 
