@@ -141,6 +141,37 @@ def cpu_baseline(cfg, iters, seed=0):
     }
 
 
+def gather_ceiling(M, nn, rn, kernel_s, dev, reps=20):
+    """A second, labelled bound for the step kernel, which is bound by random
+    8-byte position gathers (2 M (nn + rn) per iteration: every edge read from
+    both ends): the time of the same number of gathers alone (the library's
+    probe kernel, one 8-byte load and store per index), from one eighth of the
+    position rows (one XCD's share, resident in its L2) and uniformly from all
+    M rows (the footprint of the loop)."""
+    import torch
+    from paper_2303_05455_amd import ivhd_probe_gather
+    G = 2 * M * (nn + rn)
+    gen = torch.Generator().manual_seed(7)
+    src = torch.rand((M, 2), generator=gen).to(dev)
+    out = torch.empty((G, 2), dtype=torch.float32, device=dev)
+    res = {"gathers_per_launch": G}
+    for name, n_src in (("l2_resident_us", max(1, M // 8)), ("uniform_us", M)):
+        idx = torch.randint(0, n_src, (G,), dtype=torch.int32, generator=gen).to(dev)
+        ivhd_probe_gather(src, idx, out)
+        torch.cuda.synchronize()
+        e0, e1 = events()
+        e0.record()
+        for _ in range(reps):
+            ivhd_probe_gather(src, idx, out)
+        e1.record()
+        torch.cuda.synchronize()
+        res[name] = e0.elapsed_time(e1) * 1e3 / reps
+        del idx
+    res["kernel_us"] = kernel_s * 1e6
+    res["kernel_vs_l2_resident"] = res["l2_resident_us"] / res["kernel_us"]
+    return res
+
+
 def calibrate_copy(mib: int):
     """A plain device copy of known size, for scaling the FETCH_SIZE and
     WRITE_SIZE counters (run under rocprofv3 --pmc)."""
@@ -276,9 +307,12 @@ def run_loop(args, cfg):
             "frac": achieved / HBM_PEAK_GBPS, "traffic": stored_traffic() if cfg.name == "C3" else None,
             "kernel": "det_kernel", "alg_bytes_per_launch": alg_bytes(M, nn, rn),
             "us_per_launch": per_launch * 1e6,
+            "gather_ceiling": gather_ceiling(M, nn, rn, per_launch, dev),
         }
         log(f"det step kernel: {per_launch * 1e6:.2f} us/launch, {achieved:.0f} GB/s algorithmic "
-            f"({achieved / HBM_PEAK_GBPS:.1%} of 8 TB/s)")
+            f"({achieved / HBM_PEAK_GBPS:.1%} of 8 TB/s); the same number of random gathers alone: "
+            f"{roofline['gather_ceiling']['l2_resident_us']:.1f} us from one L2's share of the positions, "
+            f"{roofline['gather_ceiling']['uniform_us']:.1f} us uniform over all of them")
 
     # the thesis's variants of the loop on the same workload (det mode).  The
     # look-ahead and the l1 distance lower the stability bound of b (Nesterov:

@@ -63,8 +63,9 @@ typedef enum ivhd_mode {
 /* ivhd_params.flags */
 #define IVHD_FLAG_REORDER 1   /* keep the vertices internally grouped by connected
                                  component of the nn graph (smallest id first), and
-                                 inside a component by nn in-degree capped at 81,
-                                 ties by id (a locality and load-balance order; the
+                                 inside a component by nn in-degree capped at 81
+                                 (17 below 500,000 vertices), ties by id (a
+                                 locality and load-balance order; the
                                  results are the same up to floating-point summation
                                  order, and the caller always sees its own order)  */
 #define IVHD_FLAG_NESTEROV 2  /* Nesterov momentum (Sec. "Optimization methods"): the

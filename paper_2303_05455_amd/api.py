@@ -25,7 +25,7 @@ __all__ = [
     "ivhd_edges_grad", "ivhd_edges_destroy", "ivhd_grad_edges", "ivhd_grad_edges_noalloc",
     "ivhd_set_adaptive",
     "ivhd_get_adaptive", "ivhd_rnn_mask", "ivhd_set_adam", "ivhd_ivf_train", "ivhd_ivf_search",
-    "ivf_knn_graph", "ivhd_eval_neighbours", "ivhd_eval_ranks", "ivhd_eval_scores",
+    "ivf_knn_graph", "ivhd_eval_neighbours", "ivhd_eval_ranks", "ivhd_eval_scores", "ivhd_probe_gather",
 ]
 
 
@@ -569,3 +569,18 @@ def ivhd_eval_scores(M: int, rows: torch.Tensor, nx: Optional[torch.Tensor], ny:
     check(_lib.load().ivhd_eval_scores(M, rows.data_ptr(), Q, p_nx, kx, ny.data_ptr(), ky, p_rank, p_lab, k,
                                        ctypes.cast(h, ctypes.c_void_p), _stream_handle(stream)))
     return h[0], h[1], h[2]
+
+
+def ivhd_probe_gather(src: torch.Tensor, idx: torch.Tensor, out: Optional[torch.Tensor] = None,
+                      stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """out[t] = src[idx[t]] for float32 [n_src, 2] rows (a random-gather rate probe)."""
+    n_src = src.shape[0]
+    _dev(src, torch.float32, (n_src, 2), "src")
+    n = idx.shape[0]
+    _dev(idx, torch.int32, (n,), "idx")
+    if out is None:
+        out = torch.empty((n, 2), dtype=torch.float32, device=src.device)
+    _dev(out, torch.float32, (n, 2), "out")
+    check(_lib.load().ivhd_probe_gather(src.data_ptr(), n_src, idx.data_ptr(), n, out.data_ptr(),
+                                        _stream_handle(stream)))
+    return out

@@ -89,6 +89,7 @@ struct ivhd_ctx {
   float2 *fown = nullptr;
   int32_t *heavy = nullptr;
   int32_t n_heavy = 0;
+  int32_t heavy_deg = kHeavyDegree;
   double *partials = nullptr;
   int nparts = 0;
   double *d_E = nullptr;
@@ -176,6 +177,7 @@ StepArgs step_args(const ivhd_ctx *c, const float2 *y, float2 *y_out) {
   a.gscale = nullptr;
   a.heavy = c->heavy;
   a.n_heavy = c->n_heavy;
+  a.heavy_deg = c->heavy_deg;
   a.M = c->p.M;
   a.nn = c->p.nn;
   a.rn = c->p.rn;
@@ -289,7 +291,7 @@ int capture(ivhd_ctx *c, bool with_draw, int64_t count, int par, hipGraphExec_t 
 
 // the internal order: vertices grouped by connected component of the nn
 // graph (components by their smallest caller id), inside a component by nn
-// in-degree capped at kHeavyDegree + 1, then by caller id
+// in-degree capped at the hub threshold + 1, then by caller id
 int build_order(ivhd_ctx *c) {
   const int64_t M = c->p.M;
   hipStream_t s = c->stream;
@@ -309,7 +311,7 @@ int build_order(ivhd_ctx *c) {
   int32_t *indeg = c->sc.cnt;           // [M+1] scratch until the nn lists are transposed
   HIPCHK(launch_fill_i32(indeg, M + 1, 0, s));
   HIPCHK(launch_count(c->nn_user, M, c->p.nn, indeg, s));
-  int rc = sort_vertex_order(parent, indeg, M, c->perm, s);
+  int rc = sort_vertex_order(parent, indeg, M, c->heavy_deg, c->perm, s);
   if (rc) return rc;
   HIPCHK(launch_inverse_perm(c->perm, M, c->inv, s));
   HIPCHK(launch_map_lists(c->nn_user, M, c->p.nn, c->perm, c->inv, c->nn_own, s));
@@ -451,6 +453,7 @@ int ivhd_init(ivhd_ctx **out, const ivhd_params *p, const int32_t *d_nn_idx, flo
     free_ctx(c);
     return fail(IVHD_EINVAL, "nn_idx holds an entry outside [-1, M) or a self edge");
   }
+  c->heavy_deg = heavy_degree(M);
   if (reorder) {
     CHK(build_order(c));
     c->nn_int = c->nn_own;
@@ -458,7 +461,7 @@ int ivhd_init(ivhd_ctx **out, const ivhd_params *p, const int32_t *d_nn_idx, flo
     c->nn_int = d_nn_idx;
   }
   CHK(build_csc(c->nn_int, M, p->nn, c->nn_csc, c->sc, c->flags, s));
-  if (c->heavy) CHK(build_heavy(c->nn_csc, M, c->heavy, c->flags, &c->n_heavy, s));
+  if (c->heavy) CHK(build_heavy(c->nn_csc, M, c->heavy_deg, c->heavy, c->flags, &c->n_heavy, s));
   if (c->fbuf) HIPCHK_C(launch_fill_i32((int32_t *)c->fbuf, 2 * M, 0, s));
   CHK(load_state(c, c->y_user, c->v_user));
   const int64_t minus_one = -1;

@@ -14,7 +14,8 @@ constexpr int kScanItems = 8;        // items per thread in the block scan
 constexpr int kScanChunk = kBlock * kScanItems;
 constexpr int kSmallSegment = 32;    // in-edge segments up to this size are sorted per thread
 constexpr int kBigSortBlocks = 256;  // blocks that share the list of large segments
-constexpr int kHeavyDegree = 80;     // nn in-degree above which a vertex gets a whole wavefront
+constexpr int kHeavyDegree = 80;     // nn in-degree above which a vertex gets a whole wavefront (large graphs)
+constexpr int kSmallGraphHeavyDegree = 16;   // the same below 500,000 vertices
 constexpr int kDetBlock = 64;        // threads per block of the deterministic step kernel (one wavefront)
 constexpr int kHeavyPerBlock = kDetBlock / 64;
 constexpr int kXcds = 8;             // MI355X: 8 XCDs, workgroups dealt round-robin
@@ -116,9 +117,10 @@ hipError_t launch_scatter_sort(const int32_t *idx, int64_t M, int k, const int32
                                int32_t *src_out, hipStream_t s);
 
 // ---- order.hip ----
-// perm = the ids 0..M-1 sorted by (root[i], min(indeg[i], kHeavyDegree + 1), i);
+// perm = the ids 0..M-1 sorted by (root[i], min(indeg[i], heavy_deg + 1), i);
 // synchronises s
-int sort_vertex_order(const int32_t *root, const int32_t *indeg, int64_t M, int32_t *perm, hipStream_t s);
+int sort_vertex_order(const int32_t *root, const int32_t *indeg, int64_t M, int heavy_deg, int32_t *perm,
+                      hipStream_t s);
 
 // ---- step.hip ----
 // device state of the self-adaptive b
@@ -159,8 +161,9 @@ struct StepArgs {
   float2 *fown;           // atomic mode: each vertex's own share of its force [M]
   int32_t *flags;
   const float *gscale;    // gradient kernels: output scaled by *gscale (NULL = 1)
-  const int32_t *heavy;   // vertices whose nn in-degree exceeds kHeavyDegree
+  const int32_t *heavy;   // vertices whose nn in-degree exceeds heavy_deg
   int32_t n_heavy;
+  int32_t heavy_deg;      // nn in-degree above which a vertex gets a whole wavefront
   int32_t heavy_blocks;   // leading blocks of a launch that serve the heavy vertices (multiple of kXcds)
   int32_t light_tiles;    // tiles of kDetBlock consecutive vertices
   int32_t tiles_per_xcd;  // consecutive tiles given to each XCD
@@ -194,9 +197,14 @@ hipError_t launch_grad_atomic(const StepArgs &a, float2 *out, hipStream_t s);
 
 // transposed lists of an [M][k] index list into g; the heavy list (synchronises s)
 int build_csc(const int32_t *idx, int64_t M, int k, Csc &g, CscScratch &sc, int32_t *flags, hipStream_t s);
-int build_heavy(const Csc &nn_csc, int64_t M, int32_t *heavy, int32_t *flags, int32_t *n_heavy, hipStream_t s);
-// list the vertices with nn in-degree > kHeavyDegree (order arbitrary); *count must be zero
-hipError_t launch_heavy_list(const int32_t *nn_ptr, int64_t M, int32_t *list, int32_t *count,
+int build_heavy(const Csc &nn_csc, int64_t M, int heavy_deg, int32_t *heavy, int32_t *flags, int32_t *n_heavy,
+                hipStream_t s);
+// the hub threshold of a graph of M vertices: kHeavyDegree for large graphs;
+// small graphs have too few wavefronts to hide a thread's long in-edge chain,
+// so more of their vertices get a wavefront
+int heavy_degree(int64_t M);
+// list the vertices with nn in-degree > heavy_deg (order arbitrary); *count must be zero
+hipError_t launch_heavy_list(const int32_t *nn_ptr, int64_t M, int heavy_deg, int32_t *list, int32_t *count,
                              hipStream_t s);
 
 // ---- reduce.hip ----

@@ -139,7 +139,8 @@ int ivhd_grad_edges_noalloc(const float *d_y, int64_t M, const int32_t *d_nn_idx
   if ((rc = build_csc(d_nn_idx, M, nn, nn_csc, sc, L.flags, s))) return rc;
   if (rn > 0 && (rc = build_csc(d_rn_idx, M, rn, rn_csc, sc, L.flags, s))) return rc;
   int32_t n_heavy = 0;
-  if ((rc = build_heavy(nn_csc, M, L.heavy, L.flags, &n_heavy, s))) return rc;
+  const int heavy_deg = heavy_degree(M);
+  if ((rc = build_heavy(nn_csc, M, heavy_deg, L.heavy, L.flags, &n_heavy, s))) return rc;
 
   StepArgs a{};
   a.y = (const float2 *)d_y;
@@ -154,6 +155,7 @@ int ivhd_grad_edges_noalloc(const float *d_y, int64_t M, const int32_t *d_nn_idx
   a.gscale = nullptr;
   a.heavy = L.heavy;
   a.n_heavy = n_heavy;
+  a.heavy_deg = heavy_deg;
   a.M = M;
   a.nn = nn;
   a.rn = rn;

@@ -2,7 +2,7 @@
 //
 // Vertices are grouped by connected component of the undirected nn graph
 // (components ordered by their smallest id), and inside a component by nn
-// in-degree, capped at kHeavyDegree + 1, ties by id.
+// in-degree, capped at the hub threshold + 1, ties by id.
 //
 // Why: the deterministic step gives one thread to each light vertex, and a
 // wavefront lasts as long as its slowest lane.  kNN graphs of
@@ -26,17 +26,19 @@ constexpr int kDegreeBits = 7;
 static_assert(kHeavyDegree + 1 < (1 << kDegreeBits), "degree cap must fit the key's low bits");
 
 __global__ void order_keys_kernel(const int32_t *__restrict__ root, const int32_t *__restrict__ indeg,
-                                  int64_t M, uint64_t *__restrict__ keys, int32_t *__restrict__ ids) {
+                                  int64_t M, int cap, uint64_t *__restrict__ keys, int32_t *__restrict__ ids) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M) return;
-  const int32_t d = indeg[i] < kHeavyDegree + 1 ? indeg[i] : kHeavyDegree + 1;
+  const int32_t d = indeg[i] < cap ? indeg[i] : cap;
   keys[i] = ((uint64_t)(uint32_t)root[i] << kDegreeBits) | (uint64_t)d;
   ids[i] = (int32_t)i;
 }
 
 }  // namespace
 
-int sort_vertex_order(const int32_t *root, const int32_t *indeg, int64_t M, int32_t *perm, hipStream_t s) {
+int sort_vertex_order(const int32_t *root, const int32_t *indeg, int64_t M, int heavy_deg, int32_t *perm,
+                      hipStream_t s) {
+  if (heavy_deg < 0 || heavy_deg + 1 >= (1 << kDegreeBits)) return fail(IVHD_EINVAL, "hub threshold %d", heavy_deg);
   int end_bit = kDegreeBits;
   while ((int64_t{1} << (end_bit - kDegreeBits)) < M) ++end_bit;
   uint64_t *keys = nullptr, *keys_out = nullptr;
@@ -57,7 +59,7 @@ int sort_vertex_order(const int32_t *root, const int32_t *indeg, int64_t M, int3
     cleanup();
     return rc;
   }
-  order_keys_kernel<<<grid_for(M), kBlock, 0, s>>>(root, indeg, M, keys, ids);
+  order_keys_kernel<<<grid_for(M), kBlock, 0, s>>>(root, indeg, M, heavy_deg + 1, keys, ids);
   e = hipGetLastError();
   if (e == hipSuccess)
     e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, keys_out, ids, perm, (int)M, 0, end_bit, s);

@@ -25,11 +25,15 @@ int build_csc(const int32_t *idx, int64_t M, int k, Csc &g, CscScratch &sc, int3
   return IVHD_OK;
 }
 
-// the vertices of nn in-degree above kHeavyDegree; synchronises s to read the count
-int build_heavy(const Csc &nn_csc, int64_t M, int32_t *heavy, int32_t *flags, int32_t *n_heavy,
+// measured: 70,000 vertices (nn = 5) 9.6 us per step at 16 against 11.2 us at
+// 80; 1.4M vertices (nn = 2) 67.9 us at 80 against 69.2 at 48 and 69.0 at 100
+int heavy_degree(int64_t M) { return M < 500000 ? kSmallGraphHeavyDegree : kHeavyDegree; }
+
+// the vertices of nn in-degree above heavy_deg; synchronises s to read the count
+int build_heavy(const Csc &nn_csc, int64_t M, int heavy_deg, int32_t *heavy, int32_t *flags, int32_t *n_heavy,
                 hipStream_t s) {
   HIPCHK(launch_fill_i32(flags + FLAG_BIG_COUNT, 1, 0, s));
-  HIPCHK(launch_heavy_list(nn_csc.ptr, M, heavy, flags + FLAG_BIG_COUNT, s));
+  HIPCHK(launch_heavy_list(nn_csc.ptr, M, heavy_deg, heavy, flags + FLAG_BIG_COUNT, s));
   HIPCHK(hipMemcpyAsync(n_heavy, flags + FLAG_BIG_COUNT, sizeof *n_heavy, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   return IVHD_OK;
@@ -50,6 +54,7 @@ struct ivhd_edges {
   CscScratch sc;
   int32_t *heavy = nullptr;
   int32_t n_heavy = 0;
+  int32_t heavy_deg = kHeavyDegree;
   int32_t *flags = nullptr;
   double *partials = nullptr;
   int nparts = 0;
@@ -88,6 +93,7 @@ StepArgs edge_args(const ivhd_edges *e, const float2 *y, float c, float eps, con
   a.gscale = gscale;
   a.heavy = e->heavy;
   a.n_heavy = e->n_heavy;
+  a.heavy_deg = e->heavy_deg;
   a.M = e->M;
   a.nn = e->nn;
   a.rn = e->rn;
@@ -164,7 +170,8 @@ int ivhd_edges_create(ivhd_edges **out, int64_t M, const int32_t *d_nn_idx, int3
   }
   E_CHK(build_csc(d_nn_idx, M, nn, e->nn_csc, e->sc, e->flags, s));
   if (rn > 0) E_CHK(build_csc(d_rn_idx, M, rn, e->rn_csc, e->sc, e->flags, s));
-  E_CHK(build_heavy(e->nn_csc, M, e->heavy, e->flags, &e->n_heavy, s));
+  e->heavy_deg = heavy_degree(M);
+  E_CHK(build_heavy(e->nn_csc, M, e->heavy_deg, e->heavy, e->flags, &e->n_heavy, s));
 #undef E_CHK
 #undef E_HIP
   {
@@ -479,3 +486,16 @@ int ivhd_rnn_mask(const int32_t *d_nn_idx, int64_t M, int32_t nn, const int32_t 
 }
 
 }  // extern "C"
+
+#include "ivhd_probe.h"
+
+extern "C" int ivhd_probe_gather(const float *d_src, int64_t n_src, const int32_t *d_idx, int64_t n, float *d_dst,
+                                 void *stream) {
+  clear_error();
+  if (n < 0 || n_src < 1) return fail(IVHD_EINVAL, "n = %lld and n_src = %lld must be >= 0 and >= 1",
+                                      (long long)n, (long long)n_src);
+  if (n == 0) return IVHD_OK;
+  if (!d_src || !d_idx || !d_dst) return fail(IVHD_EINVAL, "d_src, d_idx and d_dst must not be NULL");
+  HIPCHK(launch_gather_f2((const float2 *)d_src, d_idx, n, (float2 *)d_dst, (hipStream_t)stream));
+  return IVHD_OK;
+}

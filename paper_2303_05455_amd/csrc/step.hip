@@ -18,7 +18,7 @@
 // iteration behind its chain of dependent loads.  So the work is split by
 // degree:
 //   * the first `heavy_blocks` blocks give each vertex of nn in-degree above
-//     kHeavyDegree a whole wavefront: the 64 lanes stride over its edge list
+//     heavy_deg a whole wavefront: the 64 lanes stride over its edge list
 //     and a fixed xor-butterfly adds their partial sums;
 //   * the other blocks give each remaining vertex one thread, which issues
 //     its in-edge gathers eight (then four) at a time so several loads are
@@ -302,7 +302,7 @@ __global__ void __launch_bounds__(kDetBlock) det_kernel(StepArgs A, float2 *out)
     const int64_t i = (int64_t)tile * kDetBlock + threadIdx.x;
     if (tile < A.light_tiles && i < A.M) {
       const int32_t ns = A.nn_ptr[i], ne = A.nn_ptr[i + 1];
-      if (ne - ns <= kHeavyDegree) {   // else served by a heavy wavefront
+      if (ne - ns <= A.heavy_deg) {   // else served by a heavy wavefront
         const float2 hi = A.h[i];
         const float2 f = light_force<L1, ARN>(A, i, hi, ns, ne);
         if (ARN) {
@@ -319,11 +319,11 @@ __global__ void __launch_bounds__(kDetBlock) det_kernel(StepArgs A, float2 *out)
   if (OPT == OPT_ADAPT) block_sum_store(ke, A.ke_part + blockIdx.x);
 }
 
-__global__ void heavy_list_kernel(const int32_t *__restrict__ nn_ptr, int64_t M, int32_t *list,
+__global__ void heavy_list_kernel(const int32_t *__restrict__ nn_ptr, int64_t M, int heavy_deg, int32_t *list,
                                   int32_t *count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M) return;
-  if (nn_ptr[i + 1] - nn_ptr[i] > kHeavyDegree) list[atomicAdd(count, 1)] = (int32_t)i;
+  if (nn_ptr[i + 1] - nn_ptr[i] > heavy_deg) list[atomicAdd(count, 1)] = (int32_t)i;
 }
 
 // update after the scatter pass; in place (y_out == y), H rewritten in place
@@ -435,9 +435,9 @@ hipError_t launch_adapt_commit(const AdaptState *st, const float2 *y, const floa
 
 unsigned det_grid(const StepArgs &a) { return (unsigned)(a.heavy_blocks + kXcds * a.tiles_per_xcd); }
 
-hipError_t launch_heavy_list(const int32_t *nn_ptr, int64_t M, int32_t *list, int32_t *count,
+hipError_t launch_heavy_list(const int32_t *nn_ptr, int64_t M, int heavy_deg, int32_t *list, int32_t *count,
                              hipStream_t s) {
-  heavy_list_kernel<<<grid_for(M), kBlock, 0, s>>>(nn_ptr, M, list, count);
+  heavy_list_kernel<<<grid_for(M), kBlock, 0, s>>>(nn_ptr, M, heavy_deg, list, count);
   return hipGetLastError();
 }
 

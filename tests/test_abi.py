@@ -25,18 +25,23 @@ def _declared(header):
     return sorted(set(re.findall(r"\b(ivhd_\w+)\s*\(", text)))
 
 
+HEADERS = sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
+
+
 def test_every_declared_symbol_is_exported(lib):
     names = _declared("ivhd.h")
     assert "ivhd_init" in names and "ivhd_step" in names
-    for n in names:
-        assert hasattr(lib, n), n
+    for h in HEADERS:
+        for n in _declared(h):
+            assert hasattr(lib, n), (h, n)
 
 
 def test_binding_covers_every_declared_symbol():
     from paper_2303_05455_amd import _lib, api
-    for n in _declared("ivhd.h"):
-        assert n in _lib.SIGNATURES, n
-        assert hasattr(api, n), n
+    for h in HEADERS:
+        for n in _declared(h):
+            assert n in _lib.SIGNATURES, n
+            assert hasattr(api, n), n
 
 
 def test_struct_layout_matches_header():
@@ -171,3 +176,10 @@ def test_eval_calls_reject_bad_sizes_before_device_work(lib):
     assert "d_rank_y needs d_nx" in lib.ivhd_last_error().decode()
     assert lib.ivhd_eval_scores(100, FAKE, 0, None, 0, FAKE, 10, None, None, 6, ctypes.cast(out, ctypes.c_void_p),
                                 None) == -1
+
+
+def test_probe_gather_rejects_bad_sizes(lib):
+    assert lib.ivhd_probe_gather(FAKE, 0, FAKE, 10, FAKE, None) == -1
+    assert lib.ivhd_probe_gather(FAKE, 10, FAKE, -1, FAKE, None) == -1
+    assert lib.ivhd_probe_gather(None, 10, FAKE, 5, FAKE, None) == -1
+    assert lib.ivhd_probe_gather(None, 10, None, 0, None, None) == 0
