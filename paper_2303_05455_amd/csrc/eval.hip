@@ -13,11 +13,11 @@
 //
 // eval_scan_kernel: one wavefront per 64 sample rows (one row per lane) and
 // one contiguous chunk of the candidates (blockIdx.y).  Candidate tiles are
-// staged in LDS as FP64 and read by all lanes at once (broadcast); each lane
-// keeps its row's best k + 1 (distance, index) pairs sorted in LDS
-// (neighbour mode) or counts, for each of its kc thresholds, the candidates
-// that come before it (rank mode).  A merge kernel takes the best k + 1 of
-// the chunks' lists and drops position 0.
+// staged in LDS as FP64, a chunk of dimensions at a time, and read by all
+// lanes at once (broadcast); each lane keeps its row's best k + 1 (distance,
+// index) pairs sorted in LDS (neighbour mode) or counts, for each of its kc
+// thresholds, the candidates that come before it (rank mode).  A merge
+// kernel takes the best k + 1 of the chunks' lists and drops position 0.
 #include <cfloat>
 #include <climits>
 #include <cmath>
@@ -28,56 +28,30 @@ namespace ivhd {
 namespace {
 
 constexpr int kEvalLanes = 64;
-constexpr int kEvalDimChunk = 32;
+constexpr int kEvalTile = 32;       // candidates per tile
+constexpr int kEvalDimChunk = 32;   // dimensions staged at a time (2 for 2-D layouts, 8 up to 8-D)
 
 __device__ __forceinline__ bool pair_before(double a, int32_t ia, double b, int32_t ib) {
   return a < b || (a == b && ia < ib);
 }
 
-// sum over n of ((double)z_c[n] - (double)q[n])^2 for the TC candidates of
-// an LDS tile (rows of pitch np doubles), in dimension order
-template <int TC>
-__device__ __forceinline__ void tile_distances(const double *__restrict__ tile, int np, const float *__restrict__ qrow,
-                                               bool qvalid, int N, double (&acc)[TC]) {
-#pragma unroll
-  for (int c = 0; c < TC; ++c) acc[c] = 0.0;
-  for (int n0 = 0; n0 < N; n0 += kEvalDimChunk) {
-    double qv[kEvalDimChunk];
-#pragma unroll
-    for (int d = 0; d < kEvalDimChunk; ++d) qv[d] = (qvalid && n0 + d < N) ? (double)qrow[n0 + d] : 0.0;
-    const int dn = N - n0 < kEvalDimChunk ? N - n0 : kEvalDimChunk;
-    if (dn == kEvalDimChunk) {
-#pragma unroll
-      for (int d = 0; d < kEvalDimChunk; ++d) {
-#pragma unroll
-        for (int c = 0; c < TC; ++c) {
-          const double t = tile[c * np + n0 + d] - qv[d];
-          acc[c] = __dadd_rn(acc[c], __dmul_rn(t, t));
-        }
-      }
-    } else {
-      for (int d = 0; d < dn; ++d) {
-#pragma unroll
-        for (int c = 0; c < TC; ++c) {
-          const double t = tile[c * np + n0 + d] - qv[d];
-          acc[c] = __dadd_rn(acc[c], __dmul_rn(t, t));
-        }
-      }
-    }
-  }
-}
-
-// MODE 0: neighbour lists; MODE 1: rank counts.  Dynamic LDS: the tile
-// [TC][np] doubles, then per lane either the list (k + 1 doubles and k + 1
-// ints) or the thresholds and counts (kc doubles, kc ints, kc ints).
-template <int MODE, int TC>
+// MODE 0: neighbour lists; MODE 1: rank counts.  Candidates go in tiles of
+// kEvalTile; each tile's coordinates are staged in LDS as FP64 one chunk of
+// kEvalDimChunk dimensions at a time (read by all lanes at once) while each
+// lane's own row chunk sits in registers, and every lane keeps the tile's
+// kEvalTile running distances in registers, adding dimensions in order.
+// Dynamic LDS: the chunk [kEvalTile][kEvalDimChunk] doubles, each lane's
+// kEvalTile finished distances, then per lane either the list (kl doubles
+// and kl ints) or the thresholds and counts (kl doubles, kl ints, kl ints).
+template <int MODE, int DC>
 __global__ void __launch_bounds__(kEvalLanes)
-eval_scan_kernel(const float *__restrict__ Z, int64_t M, int N, int np, const int32_t *__restrict__ rows,
-                 int64_t Q, int kl, int64_t chunk, const int32_t *__restrict__ cand, double *__restrict__ part_d,
+eval_scan_kernel(const float *__restrict__ Z, int64_t M, int N, const int32_t *__restrict__ rows, int64_t Q, int kl,
+                 int64_t chunk, const int32_t *__restrict__ cand, double *__restrict__ part_d,
                  int32_t *__restrict__ part_i, int32_t *__restrict__ rank_out) {
   extern __shared__ __attribute__((aligned(16))) unsigned char eval_lds[];
-  double *tile = (double *)eval_lds;
-  double *ld = tile + (size_t)TC * np;                      // [64][kl]
+  double *tile = (double *)eval_lds;                        // [kEvalTile][DC]
+  double *dist = tile + kEvalTile * DC;          // [64][kEvalTile]: each lane's tile distances
+  double *ld = dist + kEvalLanes * kEvalTile;               // [64][kl]
   int32_t *li = (int32_t *)(ld + (size_t)kEvalLanes * kl);  // [64][kl]
   int32_t *lc = li + (size_t)kEvalLanes * kl;               // rank mode: [64][kl] counts
   const int lane = threadIdx.x;
@@ -107,23 +81,40 @@ eval_scan_kernel(const float *__restrict__ Z, int64_t M, int N, int np, const in
   }
   const int64_t c0 = (int64_t)blockIdx.y * chunk;
   const int64_t c1 = c0 + chunk < M ? c0 + chunk : M;
-  for (int64_t t0 = c0; t0 < c1; t0 += TC) {
-    __syncthreads();
-    // stage the tile (rows past c1 are zero and never used)
-    for (int e = lane; e < TC * np; e += kEvalLanes) {
-      const int c = e / np, n = e - c * np;
-      const int64_t row = t0 + c;
-      tile[e] = (row < c1 && n < N) ? (double)Z[row * N + n] : 0.0;
-    }
-    __syncthreads();
-    double acc[TC];
-    tile_distances<TC>(tile, np, qrow, qvalid, N, acc);
-    if (!qvalid) continue;
+  for (int64_t t0 = c0; t0 < c1; t0 += kEvalTile) {
+    double acc[kEvalTile];
 #pragma unroll
-    for (int c = 0; c < TC; ++c) {
+    for (int c = 0; c < kEvalTile; ++c) acc[c] = 0.0;
+    for (int n0 = 0; n0 < N; n0 += DC) {
+      __syncthreads();
+      // stage the chunk (rows past c1 and dimensions past N are zero: they add nothing)
+      for (int e = lane; e < kEvalTile * DC; e += kEvalLanes) {
+        const int c = e / DC, d = e - c * DC;
+        const int64_t row = t0 + c;
+        tile[e] = (row < c1 && n0 + d < N) ? (double)Z[row * N + n0 + d] : 0.0;
+      }
+      float qv[DC];
+#pragma unroll
+      for (int d = 0; d < DC; ++d) qv[d] = (qvalid && n0 + d < N) ? qrow[n0 + d] : 0.f;
+      __syncthreads();
+#pragma unroll 4
+      for (int d = 0; d < DC; ++d) {
+        const double qd = (double)qv[d];
+#pragma unroll
+        for (int c = 0; c < kEvalTile; ++c) {
+          const double t = tile[c * DC + d] - qd;
+          acc[c] = __dadd_rn(acc[c], __dmul_rn(t, t));
+        }
+      }
+    }
+    if (!qvalid) continue;
+    double *mydist = dist + lane * kEvalTile;
+#pragma unroll
+    for (int c = 0; c < kEvalTile; ++c) mydist[c] = acc[c];
+    for (int c = 0; c < kEvalTile; ++c) {
       const int64_t l = t0 + c;
       if (l >= c1) break;
-      const double d = acc[c];
+      const double d = mydist[c];
       if (MODE == 0) {
         if (pair_before(d, (int32_t)l, myd[kl - 1], myi[kl - 1])) {
           int p = kl - 1;
@@ -219,31 +210,27 @@ int eval_chunks(int64_t Q, int64_t M) {
   return (int)S;
 }
 
+template <int MODE, int DC>
+hipError_t launch_scan_dc(const float *Z, int64_t M, int N, const int32_t *rows, int64_t Q, int kl, int S,
+                          const int32_t *cand, double *part_d, int32_t *part_i, int32_t *rank_out, hipStream_t s) {
+  const int64_t chunk = (M + S - 1) / S;
+  const dim3 grid((unsigned)((Q + kEvalLanes - 1) / kEvalLanes), (unsigned)S);
+  const size_t bytes = (size_t)kEvalTile * DC * 8 + (size_t)kEvalLanes * kEvalTile * 8 +
+                       (size_t)kEvalLanes * kl * (MODE == 0 ? 12 : 16);
+  hipError_t e = hipFuncSetAttribute((const void *)eval_scan_kernel<MODE, DC>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  eval_scan_kernel<MODE, DC><<<grid, kEvalLanes, bytes, s>>>(Z, M, N, rows, Q, kl, chunk, cand, part_d, part_i,
+                                                             rank_out);
+  return hipGetLastError();
+}
+
 template <int MODE>
 hipError_t launch_scan(const float *Z, int64_t M, int N, const int32_t *rows, int64_t Q, int kl, int S,
                        const int32_t *cand, double *part_d, int32_t *part_i, int32_t *rank_out, hipStream_t s) {
-  const int np = (N + kEvalDimChunk - 1) / kEvalDimChunk * kEvalDimChunk;
-  const int64_t chunk = (M + S - 1) / S;
-  const dim3 grid((unsigned)((Q + kEvalLanes - 1) / kEvalLanes), (unsigned)S);
-  const size_t lists = (size_t)kEvalLanes * kl * (MODE == 0 ? 12 : 16);
-  if (np <= 128) {
-    constexpr int TC = 16;
-    const size_t bytes = (size_t)TC * np * 8 + lists;
-    hipError_t e = hipFuncSetAttribute((const void *)eval_scan_kernel<MODE, TC>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    eval_scan_kernel<MODE, TC><<<grid, kEvalLanes, bytes, s>>>(Z, M, N, np, rows, Q, kl, chunk, cand, part_d,
-                                                               part_i, rank_out);
-  } else {
-    constexpr int TC = 4;
-    const size_t bytes = (size_t)TC * np * 8 + lists;
-    hipError_t e = hipFuncSetAttribute((const void *)eval_scan_kernel<MODE, TC>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    eval_scan_kernel<MODE, TC><<<grid, kEvalLanes, bytes, s>>>(Z, M, N, np, rows, Q, kl, chunk, cand, part_d,
-                                                               part_i, rank_out);
-  }
-  return hipGetLastError();
+  if (N <= 2) return launch_scan_dc<MODE, 2>(Z, M, N, rows, Q, kl, S, cand, part_d, part_i, rank_out, s);
+  if (N <= 8) return launch_scan_dc<MODE, 8>(Z, M, N, rows, Q, kl, S, cand, part_d, part_i, rank_out, s);
+  return launch_scan_dc<MODE, kEvalDimChunk>(Z, M, N, rows, Q, kl, S, cand, part_d, part_i, rank_out, s);
 }
 
 int eval_max_k() { return 128; }
