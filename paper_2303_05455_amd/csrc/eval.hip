@@ -36,13 +36,14 @@ __device__ __forceinline__ bool pair_before(double a, int32_t ia, double b, int3
 }
 
 // MODE 0: neighbour lists; MODE 1: rank counts.  Candidates go in tiles of
-// kEvalTile; each tile's coordinates are staged in LDS as FP64 one chunk of
-// kEvalDimChunk dimensions at a time (read by all lanes at once) while each
-// lane's own row chunk sits in registers, and every lane keeps the tile's
-// kEvalTile running distances in registers, adding dimensions in order.
-// Dynamic LDS: the chunk [kEvalTile][kEvalDimChunk] doubles, each lane's
-// kEvalTile finished distances, then per lane either the list (kl doubles
-// and kl ints) or the thresholds and counts (kl doubles, kl ints, kl ints).
+// kEvalTile; each tile's coordinates are staged in LDS as FP64, DC
+// dimensions at a time (read by all lanes at once), while each lane's own
+// row chunk sits in registers; every lane keeps the tile's kEvalTile running
+// distances in registers, adding dimensions in order, then parks them in
+// LDS for the per-candidate pass (list insertion or rank counting).
+// Dynamic LDS: the chunk [kEvalTile][DC] doubles, each lane's kEvalTile
+// finished distances, then per lane either the list (kl doubles and kl
+// ints) or the thresholds and counts (kl doubles, kl ints, kl ints).
 template <int MODE, int DC>
 __global__ void __launch_bounds__(kEvalLanes)
 eval_scan_kernel(const float *__restrict__ Z, int64_t M, int N, const int32_t *__restrict__ rows, int64_t Q, int kl,
@@ -50,7 +51,7 @@ eval_scan_kernel(const float *__restrict__ Z, int64_t M, int N, const int32_t *_
                  int32_t *__restrict__ part_i, int32_t *__restrict__ rank_out) {
   extern __shared__ __attribute__((aligned(16))) unsigned char eval_lds[];
   double *tile = (double *)eval_lds;                        // [kEvalTile][DC]
-  double *dist = tile + kEvalTile * DC;          // [64][kEvalTile]: each lane's tile distances
+  double *dist = tile + kEvalTile * DC;                     // [64][kEvalTile]: each lane's tile distances
   double *ld = dist + kEvalLanes * kEvalTile;               // [64][kl]
   int32_t *li = (int32_t *)(ld + (size_t)kEvalLanes * kl);  // [64][kl]
   int32_t *lc = li + (size_t)kEvalLanes * kl;               // rank mode: [64][kl] counts
