@@ -42,6 +42,10 @@ def _norm_rel(x, ref):
     # more column tiles than row tiles
     (300, 200, 840, 0, 1, 0, 5), (999, 136, 512, 0, 1, 2, 1), (64, 8, 8, 0, 1, 0, 1),
     (130, 640, 4160, 0, 1, 0, 16), (200, 1000, 72, 0, 1, 1, 1), (136, 4104, 512, 0, 1, 2, 1),
+    # tall products like the training step's: ragged rows and columns, a K
+    # tail inside the last step, every epilogue, split-K
+    (33001, 520, 792, 0, 1, 0, 1), (33001, 520, 792, 0, 1, 1, 1), (33001, 520, 792, 0, 1, 2, 1),
+    (4096, 512, 4096, 0, 1, 0, 8), (65536, 512, 784, 0, 1, 1, 1),
 ])
 def test_gemm_matches_fp64_on_identical_bf16_operands(pkg, M, N, K, ta, tb, epi, splits):
     m, api, _, _ = pkg
