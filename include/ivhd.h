@@ -64,7 +64,8 @@ typedef enum ivhd_mode {
 #define IVHD_FLAG_REORDER 1   /* keep the vertices internally grouped by connected
                                  component of the nn graph (smallest id first), and
                                  inside a component by nn in-degree capped at 81
-                                 (17 below 500,000 vertices), ties by id (a
+                                 (17 below 500,000 vertices), then by first nn
+                                 neighbour (absent last), then by id (a
                                  locality and load-balance order; the
                                  results are the same up to floating-point summation
                                  order, and the caller always sees its own order)  */

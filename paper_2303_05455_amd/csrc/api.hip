@@ -311,7 +311,7 @@ int build_order(ivhd_ctx *c) {
   int32_t *indeg = c->sc.cnt;           // [M+1] scratch until the nn lists are transposed
   HIPCHK(launch_fill_i32(indeg, M + 1, 0, s));
   HIPCHK(launch_count(c->nn_user, M, c->p.nn, indeg, s));
-  int rc = sort_vertex_order(parent, indeg, M, c->heavy_deg, c->perm, s);
+  int rc = sort_vertex_order(parent, indeg, c->nn_user, c->p.nn, M, c->heavy_deg, c->perm, s);
   if (rc) return rc;
   HIPCHK(launch_inverse_perm(c->perm, M, c->inv, s));
   HIPCHK(launch_map_lists(c->nn_user, M, c->p.nn, c->perm, c->inv, c->nn_own, s));

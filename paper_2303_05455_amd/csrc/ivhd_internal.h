@@ -117,10 +117,11 @@ hipError_t launch_scatter_sort(const int32_t *idx, int64_t M, int k, const int32
                                int32_t *src_out, hipStream_t s);
 
 // ---- order.hip ----
-// perm = the ids 0..M-1 sorted by (root[i], min(indeg[i], heavy_deg + 1), i);
+// perm = the ids 0..M-1 sorted by (root[i], min(indeg[i], heavy_deg + 1),
+// first nn neighbour of i (absent last), i); nn_idx is [M, nn] with nn >= 1;
 // synchronises s
-int sort_vertex_order(const int32_t *root, const int32_t *indeg, int64_t M, int heavy_deg, int32_t *perm,
-                      hipStream_t s);
+int sort_vertex_order(const int32_t *root, const int32_t *indeg, const int32_t *nn_idx, int nn, int64_t M,
+                      int heavy_deg, int32_t *perm, hipStream_t s);
 
 // ---- step.hip ----
 // device state of the self-adaptive b

@@ -179,11 +179,14 @@ def test_in_edge_lists_are_the_exact_transpose(ivhd, M, nn, rn, seed, extra, reo
     if reorder:
         # vertices grouped by connected component (smallest id first), then by
         # nn in-degree capped one above the hub threshold (80 from 500,000
-        # vertices on, 16 below), then by id
+        # vertices on, 16 below), then by first nn neighbour (absent last),
+        # then by id
         comp = _components(nn_idx, M)
         indeg = np.bincount(nn_idx[nn_idx >= 0].ravel(), minlength=M)
         cap = 81 if M >= 500_000 else 17
-        assert np.array_equal(perm, np.lexsort((np.arange(M), np.minimum(indeg, cap), comp)))
+        first = np.where(nn_idx[:, 0] >= 0, nn_idx[:, 0].astype(np.int64), 2**32 - 1)
+        want = np.lexsort((np.arange(M), first, np.minimum(indeg, cap), comp))
+        assert np.array_equal(perm, want)
     else:
         assert np.array_equal(perm, np.arange(M))
     inv = np.empty(M, np.int64)
