@@ -214,16 +214,24 @@ int ivhd_destroy(ivhd_ctx *ctx);
  * An edge plan holds the transposed lists of caller-given nn and rn edge
  * lists so that the stress E(Y) of Eq. ivhd_cost_function and its gradient
  * can be evaluated for many layouts Y (a loss for gradient-based training).
- * The plan keeps the caller's index pointers: they must stay valid and
- * unchanged while the plan lives. */
+ * Without IVHD_EDGES_REORDER the plan keeps the caller's index pointers:
+ * they must then stay valid and unchanged while the plan lives. */
 typedef struct ivhd_edges ivhd_edges;   /* opaque */
 
 /* ivhd_edges_create: d_nn_idx int32 [M][nn], d_rn_idx int32 [M][rn] (-1 =
  * absent slot in either), rn may be 0 (d_rn_idx ignored).
- * Entries equal to their own row are rejected (IVHD_EINVAL).  Synchronises
- * the stream.                                                              */
+ * Entries equal to their own row are rejected (IVHD_EINVAL).  flags: 0 or
+ * IVHD_EDGES_REORDER, which makes the plan keep its own copy of the lists in
+ * the internal vertex order of IVHD_FLAG_REORDER; every stress and gradient
+ * call then gathers Y into that order first (one extra pass over Y, paid
+ * back by the locality of the edge gathers on large graphs; results equal
+ * up to floating-point summation order, inputs and outputs in the caller's
+ * order).  Building the order costs a few milliseconds at a million
+ * vertices.  Other bits: IVHD_EINVAL.  Synchronises the stream; the plan's
+ * later calls run on this stream.                                          */
+#define IVHD_EDGES_REORDER 1
 int ivhd_edges_create(ivhd_edges **out, int64_t M, const int32_t *d_nn_idx, int32_t nn,
-                      const int32_t *d_rn_idx, int32_t rn, void *stream);
+                      const int32_t *d_rn_idx, int32_t rn, int32_t flags, void *stream);
 
 /* ivhd_edges_stress: *d_E (device double) = E(Y) accumulated in FP64 from the
  * FP32 layout d_y [M][2], fixed-order reduction.  Asynchronous.             */

@@ -49,7 +49,7 @@ SIGNATURES = {
     "ivhd_ivf_train": (i32, [vp, i64, i32, i32, i32, vp, vp, vp]),
     "ivhd_ivf_search": (i32, [vp, i64, i32, vp, i32, vp, vp, i64, vp, i32, i32, vp, vp, vp]),
     "ivhd_destroy": (i32, [vp]),
-    "ivhd_edges_create": (i32, [ctypes.POINTER(vp), i64, vp, i32, vp, i32, vp]),
+    "ivhd_edges_create": (i32, [ctypes.POINTER(vp), i64, vp, i32, vp, i32, i32, vp]),
     "ivhd_edges_stress": (i32, [vp, vp, f32, vp]),
     "ivhd_edges_grad": (i32, [vp, vp, f32, f32, vp, vp]),
     "ivhd_edges_destroy": (i32, [vp]),

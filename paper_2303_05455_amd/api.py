@@ -170,8 +170,11 @@ def ivhd_rnn_mask(nn_idx: torch.Tensor, helper: torch.Tensor, out: Optional[torc
     return out
 
 
+EDGES_REORDER = 1
+
+
 def ivhd_edges_create(nn_idx: torch.Tensor, rn_idx: Optional[torch.Tensor] = None,
-                      stream: Optional[torch.cuda.Stream] = None) -> ctypes.c_void_p:
+                      stream: Optional[torch.cuda.Stream] = None, *, reorder: bool = False) -> ctypes.c_void_p:
     M, nn = nn_idx.shape
     p_nn = _dev(nn_idx, torch.int32, (M, nn), "nn_idx")
     rn, p_rn = 0, None
@@ -179,7 +182,8 @@ def ivhd_edges_create(nn_idx: torch.Tensor, rn_idx: Optional[torch.Tensor] = Non
         rn = rn_idx.shape[1]
         p_rn = _dev(rn_idx, torch.int32, (M, rn), "rn_idx")
     h = ctypes.c_void_p()
-    check(_lib.load().ivhd_edges_create(ctypes.byref(h), M, p_nn, nn, p_rn, rn, _stream_handle(stream)))
+    check(_lib.load().ivhd_edges_create(ctypes.byref(h), M, p_nn, nn, p_rn, rn,
+                                        EDGES_REORDER if reorder else 0, _stream_handle(stream)))
     return h
 
 

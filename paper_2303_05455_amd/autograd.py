@@ -23,17 +23,23 @@ class StressEdges:
     a call from another stream is ordered after that stream's queued work and
     the caller's stream waits for the result, and the tensors it touches are
     marked as used on the plan's stream (so the caching allocator does not
-    hand their memory out early)."""
+    hand their memory out early).
+
+    reorder=True (the default) lets the plan work in the vertex order of the
+    loop's contexts (components, then in-degree): each call gathers Y into
+    that order first, and the edge gathers then stay within a component's
+    stretch of positions.  Inputs and outputs stay in the caller's order; the
+    results equal the unordered plan's up to floating-point summation order."""
 
     def __init__(self, nn_idx: torch.Tensor, rn_idx: Optional[torch.Tensor] = None, *,
-                 c: float = 0.1, eps: float = 1e-12):
+                 c: float = 0.1, eps: float = 1e-12, reorder: bool = True):
         self.nn_idx = nn_idx.contiguous()
         self.rn_idx = None if rn_idx is None else rn_idx.contiguous()
         self.M = nn_idx.shape[0]
         self.c, self.eps = float(c), float(eps)
         self._h = None
         self.stream = torch.cuda.current_stream(nn_idx.device)
-        self._h = api.ivhd_edges_create(self.nn_idx, self.rn_idx, stream=self.stream)
+        self._h = api.ivhd_edges_create(self.nn_idx, self.rn_idx, stream=self.stream, reorder=reorder)
         self._E = torch.zeros((), dtype=torch.float64, device=nn_idx.device)
 
     def _run(self, fn, *tensors):

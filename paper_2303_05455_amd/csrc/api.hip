@@ -52,7 +52,6 @@ std::mutex g_live_mu;
 std::unordered_set<const ivhd_ctx *> g_live;
 
 constexpr int kChunkIters = 64;   // graph length when random neighbours are drawn once
-constexpr int kCcMaxRounds = 64;  // bound on the component rounds (pointer jumping converges long before)
 
 }  // namespace
 
@@ -295,25 +294,11 @@ int capture(ivhd_ctx *c, bool with_draw, int64_t count, int par, hipGraphExec_t 
 int build_order(ivhd_ctx *c) {
   const int64_t M = c->p.M;
   hipStream_t s = c->stream;
-  int32_t *parent = c->nn_own;          // [M*nn] >= M ints, free until the lists are mapped
-  int32_t *changed = c->flags + 3;
-  HIPCHK(launch_cc_init(parent, M, s));
-  int rounds = 0;
-  for (;;) {
-    int32_t h = 0;
-    HIPCHK(launch_fill_i32(changed, 1, 0, s));
-    HIPCHK(launch_cc_round(c->nn_user, M, c->p.nn, parent, changed, s));
-    HIPCHK(hipMemcpyAsync(&h, changed, sizeof h, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (!h) break;
-    if (++rounds >= kCcMaxRounds) return fail(IVHD_EDEVICE, "connected components did not converge");
-  }
-  int32_t *indeg = c->sc.cnt;           // [M+1] scratch until the nn lists are transposed
-  HIPCHK(launch_fill_i32(indeg, M + 1, 0, s));
-  HIPCHK(launch_count(c->nn_user, M, c->p.nn, indeg, s));
-  int rc = sort_vertex_order(parent, indeg, c->nn_user, c->p.nn, M, c->heavy_deg, c->perm, s);
+  // parent: nn_own ([M*nn] >= M ints) is free until the lists are mapped;
+  // indeg: the CSC counts are free until the nn lists are transposed
+  int rc = build_vertex_order(c->nn_user, M, c->p.nn, c->heavy_deg, c->nn_own, c->sc.cnt, c->flags + 3, c->perm,
+                              c->inv, s);
   if (rc) return rc;
-  HIPCHK(launch_inverse_perm(c->perm, M, c->inv, s));
   HIPCHK(launch_map_lists(c->nn_user, M, c->p.nn, c->perm, c->inv, c->nn_own, s));
   return IVHD_OK;
 }

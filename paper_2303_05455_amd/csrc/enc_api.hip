@@ -397,7 +397,7 @@ int ivhd_enc_train_epoch(ivhd_enc *e, const uint16_t *d_x16, int64_t M, const in
     if (rn > 0 && (rc = dev_alloc(&e->lrn, R * rn, "batch rn lists"))) return rc;
     if ((rc = dev_alloc(&e->rows, R, "batch rows"))) return rc;
     HIPCHK(launch_batch_plan(batch, nn, rn, e->lnn, e->lrn, s));
-    if ((rc = ivhd_edges_create(&e->plan, R, e->lnn, nn, e->lrn, rn, s))) return rc;
+    if ((rc = ivhd_edges_create(&e->plan, R, e->lnn, nn, e->lrn, rn, 0, s))) return rc;
     e->plan_B = batch;
     e->plan_nn = nn;
     e->plan_rn = rn;

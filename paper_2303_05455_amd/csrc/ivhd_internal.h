@@ -122,6 +122,13 @@ hipError_t launch_scatter_sort(const int32_t *idx, int64_t M, int k, const int32
 // synchronises s
 int sort_vertex_order(const int32_t *root, const int32_t *indeg, const int32_t *nn_idx, int nn, int64_t M,
                       int heavy_deg, int32_t *perm, hipStream_t s);
+// the whole order: components of the undirected nn graph (at most
+// kCcMaxRounds rounds), in-degrees, the sort above, and inv = perm^-1.
+// parent [M] and indeg [M+1] are scratch, changed one device int;
+// synchronises s
+constexpr int kCcMaxRounds = 64;   // pointer jumping converges long before
+int build_vertex_order(const int32_t *nn_idx, int64_t M, int nn, int heavy_deg, int32_t *parent, int32_t *indeg,
+                       int32_t *changed, int32_t *perm, int32_t *inv, hipStream_t s);
 
 // ---- step.hip ----
 // device state of the self-adaptive b
@@ -162,6 +169,7 @@ struct StepArgs {
   float2 *fown;           // atomic mode: each vertex's own share of its force [M]
   int32_t *flags;
   const float *gscale;    // gradient kernels: output scaled by *gscale (NULL = 1)
+  const int32_t *out_perm;   // gradient kernels: vertex i's output goes to out[out_perm[i]] (NULL: out[i])
   const int32_t *heavy;   // vertices whose nn in-degree exceeds heavy_deg
   int32_t n_heavy;
   int32_t heavy_deg;      // nn in-degree above which a vertex gets a whole wavefront

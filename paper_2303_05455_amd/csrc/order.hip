@@ -97,4 +97,24 @@ int sort_vertex_order(const int32_t *root, const int32_t *indeg, const int32_t *
   return IVHD_OK;
 }
 
+int build_vertex_order(const int32_t *nn_idx, int64_t M, int nn, int heavy_deg, int32_t *parent, int32_t *indeg,
+                       int32_t *changed, int32_t *perm, int32_t *inv, hipStream_t s) {
+  HIPCHK(launch_cc_init(parent, M, s));
+  for (int rounds = 0;; ++rounds) {
+    if (rounds >= kCcMaxRounds) return fail(IVHD_EDEVICE, "connected components did not converge");
+    int32_t h = 0;
+    HIPCHK(launch_fill_i32(changed, 1, 0, s));
+    HIPCHK(launch_cc_round(nn_idx, M, nn, parent, changed, s));
+    HIPCHK(hipMemcpyAsync(&h, changed, sizeof h, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (!h) break;
+  }
+  HIPCHK(launch_fill_i32(indeg, M + 1, 0, s));
+  HIPCHK(launch_count(nn_idx, M, nn, indeg, s));
+  const int rc = sort_vertex_order(parent, indeg, nn_idx, nn, M, heavy_deg, perm, s);
+  if (rc) return rc;
+  HIPCHK(launch_inverse_perm(perm, M, inv, s));
+  return IVHD_OK;
+}
+
 }  // namespace ivhd

@@ -58,6 +58,10 @@ struct ivhd_edges {
   int32_t *flags = nullptr;
   double *partials = nullptr;
   int nparts = 0;
+  // IVHD_EDGES_REORDER: internal vertex order (NULL: the caller's)
+  int32_t *perm = nullptr, *inv = nullptr;   // internal p -> caller id, and back
+  int32_t *nn_own = nullptr, *rn_own = nullptr;   // the lists in internal ids and order
+  float2 *yp = nullptr;                      // the layout gathered into the internal order
 };
 
 namespace {
@@ -72,8 +76,9 @@ bool edges_live(const ivhd_edges *e) {
 
 void free_edges(ivhd_edges *e) {
   if (!e) return;
-  void *bufs[] = {e->nn_csc.ptr, e->nn_csc.src, e->rn_csc.ptr, e->rn_csc.src, e->sc.cnt,
-                  e->sc.tmp, e->sc.part, e->sc.big, e->heavy, e->flags, e->partials};
+  void *bufs[] = {e->nn_csc.ptr, e->nn_csc.src, e->rn_csc.ptr, e->rn_csc.src, e->sc.cnt, e->sc.tmp,
+                  e->sc.part, e->sc.big, e->heavy, e->flags, e->partials, e->perm, e->inv,
+                  e->nn_own, e->rn_own, e->yp};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   delete e;
@@ -91,6 +96,7 @@ StepArgs edge_args(const ivhd_edges *e, const float2 *y, float c, float eps, con
   a.rn_src = e->rn_csc.src;
   a.flags = e->flags;
   a.gscale = gscale;
+  a.out_perm = e->perm;
   a.heavy = e->heavy;
   a.n_heavy = e->n_heavy;
   a.heavy_deg = e->heavy_deg;
@@ -105,10 +111,11 @@ StepArgs edge_args(const ivhd_edges *e, const float2 *y, float c, float eps, con
 }  // namespace
 
 int ivhd_edges_create(ivhd_edges **out, int64_t M, const int32_t *d_nn_idx, int32_t nn,
-                      const int32_t *d_rn_idx, int32_t rn, void *stream) {
+                      const int32_t *d_rn_idx, int32_t rn, int32_t flags, void *stream) {
   clear_error();
   if (!out) return fail(IVHD_EINVAL, "out is NULL");
   *out = nullptr;
+  if (flags & ~IVHD_EDGES_REORDER) return fail(IVHD_EINVAL, "unknown flags 0x%x", (unsigned)flags);
   if (M < 2 || M > (int64_t)INT32_MAX - 1) return fail(IVHD_EINVAL, "M = %lld outside [2, 2^31-2]", (long long)M);
   if (nn < 1 || nn > 64) return fail(IVHD_EINVAL, "nn = %d outside [1, 64]", nn);
   if (rn < 0 || rn > 64) return fail(IVHD_EINVAL, "rn = %d outside [0, 64]", rn);
@@ -168,9 +175,23 @@ int ivhd_edges_create(ivhd_edges **out, int64_t M, const int32_t *d_nn_idx, int3
     free_edges(e);
     return fail(IVHD_EINVAL, "an nn or rn entry is outside [-1, M) or equals its row");
   }
-  E_CHK(build_csc(d_nn_idx, M, nn, e->nn_csc, e->sc, e->flags, s));
-  if (rn > 0) E_CHK(build_csc(d_rn_idx, M, rn, e->rn_csc, e->sc, e->flags, s));
   e->heavy_deg = heavy_degree(M);
+  if (flags & IVHD_EDGES_REORDER) {
+    E_CHK(dev_alloc(&e->perm, M, "vertex order"));
+    E_CHK(dev_alloc(&e->inv, M, "inverse vertex order"));
+    E_CHK(dev_alloc(&e->nn_own, M * nn, "nn lists in internal order"));
+    if (rn > 0) E_CHK(dev_alloc(&e->rn_own, M * rn, "rn lists in internal order"));
+    E_CHK(dev_alloc(&e->yp, M, "layout in internal order"));
+    // nn_own ([M*nn] >= M ints) is the component scratch until the lists are mapped
+    E_CHK(build_vertex_order(d_nn_idx, M, nn, e->heavy_deg, e->nn_own, e->sc.cnt, e->flags + 3, e->perm, e->inv,
+                             s));
+    E_HIP(launch_map_lists(d_nn_idx, M, nn, e->perm, e->inv, e->nn_own, s));
+    if (rn > 0) E_HIP(launch_map_lists(d_rn_idx, M, rn, e->perm, e->inv, e->rn_own, s));
+    e->nn_idx = e->nn_own;
+    e->rn_idx = e->rn_own;
+  }
+  E_CHK(build_csc(e->nn_idx, M, nn, e->nn_csc, e->sc, e->flags, s));
+  if (rn > 0) E_CHK(build_csc(e->rn_idx, M, rn, e->rn_csc, e->sc, e->flags, s));
   E_CHK(build_heavy(e->nn_csc, M, e->heavy_deg, e->heavy, e->flags, &e->n_heavy, s));
 #undef E_CHK
 #undef E_HIP
@@ -186,8 +207,13 @@ int ivhd_edges_stress(ivhd_edges *e, const float *d_y, float c, double *d_E) {
   if (!edges_live(e)) return fail(IVHD_ESTATE, "invalid edge plan");
   if (!d_y || !d_E) return fail(IVHD_EINVAL, "d_y and d_E must not be NULL");
   if (!std::isfinite(c) || c < 0.f) return fail(IVHD_EINVAL, "c = %g must be finite and >= 0", (double)c);
-  HIPCHK(launch_stress((const float2 *)d_y, e->M, e->nn_idx, e->nn, e->rn_idx, e->rn, (double)c, 0,
-                       e->partials, e->nparts, d_E, e->stream));
+  const float2 *y = (const float2 *)d_y;
+  if (e->perm) {
+    HIPCHK(launch_gather_f2(y, e->perm, e->M, e->yp, e->stream));
+    y = e->yp;
+  }
+  HIPCHK(launch_stress(y, e->M, e->nn_idx, e->nn, e->rn_idx, e->rn, (double)c, 0, e->partials, e->nparts, d_E,
+                       e->stream));
   return IVHD_OK;
 }
 
@@ -198,7 +224,12 @@ int ivhd_edges_grad(ivhd_edges *e, const float *d_y, float c, float eps, const f
   if (d_y == d_grad) return fail(IVHD_EINVAL, "d_y and d_grad alias");
   if (!std::isfinite(c) || c < 0.f) return fail(IVHD_EINVAL, "c = %g must be finite and >= 0", (double)c);
   if (!std::isfinite(eps) || eps < 0.f) return fail(IVHD_EINVAL, "eps = %g must be >= 0", (double)eps);
-  HIPCHK(launch_grad_det(edge_args(e, (const float2 *)d_y, c, eps, d_scale), (float2 *)d_grad, e->stream));
+  const float2 *y = (const float2 *)d_y;
+  if (e->perm) {
+    HIPCHK(launch_gather_f2(y, e->perm, e->M, e->yp, e->stream));
+    y = e->yp;
+  }
+  HIPCHK(launch_grad_det(edge_args(e, y, c, eps, d_scale), (float2 *)d_grad, e->stream));
   return IVHD_OK;
 }
 
@@ -218,7 +249,7 @@ int ivhd_grad_edges(const float *d_y, int64_t M, const int32_t *d_nn_idx, int32_
                     const int32_t *d_rn_idx, int32_t rn, float c, float eps, float *d_grad,
                     double *h_E, void *stream) {
   ivhd_edges *e = nullptr;
-  int rc = ivhd_edges_create(&e, M, d_nn_idx, nn, d_rn_idx, rn, stream);
+  int rc = ivhd_edges_create(&e, M, d_nn_idx, nn, d_rn_idx, rn, 0, stream);
   if (rc) return rc;
   rc = ivhd_edges_grad(e, d_y, c, eps, nullptr, d_grad);
   if (!rc && h_E) {

@@ -267,8 +267,8 @@ __device__ __forceinline__ void block_sum_store(double x, double *out) {
 }
 
 // GRAD = true: out = s grad E = -2 s f with s = *gscale (1 when NULL), at
-// A.h = A.y; otherwise one iteration (force + update).  No thread leaves
-// before the ADAPT block sum.
+// A.h = A.y, stored through A.out_perm when set; otherwise one iteration
+// (force + update).  No thread leaves before the ADAPT block sum.
 // ARN = true is pass 1 of the atomic mode: each vertex's own share (its nn
 // edges both ways and its rn out-edges) goes to A.fown, the rn reactions to
 // A.fbuf by atomics; no update.
@@ -287,7 +287,7 @@ __global__ void __launch_bounds__(kDetBlock) det_kernel(StepArgs A, float2 *out)
           A.fown[i] = f;
         } else if (GRAD) {
           const float g = -2.f * (A.gscale ? *A.gscale : 1.f);
-          out[i] = make_float2(g * f.x, g * f.y);
+          out[A.out_perm ? A.out_perm[i] : i] = make_float2(g * f.x, g * f.y);
         } else {
           ke = apply_update<OPT>(A, i, hi, f);
         }
@@ -309,7 +309,7 @@ __global__ void __launch_bounds__(kDetBlock) det_kernel(StepArgs A, float2 *out)
           A.fown[i] = f;
         } else if (GRAD) {
           const float g = -2.f * (A.gscale ? *A.gscale : 1.f);
-          out[i] = make_float2(g * f.x, g * f.y);
+          out[A.out_perm ? A.out_perm[i] : i] = make_float2(g * f.x, g * f.y);
         } else {
           ke = apply_update<OPT>(A, i, hi, f);
         }
@@ -338,14 +338,15 @@ __global__ void __launch_bounds__(kBlock) atomic_update_kernel(StepArgs A) {
 }
 
 __global__ void __launch_bounds__(kBlock) atomic_grad_out_kernel(const float2 *fown, float2 *fbuf, int64_t M,
-                                                                const float *gscale, float2 *out) {
+                                                                const float *gscale, const int32_t *out_perm,
+                                                                float2 *out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M) return;
   const float2 fo = fown[i], fr = fbuf[i];
   const float2 f = make_float2(fo.x + fr.x, fo.y + fr.y);
   fbuf[i] = make_float2(0.f, 0.f);
   const float g = -2.f * (gscale ? *gscale : 1.f);
-  out[i] = make_float2(g * f.x, g * f.y);
+  out[out_perm ? out_perm[i] : i] = make_float2(g * f.x, g * f.y);
 }
 
 __global__ void adam_prep_kernel(AdamState *st, float beta1, float beta2) {
@@ -474,7 +475,7 @@ hipError_t launch_grad_det(const StepArgs &a, float2 *out, hipStream_t s) {
 hipError_t launch_grad_atomic(const StepArgs &a, float2 *out, hipStream_t s) {
   if (a.l1) det_kernel<false, true, OPT_PLAIN, true><<<det_grid(a), kDetBlock, 0, s>>>(a, nullptr);
   else det_kernel<false, false, OPT_PLAIN, true><<<det_grid(a), kDetBlock, 0, s>>>(a, nullptr);
-  atomic_grad_out_kernel<<<grid_for(a.M), kBlock, 0, s>>>(a.fown, a.fbuf, a.M, a.gscale, out);
+  atomic_grad_out_kernel<<<grid_for(a.M), kBlock, 0, s>>>(a.fown, a.fbuf, a.M, a.gscale, a.out_perm, out);
   return hipGetLastError();
 }
 

@@ -183,3 +183,14 @@ def test_probe_gather_rejects_bad_sizes(lib):
     assert lib.ivhd_probe_gather(FAKE, 10, FAKE, -1, FAKE, None) == -1
     assert lib.ivhd_probe_gather(None, 10, FAKE, 5, FAKE, None) == -1
     assert lib.ivhd_probe_gather(None, 10, None, 0, None, None) == 0
+
+
+def test_edges_create_rejects_unknown_flags_and_bad_sizes(lib):
+    h = ctypes.c_void_p()
+    assert lib.ivhd_edges_create(ctypes.byref(h), 100, FAKE, 2, FAKE, 1, 2, None) == -1
+    assert "unknown flags" in lib.ivhd_last_error().decode()
+    assert not h.value
+    assert lib.ivhd_edges_create(ctypes.byref(h), 1, FAKE, 2, FAKE, 1, 1, None) == -1
+    assert lib.ivhd_edges_create(ctypes.byref(h), 100, FAKE, 0, FAKE, 1, 1, None) == -1
+    assert lib.ivhd_edges_create(ctypes.byref(h), 100, None, 2, FAKE, 1, 1, None) == -1
+    assert lib.ivhd_edges_create(None, 100, FAKE, 2, FAKE, 1, 0, None) == -1

@@ -40,12 +40,13 @@ def _case(M, nn, rn, seed, hub=0.0, absent=0.0):
     (1000, 3, 1, 0, 0.0, 0.0), (4001, 5, 1, 1, 0.8, 0.1), (777, 2, 0, 2, 0.0, 0.0),
     (2500, 1, 3, 3, 1.0, 0.0),
 ])
-def test_plan_stress_and_gradient_match_oracle(m, M, nn, rn, seed, hub, absent):
+@pytest.mark.parametrize("reorder", [True, False])
+def test_plan_stress_and_gradient_match_oracle(m, M, nn, rn, seed, hub, absent, reorder):
     pkg, ag = m
     nn_idx, rn_idx, Y = _case(M, nn, rn, seed, hub, absent)
     c = f32(0.1)
     edges = ag.StressEdges(torch.from_numpy(nn_idx).cuda(),
-                           torch.from_numpy(rn_idx).cuda() if rn else None, c=c)
+                           torch.from_numpy(rn_idx).cuda() if rn else None, c=c, reorder=reorder)
     y = torch.from_numpy(Y).cuda()
     E = edges.stress64(y).item()
     assert E == pytest.approx(oracle.stress(Y, nn_idx, rn_idx, c), rel=1e-10)
@@ -89,8 +90,10 @@ def test_backward_matches_finite_differences_of_the_fp64_stress(m):
     assert max(errs) <= 1e-3
 
 
-def test_gradient_at_the_differentiable_stress_workload_size(m):
-    # 1M vertices, nn = 5, rn = 1 (edge lists drawn without a neighbour search)
+@pytest.mark.parametrize("reorder", [True, False])
+def test_gradient_at_the_differentiable_stress_workload_size(m, reorder):
+    # 1M vertices, nn = 5, rn = 1 (edge lists drawn without a neighbour search,
+    # inside 8 labels: 8 components, as the clusters give)
     pkg, ag = m
     cfg = synth.CONFIGS["C4"]
     rng = np.random.default_rng(40)
@@ -98,7 +101,8 @@ def test_gradient_at_the_differentiable_stress_workload_size(m):
     nn_idx = synth.random_neighbour_graph(cfg.M, cfg.nn, rng, labels=labels, hub_alpha=1.5)
     rn_idx = oracle.rn_sample(nn_idx, cfg.rn, 1, 0)
     Y = rng.random((cfg.M, 2)).astype(np.float32)
-    edges = ag.StressEdges(torch.from_numpy(nn_idx).cuda(), torch.from_numpy(rn_idx).cuda(), c=cfg.c)
+    edges = ag.StressEdges(torch.from_numpy(nn_idx).cuda(), torch.from_numpy(rn_idx).cuda(), c=cfg.c,
+                           reorder=reorder)
     y = torch.from_numpy(Y).cuda()
     assert edges.stress64(y).item() == pytest.approx(oracle.stress(Y, nn_idx, rn_idx, f32(cfg.c)), rel=1e-10)
     assert _rel(edges.grad(y).cpu().numpy(), oracle.grad(Y, nn_idx, rn_idx, f32(cfg.c), f32(1e-12))) <= 1e-5
@@ -161,3 +165,34 @@ def test_forward_and_backward_on_another_torch_stream(m):
     assert got_loss.item() == pytest.approx(3.0 * loss_ref.item(), rel=1e-6)
     assert torch.equal(got_grad, 3.0 * y_ref.grad)
     edges.close()
+
+
+def test_reordered_plan_keeps_its_own_lists_and_agrees_with_the_plain_plan(m):
+    # three label groups (so three or more components) with hubs and absent
+    # slots; after creation the reordered plan no longer reads the caller's
+    # lists, and both plans give the same stress and gradient up to summation
+    # order, in the caller's order, on two different layouts
+    pkg, ag = m
+    rng = np.random.default_rng(31)
+    M = 30011
+    labels = rng.integers(0, 3, M).astype(np.int32)
+    nn_idx = synth.random_neighbour_graph(M, 4, rng, labels=labels, hub_alpha=1.2, absent_frac=0.05)
+    rn_idx = oracle.rn_sample(nn_idx, 2, 9, 0)
+    c = f32(0.1)
+    nn_t, rn_t = torch.from_numpy(nn_idx).cuda(), torch.from_numpy(rn_idx).cuda()
+    plain = ag.StressEdges(nn_t.clone(), rn_t.clone(), c=c, reorder=False)
+    ordered = ag.StressEdges(nn_t, rn_t, c=c, reorder=True)
+    nn_t.fill_(-1)
+    rn_t.fill_(-1)
+    for s in (1.0, 3.0):
+        Y = (rng.normal(0, s, size=(M, 2))).astype(np.float32)
+        y = torch.from_numpy(Y).cuda()
+        E_ref = oracle.stress(Y, nn_idx, rn_idx, c)
+        assert ordered.stress64(y).item() == pytest.approx(E_ref, rel=1e-10)
+        assert ordered.stress64(y).item() == pytest.approx(plain.stress64(y).item(), rel=1e-12)
+        g_ref = oracle.grad(Y, nn_idx, rn_idx, c, f32(1e-12))
+        g_o, g_p = ordered.grad(y).cpu().numpy(), plain.grad(y).cpu().numpy()
+        assert _rel(g_o, g_ref) <= 1e-5
+        assert _rel(g_o, g_p.astype(np.float64)) <= 1e-6
+    ordered.close()
+    plain.close()
