@@ -244,6 +244,21 @@ int ivhd_edges_stress(ivhd_edges *e, const float *d_y, float c, double *d_E);
 int ivhd_edges_grad(ivhd_edges *e, const float *d_y, float c, float eps, const float *d_scale,
                     float *d_grad);
 
+/* ivhd_edges_stress_grad: both of the above from one pass over the edges:
+ * *d_E = E(Y) in FP64 (each out-edge's term as in ivhd_edges_stress, summed
+ * per block of the gradient kernel and then in a fixed order, so equal to
+ * ivhd_edges_stress up to summation order and bitwise reproducible) and
+ * d_grad = s * grad E(Y) exactly as ivhd_edges_grad.  Same arguments and
+ * errors as the two.  Asynchronous.                                         */
+int ivhd_edges_stress_grad(ivhd_edges *e, const float *d_y, float c, float eps, const float *d_scale,
+                           double *d_E, float *d_grad);
+
+/* ivhd_scale_f32: d_out[k] = *d_scale * d_x[k] for k < n (device pointers,
+ * d_out may equal d_x): the chain-rule step for a gradient taken before its
+ * upstream scale was known.  n = 0 does nothing; n < 0 or a NULL pointer:
+ * IVHD_EINVAL.  Asynchronous on `stream`.                                   */
+int ivhd_scale_f32(const float *d_x, int64_t n, const float *d_scale, float *d_out, void *stream);
+
 /* ivhd_edges_destroy: synchronises the plan's stream and frees it.         */
 int ivhd_edges_destroy(ivhd_edges *e);
 

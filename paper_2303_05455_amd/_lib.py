@@ -52,6 +52,8 @@ SIGNATURES = {
     "ivhd_edges_create": (i32, [ctypes.POINTER(vp), i64, vp, i32, vp, i32, i32, vp]),
     "ivhd_edges_stress": (i32, [vp, vp, f32, vp]),
     "ivhd_edges_grad": (i32, [vp, vp, f32, f32, vp, vp]),
+    "ivhd_edges_stress_grad": (i32, [vp, vp, f32, f32, vp, vp, vp]),
+    "ivhd_scale_f32": (i32, [vp, i64, vp, vp, vp]),
     "ivhd_edges_destroy": (i32, [vp]),
     "ivhd_grad_edges": (i32, [vp, i64, vp, i32, vp, i32, f32, f32, vp, ctypes.POINTER(f64), vp]),
     "ivhd_grad_edges_noalloc": (i32, [vp, i64, vp, i32, vp, i32, f32, f32, vp, ctypes.POINTER(f64), vp]),

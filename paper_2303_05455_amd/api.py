@@ -22,8 +22,8 @@ __all__ = [
     "ivhd_get_rn", "ivhd_get_in_edges", "ivhd_get_order", "ivhd_set_state", "ivhd_set_iteration",
     "ivhd_get_iteration", "ivhd_set_graphs", "ivhd_destroy", "ivhd_last_error",
     "ivhd_version", "ivhd_knn_build", "ivhd_knn_query", "ivhd_edges_create", "ivhd_edges_stress",
-    "ivhd_edges_grad", "ivhd_edges_destroy", "ivhd_grad_edges", "ivhd_grad_edges_noalloc",
-    "ivhd_set_adaptive",
+    "ivhd_edges_grad", "ivhd_edges_stress_grad", "ivhd_scale_f32", "ivhd_edges_destroy", "ivhd_grad_edges",
+    "ivhd_grad_edges_noalloc", "ivhd_set_adaptive",
     "ivhd_get_adaptive", "ivhd_rnn_mask", "ivhd_set_adam", "ivhd_ivf_train", "ivhd_ivf_search",
     "ivf_knn_graph", "ivhd_eval_neighbours", "ivhd_eval_ranks", "ivhd_eval_scores", "ivhd_probe_gather",
 ]
@@ -199,6 +199,25 @@ def ivhd_edges_grad(plan, y: torch.Tensor, c: float, eps: float, scale: Optional
     p_s = None if scale is None else _dev(scale, torch.float32, tuple(scale.shape), "scale")
     check(_lib.load().ivhd_edges_grad(plan, _dev(y, torch.float32, tuple(y.shape), "y"), float(c),
                                       float(eps), p_s, _dev(out, torch.float32, tuple(y.shape), "out")))
+    return out
+
+
+def ivhd_edges_stress_grad(plan, y: torch.Tensor, c: float, eps: float, scale: Optional[torch.Tensor],
+                           E_out: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+    p_s = None if scale is None else _dev(scale, torch.float32, tuple(scale.shape), "scale")
+    _dev(E_out, torch.float64, tuple(E_out.shape), "E_out")
+    check(_lib.load().ivhd_edges_stress_grad(plan, _dev(y, torch.float32, tuple(y.shape), "y"), float(c),
+                                             float(eps), p_s, E_out.data_ptr(),
+                                             _dev(out, torch.float32, tuple(y.shape), "out")))
+    return out
+
+
+def ivhd_scale_f32(x: torch.Tensor, scale: torch.Tensor, out: torch.Tensor,
+                   stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    n = x.numel()
+    check(_lib.load().ivhd_scale_f32(_dev(x, torch.float32, tuple(x.shape), "x"), n,
+                                     _dev(scale, torch.float32, tuple(scale.shape), "scale"),
+                                     _dev(out, torch.float32, tuple(x.shape), "out"), _stream_handle(stream)))
     return out
 
 

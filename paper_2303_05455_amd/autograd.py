@@ -3,8 +3,9 @@
 E(Y) = sum_i [ sum_{j in O_nn(i)} |y_i - y_j|^2 + c sum_{k in O_rn(i)} (1 - |y_i - y_k|)^2 ]
 (Eq. ivhd_cost_function).  Forward: FP64 accumulation on the GPU, returned as
 an FP32 scalar loss (the FP64 value stays available as ``.last_stress``).
-Backward: the hand-written gather kernel of libivhd, scaled on the device by
-the upstream gradient (no host synchronisation).
+Gradient: the hand-written gather kernel of libivhd, taken together with the
+stress in the forward when the layout requires a gradient, and scaled on the
+device by the upstream gradient in the backward (no host synchronisation).
 """
 from __future__ import annotations
 
@@ -73,6 +74,18 @@ class StressEdges:
             out = torch.empty_like(y)
         return self._run(lambda: api.ivhd_edges_grad(self.handle, y, self.c, self.eps, scale, out), y, scale, out)
 
+    def stress_grad(self, y: torch.Tensor, scale: Optional[torch.Tensor] = None,
+                    out: Optional[torch.Tensor] = None):
+        """(E(y) as a float64 device scalar, scale * grad E(y)) from one pass
+        over the edges (asynchronous)."""
+        y = y.contiguous()
+        E = torch.empty((), dtype=torch.float64, device=y.device)
+        if out is None:
+            out = torch.empty_like(y)
+        self._run(lambda: api.ivhd_edges_stress_grad(self.handle, y, self.c, self.eps, scale, E, out),
+                  y, scale, E, out)
+        return E, out
+
     def close(self):
         if self._h is not None:
             h, self._h = self._h, None
@@ -86,24 +99,35 @@ class StressEdges:
 
 
 class IVHDStress(torch.autograd.Function):
-    """loss = IVHDStress.apply(y, edges): y float32 [M, 2] on the GPU."""
+    """loss = IVHDStress.apply(y, edges): y float32 [M, 2] on the GPU.
+
+    When y requires a gradient, the forward takes the stress and its
+    gradient in one pass over the edges (``StressEdges.stress_grad``) and
+    keeps the gradient; the backward only scales it by the upstream
+    gradient.  Otherwise the forward takes the stress alone."""
 
     @staticmethod
     def forward(ctx, y: torch.Tensor, edges: StressEdges):
         if y.dtype != torch.float32 or y.dim() != 2 or y.shape[1] != 2:
             raise TypeError("y must be float32 [M, 2]")
         y = y.contiguous()
-        E64 = edges.stress64(y)
+        if ctx.needs_input_grad[0]:
+            E64, g = edges.stress_grad(y)
+            ctx.save_for_backward(g)
+        else:
+            E64 = edges.stress64(y)
         edges.last_stress = E64
         ctx.edges = edges
-        ctx.save_for_backward(y)
         return E64.to(torch.float32)
 
     @staticmethod
-    def backward(ctx, g: torch.Tensor):
-        (y,) = ctx.saved_tensors
-        scale = g.detach().to(torch.float32).reshape(1).contiguous()
-        return ctx.edges.grad(y, scale), None
+    def backward(ctx, g_out: torch.Tensor):
+        (g,) = ctx.saved_tensors
+        edges = ctx.edges
+        scale = g_out.detach().to(torch.float32).reshape(1).contiguous()
+        out = torch.empty_like(g)
+        edges._run(lambda: api.ivhd_scale_f32(g, scale, out, stream=edges.stream), g, scale, out)
+        return out, None
 
 
 def ivhd_stress_loss(y: torch.Tensor, edges: StressEdges) -> torch.Tensor:

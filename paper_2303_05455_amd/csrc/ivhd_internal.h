@@ -170,6 +170,7 @@ struct StepArgs {
   int32_t *flags;
   const float *gscale;    // gradient kernels: output scaled by *gscale (NULL = 1)
   const int32_t *out_perm;   // gradient kernels: vertex i's output goes to out[out_perm[i]] (NULL: out[i])
+  double *e_part;         // gradient kernels: FP64 stress of each block's out-edges [det_grid] (NULL: none)
   const int32_t *heavy;   // vertices whose nn in-degree exceeds heavy_deg
   int32_t n_heavy;
   int32_t heavy_deg;      // nn in-degree above which a vertex gets a whole wavefront
@@ -223,6 +224,10 @@ hipError_t launch_stress(const float2 *y, int64_t M, const int32_t *nn_idx, int 
                          const int32_t *rn_idx, int rn, double c, int metric, double *partials,
                          int nparts, double *out, hipStream_t s);
 int stress_partials(int64_t M);
+// *out = the fixed-order sum of partials[0..nparts) (one block)
+hipError_t launch_stress_final(const double *partials, int nparts, double *out, hipStream_t s);
+// out[k] = *scale * x[k], k < n
+hipError_t launch_scale_f32(const float *x, int64_t n, const float *scale, float *out, hipStream_t s);
 
 // ---- knn.hip ----
 int knn_max_k();

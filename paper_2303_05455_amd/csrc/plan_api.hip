@@ -62,6 +62,8 @@ struct ivhd_edges {
   int32_t *perm = nullptr, *inv = nullptr;   // internal p -> caller id, and back
   int32_t *nn_own = nullptr, *rn_own = nullptr;   // the lists in internal ids and order
   float2 *yp = nullptr;                      // the layout gathered into the internal order
+  double *gparts = nullptr;                  // per-block stress of the fused gradient kernel
+  int ngparts = 0;
 };
 
 namespace {
@@ -78,7 +80,7 @@ void free_edges(ivhd_edges *e) {
   if (!e) return;
   void *bufs[] = {e->nn_csc.ptr, e->nn_csc.src, e->rn_csc.ptr, e->rn_csc.src, e->sc.cnt, e->sc.tmp,
                   e->sc.part, e->sc.big, e->heavy, e->flags, e->partials, e->perm, e->inv,
-                  e->nn_own, e->rn_own, e->yp};
+                  e->nn_own, e->rn_own, e->yp, e->gparts};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   delete e;
@@ -193,6 +195,8 @@ int ivhd_edges_create(ivhd_edges **out, int64_t M, const int32_t *d_nn_idx, int3
   E_CHK(build_csc(e->nn_idx, M, nn, e->nn_csc, e->sc, e->flags, s));
   if (rn > 0) E_CHK(build_csc(e->rn_idx, M, rn, e->rn_csc, e->sc, e->flags, s));
   E_CHK(build_heavy(e->nn_csc, M, e->heavy_deg, e->heavy, e->flags, &e->n_heavy, s));
+  e->ngparts = (int)det_grid(edge_args(e, nullptr, 0.f, 0.f, nullptr));
+  E_CHK(dev_alloc(&e->gparts, e->ngparts, "fused stress partials"));
 #undef E_CHK
 #undef E_HIP
   {
@@ -230,6 +234,33 @@ int ivhd_edges_grad(ivhd_edges *e, const float *d_y, float c, float eps, const f
     y = e->yp;
   }
   HIPCHK(launch_grad_det(edge_args(e, y, c, eps, d_scale), (float2 *)d_grad, e->stream));
+  return IVHD_OK;
+}
+
+int ivhd_edges_stress_grad(ivhd_edges *e, const float *d_y, float c, float eps, const float *d_scale,
+                           double *d_E, float *d_grad) {
+  if (!edges_live(e)) return fail(IVHD_ESTATE, "invalid edge plan");
+  if (!d_y || !d_E || !d_grad) return fail(IVHD_EINVAL, "d_y, d_E and d_grad must not be NULL");
+  if (d_y == d_grad) return fail(IVHD_EINVAL, "d_y and d_grad alias");
+  if (!std::isfinite(c) || c < 0.f) return fail(IVHD_EINVAL, "c = %g must be finite and >= 0", (double)c);
+  if (!std::isfinite(eps) || eps < 0.f) return fail(IVHD_EINVAL, "eps = %g must be >= 0", (double)eps);
+  const float2 *y = (const float2 *)d_y;
+  if (e->perm) {
+    HIPCHK(launch_gather_f2(y, e->perm, e->M, e->yp, e->stream));
+    y = e->yp;
+  }
+  StepArgs a = edge_args(e, y, c, eps, d_scale);
+  a.e_part = e->gparts;
+  HIPCHK(launch_grad_det(a, (float2 *)d_grad, e->stream));
+  HIPCHK(launch_stress_final(e->gparts, e->ngparts, d_E, e->stream));
+  return IVHD_OK;
+}
+
+int ivhd_scale_f32(const float *d_x, int64_t n, const float *d_scale, float *d_out, void *stream) {
+  if (n < 0) return fail(IVHD_EINVAL, "n = %lld < 0", (long long)n);
+  if (n == 0) return IVHD_OK;
+  if (!d_x || !d_scale || !d_out) return fail(IVHD_EINVAL, "d_x, d_scale and d_out must not be NULL");
+  HIPCHK(launch_scale_f32(d_x, n, d_scale, d_out, (hipStream_t)stream));
   return IVHD_OK;
 }
 

@@ -52,21 +52,50 @@ stress_partial_kernel(const float2 *__restrict__ y, int64_t M, const int32_t *__
   if (threadIdx.x == 0) partials[blockIdx.x] = lds[0];
 }
 
-__global__ void __launch_bounds__(kStressBlock)
+// one block: thread t adds partials t, t + kFinalBlock, t + 2 kFinalBlock, ...
+// in that order (eight loads in flight), then a fixed tree over the threads
+constexpr int kFinalBlock = 1024;
+
+__global__ void __launch_bounds__(kFinalBlock)
 stress_final_kernel(const double *__restrict__ partials, int nparts, double *out) {
-  __shared__ double lds[kStressBlock];
+  __shared__ double lds[kFinalBlock];
   double e = 0.0;
-  for (int p = threadIdx.x; p < nparts; p += kStressBlock) e += partials[p];
+  for (int base = threadIdx.x; base < nparts; base += 8 * kFinalBlock) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int p = base + u * kFinalBlock;
+      v[u] = p < nparts ? partials[p] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) e += v[u];
+  }
   lds[threadIdx.x] = e;
   __syncthreads();
-  for (int s = kStressBlock / 2; s > 0; s >>= 1) {
+  for (int s = kFinalBlock / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = lds[0];
 }
 
+// out may equal x
+__global__ void scale_f32_kernel(const float *x, int64_t n, const float *scale, float *out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[k] = *scale * x[k];
+}
+
 }  // namespace
+
+hipError_t launch_stress_final(const double *partials, int nparts, double *out, hipStream_t s) {
+  stress_final_kernel<<<1, kFinalBlock, 0, s>>>(partials, nparts, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_f32(const float *x, int64_t n, const float *scale, float *out, hipStream_t s) {
+  if (n > 0) scale_f32_kernel<<<grid_for(n, kStressBlock), kStressBlock, 0, s>>>(x, n, scale, out);
+  return hipGetLastError();
+}
 
 int stress_partials(int64_t M) { return (int)grid_for(M, kStressBlock); }
 
@@ -79,7 +108,7 @@ hipError_t launch_stress(const float2 *y, int64_t M, const int32_t *nn_idx, int 
   else
     stress_partial_kernel<false><<<(unsigned)nparts, kStressBlock, 0, s>>>(y, M, nn_idx, nn, rn_idx, rn, c,
                                                                           partials);
-  stress_final_kernel<<<1, kStressBlock, 0, s>>>(partials, nparts, out);
+  stress_final_kernel<<<1, kFinalBlock, 0, s>>>(partials, nparts, out);
   return hipGetLastError();
 }
 

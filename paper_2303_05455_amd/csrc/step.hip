@@ -80,6 +80,25 @@ __device__ __forceinline__ float2 rn_term(float2 yi, float2 yo, float c, float e
   return make_float2(s * dx, s * dy);
 }
 
+// an out-edge's share of Eq. ivhd_cost_function in FP64, from the FP32
+// positions widened before subtracting (the terms of the stress kernel)
+template <bool L1>
+__device__ __forceinline__ double nn_stress(float2 yi, float2 yo) {
+  const double dx = (double)yi.x - (double)yo.x, dy = (double)yi.y - (double)yo.y;
+  if (L1) {
+    const double d = fabs(dx) + fabs(dy);
+    return d * d;
+  }
+  return dx * dx + dy * dy;
+}
+
+template <bool L1>
+__device__ __forceinline__ double rn_stress(float2 yi, float2 yo, double c) {
+  const double dx = (double)yi.x - (double)yo.x, dy = (double)yi.y - (double)yo.y;
+  const double d = L1 ? fabs(dx) + fabs(dy) : sqrt(dx * dx + dy * dy);
+  return c * (1.0 - d) * (1.0 - d);
+}
+
 // in-edge segment [s, e) of a light vertex, eight (then four) gathers in
 // flight at a time; the terms are still added one by one in ascending order
 template <bool RN, bool L1>
@@ -119,23 +138,29 @@ __device__ __forceinline__ void gather_segment(const float2 *__restrict__ y, con
 // Positions are gathered from A.h (Y, or the look-ahead H = Y + a V).
 // With ARN (atomic mode) the rn in-edges are not gathered: each rn
 // out-edge's reaction goes to the other end's accumulator with float atomics.
-template <bool L1, bool ARN>
+// With ST the out-edges' stress terms are added to es in FP64 (out-nn, then
+// out-rn).
+template <bool L1, bool ARN, bool ST = false>
 __device__ __forceinline__ float2 light_force(const StepArgs &A, int64_t i, float2 yi, int32_t ns,
-                                              int32_t ne) {
+                                              int32_t ne, double &es) {
   const float2 *__restrict__ y = A.h;
   float fx = 0.f, fy = 0.f;
   for (int q = 0; q < A.nn; ++q) {
     const int32_t j = A.nn_idx[i * A.nn + q];
     if (j >= 0) {
-      const float2 t = nn_term<L1>(yi, y[j]);
+      const float2 yj = y[j];
+      const float2 t = nn_term<L1>(yi, yj);
       fx += t.x; fy += t.y;
+      if (ST) es += nn_stress<L1>(yi, yj);
     }
   }
   for (int q = 0; q < A.rn; ++q) {
     const int32_t k = A.rn_idx[i * A.rn + q];
     if (k >= 0) {
-      const float2 t = rn_term<L1>(yi, y[k], A.c, A.eps);
+      const float2 yk = y[k];
+      const float2 t = rn_term<L1>(yi, yk, A.c, A.eps);
       fx += t.x; fy += t.y;
+      if (ST) es += rn_stress<L1>(yi, yk, (double)A.c);
       if (ARN) {
         unsafeAtomicAdd(&A.fbuf[k].x, -t.x);
         unsafeAtomicAdd(&A.fbuf[k].y, -t.y);
@@ -150,9 +175,10 @@ __device__ __forceinline__ float2 light_force(const StepArgs &A, int64_t i, floa
 
 // force on a heavy vertex, computed by a whole wavefront: the vertex's edge
 // list (out-nn | out-rn | in-nn | in-rn) is split over the lanes round-robin,
-// then reduced with a fixed butterfly; every lane returns the total
-template <bool L1, bool ARN>
-__device__ __forceinline__ float2 heavy_force(const StepArgs &A, int64_t i, float2 yi, int lane) {
+// then reduced with a fixed butterfly; every lane returns the total.  With
+// ST each lane adds the stress terms of its out-edges to its own es.
+template <bool L1, bool ARN, bool ST = false>
+__device__ __forceinline__ float2 heavy_force(const StepArgs &A, int64_t i, float2 yi, int lane, double &es) {
   const float2 *__restrict__ y = A.h;
   const int32_t ns = A.nn_ptr[i], ne = A.nn_ptr[i + 1];
   const int32_t rs = !ARN && A.rn > 0 ? A.rn_ptr[i] : 0, re = !ARN && A.rn > 0 ? A.rn_ptr[i + 1] : 0;
@@ -195,6 +221,8 @@ __device__ __forceinline__ float2 heavy_force(const StepArgs &A, int64_t i, floa
       if (!kind[u]) continue;
       const float2 t = kind[u] == 1 ? nn_term<L1>(yi, yo[u]) : rn_term<L1>(yi, yo[u], A.c, A.eps);
       fx += t.x; fy += t.y;
+      if (ST && e0 + u * 64 < n_out)
+        es += kind[u] == 1 ? nn_stress<L1>(yi, yo[u]) : rn_stress<L1>(yi, yo[u], (double)A.c);
       // an rn out-edge (the only rn edges listed with ARN): its reaction by atomics
       if (ARN && kind[u] == 2) {
         unsafeAtomicAdd(&A.fbuf[other[u]].x, -t.x);
@@ -267,21 +295,23 @@ __device__ __forceinline__ void block_sum_store(double x, double *out) {
 }
 
 // GRAD = true: out = s grad E = -2 s f with s = *gscale (1 when NULL), at
-// A.h = A.y, stored through A.out_perm when set; otherwise one iteration
-// (force + update).  No thread leaves before the ADAPT block sum.
+// A.h = A.y, stored through A.out_perm when set; with ST also each block's
+// FP64 stress of its vertices' out-edges to A.e_part.  Otherwise one
+// iteration (force + update).  No thread leaves before the block sums.
 // ARN = true is pass 1 of the atomic mode: each vertex's own share (its nn
 // edges both ways and its rn out-edges) goes to A.fown, the rn reactions to
 // A.fbuf by atomics; no update.
-template <bool GRAD, bool L1, int OPT, bool ARN = false>
+template <bool GRAD, bool L1, int OPT, bool ARN = false, bool ST = false>
 __global__ void __launch_bounds__(kDetBlock) det_kernel(StepArgs A, float2 *out) {
-  double ke = 0.0;
+  static_assert(!ST || GRAD, "the stress is accumulated by the gradient kernels only");
+  double ke = 0.0, es = 0.0;
   if ((int32_t)blockIdx.x < A.heavy_blocks) {
     const int lane = threadIdx.x & 63;
     const int32_t h = (int32_t)blockIdx.x * kHeavyPerBlock + (int32_t)(threadIdx.x >> 6);
     if (h < A.n_heavy) {   // uniform over the wavefront
       const int64_t i = A.heavy[h];
       const float2 hi = A.h[i];
-      const float2 f = heavy_force<L1, ARN>(A, i, hi, lane);
+      const float2 f = heavy_force<L1, ARN, ST>(A, i, hi, lane, es);
       if (lane == 0) {
         if (ARN) {
           A.fown[i] = f;
@@ -304,7 +334,7 @@ __global__ void __launch_bounds__(kDetBlock) det_kernel(StepArgs A, float2 *out)
       const int32_t ns = A.nn_ptr[i], ne = A.nn_ptr[i + 1];
       if (ne - ns <= A.heavy_deg) {   // else served by a heavy wavefront
         const float2 hi = A.h[i];
-        const float2 f = light_force<L1, ARN>(A, i, hi, ns, ne);
+        const float2 f = light_force<L1, ARN, ST>(A, i, hi, ns, ne, es);
         if (ARN) {
           A.fown[i] = f;
         } else if (GRAD) {
@@ -317,6 +347,7 @@ __global__ void __launch_bounds__(kDetBlock) det_kernel(StepArgs A, float2 *out)
     }
   }
   if (OPT == OPT_ADAPT) block_sum_store(ke, A.ke_part + blockIdx.x);
+  if (ST) block_sum_store(es, A.e_part + blockIdx.x);
 }
 
 __global__ void heavy_list_kernel(const int32_t *__restrict__ nn_ptr, int64_t M, int heavy_deg, int32_t *list,
@@ -467,8 +498,14 @@ hipError_t launch_step_atomic(const StepArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_grad_det(const StepArgs &a, float2 *out, hipStream_t s) {
-  if (a.l1) det_kernel<true, true, OPT_PLAIN><<<det_grid(a), kDetBlock, 0, s>>>(a, out);
-  else det_kernel<true, false, OPT_PLAIN><<<det_grid(a), kDetBlock, 0, s>>>(a, out);
+  const unsigned g = det_grid(a);
+  if (a.e_part) {
+    if (a.l1) det_kernel<true, true, OPT_PLAIN, false, true><<<g, kDetBlock, 0, s>>>(a, out);
+    else det_kernel<true, false, OPT_PLAIN, false, true><<<g, kDetBlock, 0, s>>>(a, out);
+  } else {
+    if (a.l1) det_kernel<true, true, OPT_PLAIN><<<g, kDetBlock, 0, s>>>(a, out);
+    else det_kernel<true, false, OPT_PLAIN><<<g, kDetBlock, 0, s>>>(a, out);
+  }
   return hipGetLastError();
 }
 

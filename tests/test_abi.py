@@ -194,3 +194,12 @@ def test_edges_create_rejects_unknown_flags_and_bad_sizes(lib):
     assert lib.ivhd_edges_create(ctypes.byref(h), 100, FAKE, 0, FAKE, 1, 1, None) == -1
     assert lib.ivhd_edges_create(ctypes.byref(h), 100, None, 2, FAKE, 1, 1, None) == -1
     assert lib.ivhd_edges_create(None, 100, FAKE, 2, FAKE, 1, 0, None) == -1
+
+
+def test_fused_stress_gradient_and_scale_reject_bad_arguments(lib):
+    assert lib.ivhd_edges_stress_grad(None, FAKE, 0.1, 1e-12, None, FAKE, FAKE) != 0
+    assert "invalid edge plan" in lib.ivhd_last_error().decode()
+    assert lib.ivhd_scale_f32(FAKE, -1, FAKE, FAKE, None) == -1
+    assert lib.ivhd_scale_f32(None, 0, None, None, None) == 0
+    assert lib.ivhd_scale_f32(FAKE, 10, None, FAKE, None) == -1
+    assert lib.ivhd_scale_f32(None, 10, FAKE, FAKE, None) == -1

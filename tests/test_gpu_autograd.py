@@ -104,8 +104,13 @@ def test_gradient_at_the_differentiable_stress_workload_size(m, reorder):
     edges = ag.StressEdges(torch.from_numpy(nn_idx).cuda(), torch.from_numpy(rn_idx).cuda(), c=cfg.c,
                            reorder=reorder)
     y = torch.from_numpy(Y).cuda()
-    assert edges.stress64(y).item() == pytest.approx(oracle.stress(Y, nn_idx, rn_idx, f32(cfg.c)), rel=1e-10)
-    assert _rel(edges.grad(y).cpu().numpy(), oracle.grad(Y, nn_idx, rn_idx, f32(cfg.c), f32(1e-12))) <= 1e-5
+    E_ref = oracle.stress(Y, nn_idx, rn_idx, f32(cfg.c))
+    assert edges.stress64(y).item() == pytest.approx(E_ref, rel=1e-10)
+    g = edges.grad(y)
+    assert _rel(g.cpu().numpy(), oracle.grad(Y, nn_idx, rn_idx, f32(cfg.c), f32(1e-12))) <= 1e-5
+    E_f, g_f = edges.stress_grad(y)
+    assert E_f.item() == pytest.approx(E_ref, rel=1e-10)
+    assert torch.equal(g_f, g)
 
 
 def test_one_shot_gradient_and_stress(m):
@@ -196,3 +201,55 @@ def test_reordered_plan_keeps_its_own_lists_and_agrees_with_the_plain_plan(m):
         assert _rel(g_o, g_p.astype(np.float64)) <= 1e-6
     ordered.close()
     plain.close()
+
+
+@pytest.mark.parametrize("reorder", [True, False])
+@pytest.mark.parametrize("M,nn,rn,seed,hub,absent", [
+    (1000, 3, 1, 0, 0.0, 0.0), (4001, 5, 2, 1, 0.8, 0.1), (777, 2, 0, 2, 0.0, 0.0), (2500, 1, 3, 3, 1.0, 0.0),
+])
+def test_stress_and_gradient_from_one_pass(m, M, nn, rn, seed, hub, absent, reorder):
+    # the fused call's stress is the oracle's (the per-edge terms of the
+    # stress kernel, summed per block of the gradient kernel), its gradient
+    # the gradient call's bit for bit, scaled or not; hubs (in-degree above
+    # the threshold) exercise the wavefront-per-vertex path
+    pkg, ag = m
+    nn_idx, rn_idx, Y = _case(M, nn, rn, seed, hub, absent)
+    c = f32(0.1)
+    edges = ag.StressEdges(torch.from_numpy(nn_idx).cuda(),
+                           torch.from_numpy(rn_idx).cuda() if rn else None, c=c, reorder=reorder)
+    y = torch.from_numpy(Y).cuda()
+    E_ref = oracle.stress(Y, nn_idx, rn_idx, c)
+    E, g = edges.stress_grad(y)
+    assert E.item() == pytest.approx(E_ref, rel=1e-10)
+    assert E.item() == pytest.approx(edges.stress64(y).item(), rel=1e-12)
+    assert torch.equal(g, edges.grad(y))
+    s = torch.tensor([0.375], dtype=torch.float32, device="cuda")
+    E2, g2 = edges.stress_grad(y, scale=s)
+    assert E2.item() == E.item()
+    assert torch.equal(g2, edges.grad(y, s))
+    # the chain-rule scale, in place and out of place
+    out = torch.empty_like(g)
+    pkg.ivhd_scale_f32(g, s, out)
+    assert torch.equal(out, g2)
+    pkg.ivhd_scale_f32(g, s, g)
+    assert torch.equal(g, g2)
+    edges.close()
+
+
+def test_autograd_takes_one_pass_when_the_layout_requires_a_gradient(m):
+    # with a gradient the forward runs the fused call and the backward only
+    # scales; without one the forward takes the stress alone; both losses
+    # equal, and the gradient equals the gradient call's
+    pkg, ag = m
+    nn_idx, rn_idx, Y = _case(3001, 4, 1, 12, hub=0.9)
+    edges = ag.StressEdges(torch.from_numpy(nn_idx).cuda(), torch.from_numpy(rn_idx).cuda(), c=0.1)
+    y = torch.from_numpy(Y).cuda().requires_grad_(True)
+    loss = ag.IVHDStress.apply(y, edges)
+    (0.5 * loss).backward()
+    with torch.no_grad():
+        loss_ng = ag.IVHDStress.apply(y, edges)
+    assert loss.item() == pytest.approx(loss_ng.item(), rel=1e-6)
+    half = torch.tensor([0.5], dtype=torch.float32, device="cuda")
+    assert torch.equal(y.grad, edges.grad(y.detach(), half))
+    assert _rel(y.grad.cpu().numpy(), 0.5 * oracle.grad(Y, nn_idx, rn_idx, f32(0.1), f32(1e-12))) <= 1e-5
+    edges.close()
