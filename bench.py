@@ -501,7 +501,7 @@ def layout_quality(dX, y, labels, n_rows=10_000, seed=5):
 
 def run_encoder(args, cfg):
     """Parametric IVHD: train the MLP on the stress of its batches, embed the
-    held-out points, judge them by kNN preservation beside plain IVHD."""
+    held-out points, score them by kNN preservation beside plain IVHD."""
     import torch
     import synth
     from paper_2303_05455_amd import Context, ivhd_knn_build
@@ -655,7 +655,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+        print(f"bench.py runs on one GPU only (the library has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
 
