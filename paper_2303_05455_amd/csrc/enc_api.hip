@@ -41,7 +41,7 @@ struct ivhd_enc {
   float *z = nullptr, *dz = nullptr;
   float *ws = nullptr;
   int64_t ws_elems = 0;
-  int splits = 16;
+  int splits = 32;   // K splits of the weight-gradient GEMMs: 8-14 output tiles each, so 256-448 blocks
   // epoch training state
   int32_t *rows = nullptr;
   int32_t *lnn = nullptr, *lrn = nullptr;
