@@ -46,6 +46,9 @@ def _norm_rel(x, ref):
     # tail inside the last step, every epilogue, split-K
     (33001, 520, 792, 0, 1, 0, 1), (33001, 520, 792, 0, 1, 1, 1), (33001, 520, 792, 0, 1, 2, 1),
     (4096, 512, 4096, 0, 1, 0, 8), (65536, 512, 784, 0, 1, 1, 1),
+    # K-contiguous operands with an output width that is not a multiple of 8
+    # (element-wise output and mask chunks), every epilogue, split-K
+    (300, 77, 512, 0, 1, 1, 1), (300, 77, 512, 0, 1, 2, 1), (300, 77, 520, 0, 1, 0, 3),
 ])
 def test_gemm_matches_fp64_on_identical_bf16_operands(pkg, M, N, K, ta, tb, epi, splits):
     m, api, _, _ = pkg
