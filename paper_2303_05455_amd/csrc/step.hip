@@ -145,8 +145,27 @@ __device__ __forceinline__ float2 light_force(const StepArgs &A, int64_t i, floa
                                               int32_t ne, double &es) {
   const float2 *__restrict__ y = A.h;
   float fx = 0.f, fy = 0.f;
-  for (int q = 0; q < A.nn; ++q) {
-    const int32_t j = A.nn_idx[i * A.nn + q];
+  const int32_t *__restrict__ out_nn = A.nn_idx + i * A.nn;
+  int q = 0;
+  // four out-nn edges at a time (their loads in flight together; an absent
+  // slot reads the vertex itself and adds nothing), terms in edge order
+  for (; q + 4 <= A.nn; q += 4) {
+    int32_t j[4];
+    float2 yv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) j[u] = out_nn[q + u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) yv[u] = y[j[u] >= 0 ? (int64_t)j[u] : i];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (j[u] < 0) continue;
+      const float2 t = nn_term<L1>(yi, yv[u]);
+      fx += t.x; fy += t.y;
+      if (ST) es += nn_stress<L1>(yi, yv[u]);
+    }
+  }
+  for (; q < A.nn; ++q) {
+    const int32_t j = out_nn[q];
     if (j >= 0) {
       const float2 yj = y[j];
       const float2 t = nn_term<L1>(yi, yj);
