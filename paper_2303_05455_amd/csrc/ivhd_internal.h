@@ -15,7 +15,9 @@ constexpr int kScanChunk = kBlock * kScanItems;
 constexpr int kSmallSegment = 32;    // in-edge segments up to this size are sorted per thread
 constexpr int kBigSortBlocks = 256;  // blocks that share the list of large segments
 constexpr int kHeavyDegree = 80;     // nn in-degree above which a vertex gets a whole wavefront (large graphs)
-constexpr int kSmallGraphHeavyDegree = 16;   // the same below 500,000 vertices
+constexpr int kSmallGraphHeavyDegree = 16;   // the same below kSmallGraphVertices
+constexpr int64_t kSmallGraphVertices = 500000;
+constexpr int kSmallGraphLanes = 4;  // lanes per light vertex of the deterministic step below that size
 constexpr int kDetBlock = 64;        // threads per block of the deterministic step kernel (one wavefront)
 constexpr int kHeavyPerBlock = kDetBlock / 64;
 constexpr int kXcds = 8;             // MI355X: 8 XCDs, workgroups dealt round-robin
@@ -175,7 +177,8 @@ struct StepArgs {
   int32_t n_heavy;
   int32_t heavy_deg;      // nn in-degree above which a vertex gets a whole wavefront
   int32_t heavy_blocks;   // leading blocks of a launch that serve the heavy vertices (multiple of kXcds)
-  int32_t light_tiles;    // tiles of kDetBlock consecutive vertices
+  int32_t lanes;          // lanes per light vertex: 1, or kSmallGraphLanes below kSmallGraphVertices
+  int32_t light_tiles;    // tiles of kDetBlock / lanes consecutive vertices
   int32_t tiles_per_xcd;  // consecutive tiles given to each XCD
   int64_t M;
   int nn, rn;
@@ -187,7 +190,9 @@ struct StepArgs {
 inline void set_launch_shape(StepArgs &a) {
   const int32_t hb = (a.n_heavy + kHeavyPerBlock - 1) / kHeavyPerBlock;
   a.heavy_blocks = (hb + kXcds - 1) / kXcds * kXcds;
-  a.light_tiles = (int32_t)((a.M + kDetBlock - 1) / kDetBlock);
+  a.lanes = a.M < kSmallGraphVertices ? kSmallGraphLanes : 1;
+  const int32_t per_tile = kDetBlock / a.lanes;
+  a.light_tiles = (int32_t)((a.M + per_tile - 1) / per_tile);
   a.tiles_per_xcd = (a.light_tiles + kXcds - 1) / kXcds;
 }
 unsigned det_grid(const StepArgs &a);   // blocks of one deterministic launch

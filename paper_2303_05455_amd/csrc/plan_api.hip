@@ -27,7 +27,7 @@ int build_csc(const int32_t *idx, int64_t M, int k, Csc &g, CscScratch &sc, int3
 
 // measured: 70,000 vertices (nn = 5) 9.6 us per step at 16 against 11.2 us at
 // 80; 1.4M vertices (nn = 2) 67.9 us at 80 against 69.2 at 48 and 69.0 at 100
-int heavy_degree(int64_t M) { return M < 500000 ? kSmallGraphHeavyDegree : kHeavyDegree; }
+int heavy_degree(int64_t M) { return M < kSmallGraphVertices ? kSmallGraphHeavyDegree : kHeavyDegree; }
 
 // the vertices of nn in-degree above heavy_deg; synchronises s to read the count
 int build_heavy(const Csc &nn_csc, int64_t M, int heavy_deg, int32_t *heavy, int32_t *flags, int32_t *n_heavy,

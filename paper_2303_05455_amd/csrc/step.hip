@@ -22,7 +22,8 @@
 //     and a fixed xor-butterfly adds their partial sums;
 //   * the other blocks give each remaining vertex one thread, which issues
 //     its in-edge gathers eight (then four) at a time so several loads are
-//     in flight.
+//     in flight -- or, on graphs too small to fill the chip that way, a
+//     group of four lanes that share its edge list like a hub's wavefront.
 // Both orders of summation are fixed, so results are bitwise reproducible.
 //
 // Atomic mode: pass 1 is the deterministic kernel's walk without the rn
@@ -192,26 +193,30 @@ __device__ __forceinline__ float2 light_force(const StepArgs &A, int64_t i, floa
   return make_float2(fx, fy);
 }
 
-// force on a heavy vertex, computed by a whole wavefront: the vertex's edge
-// list (out-nn | out-rn | in-nn | in-rn) is split over the lanes round-robin,
-// then reduced with a fixed butterfly; every lane returns the total.  With
+// force on a vertex computed by a group of G aligned lanes (a whole
+// wavefront for a hub, G = 64; four lanes for a light vertex of a small
+// graph): the vertex's edge list (out-nn | out-rn | in-nn | in-rn) is split
+// over the group's lanes round-robin, then reduced with a fixed butterfly
+// over the group; every lane of the group returns the total.  r is the
+// lane's rank in the group, [ns, ne) the vertex's nn in-edge segment.  With
 // ST each lane adds the stress terms of its out-edges to its own es.
-template <bool L1, bool ARN, bool ST = false>
-__device__ __forceinline__ float2 heavy_force(const StepArgs &A, int64_t i, float2 yi, int lane, double &es) {
+template <bool L1, bool ARN, bool ST, int G>
+__device__ __forceinline__ float2 spread_force(const StepArgs &A, int64_t i, float2 yi, int r, int32_t ns,
+                                               int32_t ne, double &es) {
+  static_assert(G >= 2 && G <= 64 && (G & (G - 1)) == 0, "a group is a power of two within a wavefront");
   const float2 *__restrict__ y = A.h;
-  const int32_t ns = A.nn_ptr[i], ne = A.nn_ptr[i + 1];
   const int32_t rs = !ARN && A.rn > 0 ? A.rn_ptr[i] : 0, re = !ARN && A.rn > 0 ? A.rn_ptr[i + 1] : 0;
   const int32_t n_out = A.nn + A.rn, n_in_nn = ne - ns;
   const int32_t total = n_out + n_in_nn + (re - rs);
   float fx = 0.f, fy = 0.f;
   // four of a lane's edges at a time: their index and position loads are
   // issued together, the terms are still added in ascending edge order
-  for (int32_t e0 = lane; e0 < total; e0 += 4 * 64) {
+  for (int32_t e0 = r; e0 < total; e0 += 4 * G) {
     int32_t other[4];
     int kind[4];   // 0 none, 1 nn, 2 rn
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int32_t e = e0 + u * 64;
+      const int32_t e = e0 + u * G;
       int32_t o = -1;
       int k = 0;
       if (e < total) {
@@ -240,7 +245,7 @@ __device__ __forceinline__ float2 heavy_force(const StepArgs &A, int64_t i, floa
       if (!kind[u]) continue;
       const float2 t = kind[u] == 1 ? nn_term<L1>(yi, yo[u]) : rn_term<L1>(yi, yo[u], A.c, A.eps);
       fx += t.x; fy += t.y;
-      if (ST && e0 + u * 64 < n_out)
+      if (ST && e0 + u * G < n_out)
         es += kind[u] == 1 ? nn_stress<L1>(yi, yo[u]) : rn_stress<L1>(yi, yo[u], (double)A.c);
       // an rn out-edge (the only rn edges listed with ARN): its reaction by atomics
       if (ARN && kind[u] == 2) {
@@ -250,7 +255,7 @@ __device__ __forceinline__ float2 heavy_force(const StepArgs &A, int64_t i, floa
     }
   }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
+  for (int o = G / 2; o > 0; o >>= 1) {
     fx += __shfl_xor(fx, o, 64);
     fy += __shfl_xor(fy, o, 64);
   }
@@ -320,9 +325,13 @@ __device__ __forceinline__ void block_sum_store(double x, double *out) {
 // ARN = true is pass 1 of the atomic mode: each vertex's own share (its nn
 // edges both ways and its rn out-edges) goes to A.fown, the rn reactions to
 // A.fbuf by atomics; no update.
-template <bool GRAD, bool L1, int OPT, bool ARN = false, bool ST = false>
+// G = lanes per light vertex (A.lanes): 1, or kSmallGraphLanes on graphs of
+// fewer than kSmallGraphVertices vertices, where one lane per vertex leaves
+// too few wavefronts to hide each lane's chain of dependent loads.
+template <bool GRAD, bool L1, int OPT, bool ARN = false, bool ST = false, int G = 1>
 __global__ void __launch_bounds__(kDetBlock) det_kernel(StepArgs A, float2 *out) {
   static_assert(!ST || GRAD, "the stress is accumulated by the gradient kernels only");
+  static_assert(G == 1 || G == kSmallGraphLanes, "lanes per light vertex");
   double ke = 0.0, es = 0.0;
   if ((int32_t)blockIdx.x < A.heavy_blocks) {
     const int lane = threadIdx.x & 63;
@@ -330,7 +339,7 @@ __global__ void __launch_bounds__(kDetBlock) det_kernel(StepArgs A, float2 *out)
     if (h < A.n_heavy) {   // uniform over the wavefront
       const int64_t i = A.heavy[h];
       const float2 hi = A.h[i];
-      const float2 f = heavy_force<L1, ARN, ST>(A, i, hi, lane, es);
+      const float2 f = spread_force<L1, ARN, ST, 64>(A, i, hi, lane, A.nn_ptr[i], A.nn_ptr[i + 1], es);
       if (lane == 0) {
         if (ARN) {
           A.fown[i] = f;
@@ -346,15 +355,22 @@ __global__ void __launch_bounds__(kDetBlock) det_kernel(StepArgs A, float2 *out)
     // XCD-aware tiles: blocks are dealt to the XCDs round-robin, so block b
     // runs on XCD b % kXcds; each XCD is given one contiguous range of tiles,
     // keeping the positions its vertices gather from in its own L2
+    // (a tile is kDetBlock / G consecutive vertices; with G > 1 the group
+    // condition below is uniform over each group of G lanes)
     const int32_t lb = (int32_t)blockIdx.x - A.heavy_blocks;
     const int32_t tile = (lb % kXcds) * A.tiles_per_xcd + lb / kXcds;
-    const int64_t i = (int64_t)tile * kDetBlock + threadIdx.x;
+    const int64_t i = (int64_t)tile * (kDetBlock / G) + threadIdx.x / G;
+    const int r = (int)(threadIdx.x % G);
     if (tile < A.light_tiles && i < A.M) {
       const int32_t ns = A.nn_ptr[i], ne = A.nn_ptr[i + 1];
       if (ne - ns <= A.heavy_deg) {   // else served by a heavy wavefront
         const float2 hi = A.h[i];
-        const float2 f = light_force<L1, ARN, ST>(A, i, hi, ns, ne, es);
-        if (ARN) {
+        float2 f;
+        if constexpr (G == 1) f = light_force<L1, ARN, ST>(A, i, hi, ns, ne, es);
+        else f = spread_force<L1, ARN, ST, G>(A, i, hi, r, ns, ne, es);
+        if (r != 0) {
+          // the group's leader stores the result
+        } else if (ARN) {
           A.fown[i] = f;
         } else if (GRAD) {
           const float g = -2.f * (A.gscale ? *A.gscale : 1.f);
@@ -492,45 +508,53 @@ hipError_t launch_heavy_list(const int32_t *nn_ptr, int64_t M, int heavy_deg, in
   return hipGetLastError();
 }
 
+// one deterministic launch, with the lanes per light vertex of the shape
+template <bool GRAD, bool L1, int OPT, bool ARN = false, bool ST = false>
+void launch_det(const StepArgs &a, float2 *out, hipStream_t s) {
+  if (a.lanes == kSmallGraphLanes)
+    det_kernel<GRAD, L1, OPT, ARN, ST, kSmallGraphLanes><<<det_grid(a), kDetBlock, 0, s>>>(a, out);
+  else
+    det_kernel<GRAD, L1, OPT, ARN, ST, 1><<<det_grid(a), kDetBlock, 0, s>>>(a, out);
+}
+
 template <bool L1>
-void launch_det_opt(const StepArgs &a, unsigned g, hipStream_t s) {
+void launch_det_opt(const StepArgs &a, hipStream_t s) {
   switch (a.opt) {
-    case OPT_NEST: det_kernel<false, L1, OPT_NEST><<<g, kDetBlock, 0, s>>>(a, nullptr); break;
-    case OPT_ADAPT: det_kernel<false, L1, OPT_ADAPT><<<g, kDetBlock, 0, s>>>(a, nullptr); break;
-    case OPT_ADAM: det_kernel<false, L1, OPT_ADAM><<<g, kDetBlock, 0, s>>>(a, nullptr); break;
-    default: det_kernel<false, L1, OPT_PLAIN><<<g, kDetBlock, 0, s>>>(a, nullptr); break;
+    case OPT_NEST: launch_det<false, L1, OPT_NEST>(a, nullptr, s); break;
+    case OPT_ADAPT: launch_det<false, L1, OPT_ADAPT>(a, nullptr, s); break;
+    case OPT_ADAM: launch_det<false, L1, OPT_ADAM>(a, nullptr, s); break;
+    default: launch_det<false, L1, OPT_PLAIN>(a, nullptr, s); break;
   }
 }
 
 hipError_t launch_step_det(const StepArgs &a, hipStream_t s) {
-  if (a.l1) launch_det_opt<true>(a, det_grid(a), s);
-  else launch_det_opt<false>(a, det_grid(a), s);
+  if (a.l1) launch_det_opt<true>(a, s);
+  else launch_det_opt<false>(a, s);
   return hipGetLastError();
 }
 
 hipError_t launch_step_atomic(const StepArgs &a, hipStream_t s) {
-  if (a.l1) det_kernel<false, true, OPT_PLAIN, true><<<det_grid(a), kDetBlock, 0, s>>>(a, nullptr);
-  else det_kernel<false, false, OPT_PLAIN, true><<<det_grid(a), kDetBlock, 0, s>>>(a, nullptr);
+  if (a.l1) launch_det<false, true, OPT_PLAIN, true>(a, nullptr, s);
+  else launch_det<false, false, OPT_PLAIN, true>(a, nullptr, s);
   if (a.opt == OPT_NEST) atomic_update_kernel<OPT_NEST><<<grid_for(a.M), kBlock, 0, s>>>(a);
   else atomic_update_kernel<OPT_PLAIN><<<grid_for(a.M), kBlock, 0, s>>>(a);
   return hipGetLastError();
 }
 
 hipError_t launch_grad_det(const StepArgs &a, float2 *out, hipStream_t s) {
-  const unsigned g = det_grid(a);
   if (a.e_part) {
-    if (a.l1) det_kernel<true, true, OPT_PLAIN, false, true><<<g, kDetBlock, 0, s>>>(a, out);
-    else det_kernel<true, false, OPT_PLAIN, false, true><<<g, kDetBlock, 0, s>>>(a, out);
+    if (a.l1) launch_det<true, true, OPT_PLAIN, false, true>(a, out, s);
+    else launch_det<true, false, OPT_PLAIN, false, true>(a, out, s);
   } else {
-    if (a.l1) det_kernel<true, true, OPT_PLAIN><<<g, kDetBlock, 0, s>>>(a, out);
-    else det_kernel<true, false, OPT_PLAIN><<<g, kDetBlock, 0, s>>>(a, out);
+    if (a.l1) launch_det<true, true, OPT_PLAIN>(a, out, s);
+    else launch_det<true, false, OPT_PLAIN>(a, out, s);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_grad_atomic(const StepArgs &a, float2 *out, hipStream_t s) {
-  if (a.l1) det_kernel<false, true, OPT_PLAIN, true><<<det_grid(a), kDetBlock, 0, s>>>(a, nullptr);
-  else det_kernel<false, false, OPT_PLAIN, true><<<det_grid(a), kDetBlock, 0, s>>>(a, nullptr);
+  if (a.l1) launch_det<false, true, OPT_PLAIN, true>(a, nullptr, s);
+  else launch_det<false, false, OPT_PLAIN, true>(a, nullptr, s);
   atomic_grad_out_kernel<<<grid_for(a.M), kBlock, 0, s>>>(a.fown, a.fbuf, a.M, a.gscale, a.out_perm, out);
   return hipGetLastError();
 }
