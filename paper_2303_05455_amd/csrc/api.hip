@@ -290,7 +290,8 @@ int capture(ivhd_ctx *c, bool with_draw, int64_t count, int par, hipGraphExec_t 
 
 // the internal order: vertices grouped by connected component of the nn
 // graph (components by their smallest caller id), inside a component by nn
-// in-degree capped at the hub threshold + 1, then by caller id
+// in-degree capped at the hub threshold + 1, then by first nn neighbour,
+// then by caller id
 int build_order(ivhd_ctx *c) {
   const int64_t M = c->p.M;
   hipStream_t s = c->stream;
