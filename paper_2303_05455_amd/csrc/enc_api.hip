@@ -173,8 +173,11 @@ int train_step_rows(ivhd_enc *e, int64_t R, bool xbT_ready, ivhd_edges *plan, fl
   if (!xbT_ready && (rc = feature_major(e->xb, R, e->n_in, Rp, e->xbT, s))) return rc;
   if ((rc = feature_major(e->a1, R, e->h1, Rp, e->a1T, s))) return rc;
   if ((rc = feature_major(e->w16 + e->oW2, e->h2, e->h1, e->h2, e->w2T, s))) return rc;
-  if (d_loss && (rc = ivhd_edges_stress(plan, e->z, c, d_loss))) return rc;
-  if ((rc = ivhd_edges_grad(plan, e->z, c, eps, nullptr, e->dz))) return rc;
+  if (d_loss) {   // the batch stress and its gradient from one pass
+    if ((rc = ivhd_edges_stress_grad(plan, e->z, c, eps, nullptr, d_loss, e->dz))) return rc;
+  } else if ((rc = ivhd_edges_grad(plan, e->z, c, eps, nullptr, e->dz))) {
+    return rc;
+  }
   // head: d2 = input gradient of the head, row-major and feature-major
   TileTArgs hd;
   hd.in = e->a2;

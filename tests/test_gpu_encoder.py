@@ -49,6 +49,11 @@ def _norm_rel(x, ref):
     # K-contiguous operands with an output width that is not a multiple of 8
     # (element-wise output and mask chunks), every epilogue, split-K
     (300, 77, 512, 0, 1, 1, 1), (300, 77, 512, 0, 1, 2, 1), (300, 77, 520, 0, 1, 0, 3),
+    # both operands K-major with widths that are multiples of 8 (the K-major
+    # kernel the weight gradients use): ragged M and N tiles, K tails inside
+    # a step and inside a split, split-K like the training step's, a tiny case
+    (256, 136, 1000, 1, 0, 0, 3), (264, 512, 33001, 1, 0, 0, 32), (520, 784, 20000, 1, 0, 0, 32),
+    (8, 16, 40, 1, 0, 0, 1), (512, 512, 4104, 1, 0, 0, 1),
 ])
 def test_gemm_matches_fp64_on_identical_bf16_operands(pkg, M, N, K, ta, tb, epi, splits):
     m, api, _, _ = pkg
