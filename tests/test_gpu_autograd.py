@@ -206,8 +206,9 @@ def test_reordered_plan_keeps_its_own_lists_and_agrees_with_the_plain_plan(m):
 @pytest.mark.parametrize("reorder", [True, False])
 @pytest.mark.parametrize("M,nn,rn,seed,hub,absent", [
     (1000, 3, 1, 0, 0.0, 0.0), (4001, 5, 2, 1, 0.8, 0.1), (777, 2, 0, 2, 0.0, 0.0), (2500, 1, 3, 3, 1.0, 0.0),
-    # tiny and ragged graphs: two vertices, three, and half the nn slots absent
-    (2, 1, 0, 4, 0.0, 0.0), (3, 1, 1, 5, 0.0, 0.0), (65, 2, 1, 6, 0.0, 0.5),
+    # tiny and ragged graphs: two vertices, three, half the nn slots absent,
+    # and no nn edge at all (every vertex its own component)
+    (2, 1, 0, 4, 0.0, 0.0), (3, 1, 1, 5, 0.0, 0.0), (65, 2, 1, 6, 0.0, 0.5), (500, 2, 1, 7, 0.0, 1.0),
 ])
 def test_stress_and_gradient_from_one_pass(m, M, nn, rn, seed, hub, absent, reorder):
     # the fused call's stress is the oracle's (the per-edge terms of the
