@@ -55,9 +55,15 @@ typedef enum ivhd_mode {
                               reproducible run to run                        */
     IVHD_MODE_ATOMIC = 1   /* a pass that gathers each vertex's nn edges (both
                               ways) and rn out-edges, adding each rn edge's
-                              reaction to the other end with float atomics,
-                              then an update pass; the order in which those
-                              reactions are summed varies run to run        */
+                              reaction to the other end with one 64-bit
+                              integer atomic (x and y in fixed point, unit
+                              c 2^-22, range set after each draw from the
+                              largest rn in-degree), then an update pass.
+                              Integer sums do not depend on the order of
+                              arrival: bitwise reproducible run to run, unless
+                              a reaction exceeds the fixed-point range (then
+                              it goes through float atomics, whose order of
+                              summation varies)                             */
 } ivhd_mode;
 
 /* ivhd_params.flags */

@@ -86,6 +86,10 @@ struct ivhd_ctx {
   int32_t *flags = nullptr;
   float2 *fbuf = nullptr;
   float2 *fown = nullptr;
+  uint64_t *facc = nullptr;       // atomic mode: fixed-point rn reactions
+  ReactionRange *rx = nullptr;    // atomic mode: their range for the current draw
+  int32_t *fflag = nullptr;       // atomic mode: [2] float-accumulator flags
+  int32_t fpar = 0;               // atomic mode: flag slot of the next iteration
   int32_t *heavy = nullptr;
   int32_t n_heavy = 0;
   int32_t heavy_deg = kHeavyDegree;
@@ -118,7 +122,7 @@ void free_ctx(ivhd_ctx *c) {
   }
   void *bufs[] = {c->perm, c->inv, c->nn_own, c->ya, c->yb, c->v, c->tmp, c->nn_csc.ptr, c->nn_csc.src,
                   c->rn_csc.ptr, c->rn_csc.src, c->sc.cnt, c->sc.tmp, c->sc.part, c->sc.big, c->sc.rank, c->rn_idx,
-                  c->epoch, c->flags, c->fbuf, c->fown, c->heavy, c->partials, c->d_E, c->ha, c->hb, c->vb,
+                  c->epoch, c->flags, c->fbuf, c->fown, c->facc, c->rx, c->fflag, c->heavy, c->partials, c->d_E, c->ha, c->hb, c->vb,
                   c->adapt, c->ke_part, c->s2, c->adam};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
@@ -172,6 +176,11 @@ StepArgs step_args(const ivhd_ctx *c, const float2 *y, float2 *y_out) {
   a.rn_src = c->rn_csc.src;
   a.fbuf = c->fbuf;
   a.fown = c->fown;
+  a.facc = c->facc;
+  a.rx = c->rx;
+  a.fflag = c->fflag;
+  a.rx_unit = ldexpf(c->p.c, -kReactionFracBits);
+  a.rx_inv_unit = ldexpf(1.f / c->p.c, kReactionFracBits);
   a.flags = c->flags;
   a.gscale = nullptr;
   a.heavy = c->heavy;
@@ -188,12 +197,13 @@ StepArgs step_args(const ivhd_ctx *c, const float2 *y, float2 *y_out) {
   return a;
 }
 
-// A new random-neighbour epoch: epoch += 1, draw, and (det mode) rebuild the
-// transposed rn lists.
+// A new random-neighbour epoch: epoch += 1, draw, count the rn in-degrees,
+// then rebuild the transposed rn lists (det mode) or set the fixed-point
+// range of the rn reactions (atomic mode).
 int enqueue_draw(ivhd_ctx *c, hipStream_t s) {
   if (c->p.rn == 0) return IVHD_OK;
   const int64_t M = c->p.M;
-  int32_t *cnt = c->det() ? c->sc.cnt : nullptr;
+  int32_t *cnt = c->sc.cnt;
   HIPCHK(launch_epoch_begin(c->epoch, cnt, M, c->flags, s));
   HIPCHK(launch_rn_sample(c->nn_user, M, c->p.nn, c->p.rn, c->p.seed, c->epoch, c->perm, c->inv, c->rn_idx, cnt,
                           c->det() ? c->sc.rank : nullptr, s));
@@ -201,6 +211,8 @@ int enqueue_draw(ivhd_ctx *c, hipStream_t s) {
     HIPCHK(launch_scan(c->sc.cnt, M, c->sc.part, c->rn_csc.ptr, s));
     HIPCHK(launch_place_sort(c->rn_idx, M, c->p.rn, c->rn_csc.ptr, c->sc.rank, c->sc.tmp, c->sc.big, c->flags,
                              c->rn_csc.src, s));
+  } else {
+    HIPCHK(launch_reaction_range(cnt, M, c->rx, s));
   }
   return IVHD_OK;
 }
@@ -245,6 +257,8 @@ int enqueue_steps(ivhd_ctx *c, hipStream_t s, int64_t count, int *par) {
       *par ^= 1;
     } else {
       StepArgs a = step_args(c, c->ya, c->ya);
+      a.fpar = c->fpar;
+      c->fpar ^= 1;
       if (c->nest()) {
         a.opt = OPT_NEST;
         a.h = c->ha;
@@ -417,8 +431,11 @@ int ivhd_init(ivhd_ctx **out, const ivhd_params *p, const int32_t *d_nn_idx, flo
     }
   }
   if (p->mode == IVHD_MODE_ATOMIC) {
-    ALLOC(c->fbuf, M, "rn reaction accumulator");
+    ALLOC(c->fbuf, M, "rn reaction accumulator (float)");
     ALLOC(c->fown, M, "own force shares");
+    ALLOC(c->facc, M, "rn reaction accumulator (fixed point)");
+    ALLOC(c->rx, 1, "fixed-point range of the rn reactions");
+    ALLOC(c->fflag, 2, "float reaction flags");
   }
   if (p->flags & IVHD_FLAG_NESTEROV) {
     ALLOC(c->ha, M, "look-ahead positions");
@@ -449,6 +466,8 @@ int ivhd_init(ivhd_ctx **out, const ivhd_params *p, const int32_t *d_nn_idx, flo
   CHK(build_csc(c->nn_int, M, p->nn, c->nn_csc, c->sc, c->flags, s));
   if (c->heavy) CHK(build_heavy(c->nn_csc, M, c->heavy_deg, c->heavy, c->flags, &c->n_heavy, s));
   if (c->fbuf) HIPCHK_C(launch_fill_i32((int32_t *)c->fbuf, 2 * M, 0, s));
+  if (c->facc) HIPCHK_C(launch_fill_i32((int32_t *)c->facc, 2 * M, 0, s));
+  if (c->fflag) HIPCHK_C(launch_fill_i32(c->fflag, 2, 0, s));
   CHK(load_state(c, c->y_user, c->v_user));
   const int64_t minus_one = -1;
   HIPCHK_C(hipMemcpyAsync(c->epoch, &minus_one, sizeof minus_one, hipMemcpyHostToDevice, s));
@@ -561,10 +580,13 @@ int ivhd_grad(ivhd_ctx *c, const float *d_y, float *d_grad) {
   const float2 *y = internal_positions(c, d_y, &rc);
   if (rc) return rc;
   StepArgs a = step_args(c, y, nullptr);
-  if (c->det())
+  if (c->det()) {
     HIPCHK(launch_grad_det(a, c->tmp, c->stream));
-  else
+  } else {
+    a.fpar = c->fpar;
+    c->fpar ^= 1;
     HIPCHK(launch_grad_atomic(a, c->tmp, c->stream));
+  }
   HIPCHK(launch_gather_f2(c->tmp, c->inv, c->p.M, (float2 *)d_grad, c->stream));
   return IVHD_OK;
 }

@@ -150,6 +150,22 @@ struct AdamState {
 // update rule of the deterministic step (template argument of its kernel)
 enum { OPT_PLAIN = 0, OPT_NEST = 1, OPT_ADAPT = 2, OPT_ADAM = 3 };
 
+// Atomic mode: the rn reactions a vertex receives are summed in fixed point,
+// x and y as two signed 32-bit fields of one 64-bit integer, so that one
+// integer atomic carries both coordinates and the sum does not depend on the
+// order of arrival.  The unit is c 2^-kReactionFracBits; after each draw the
+// range of one reaction is set to 2^e units with e = 30 - ceil(log2 K), K the
+// largest rn in-degree of the draw, so no field's sum can leave
+// [-2^30, 2^30].  Reactions outside the range go to a float accumulator.
+constexpr int kReactionFracBits = 22;
+constexpr int kRangeParts = 256;   // blocks of the in-degree maximum
+struct ReactionRange {
+  int32_t part[kRangeParts];   // per-block maxima of the in-degree
+  float cap;                   // largest |reaction| / unit held in fixed point (a power of two)
+};
+// rr->cap from the rn in-degree counts cnt[0..M) of a draw (two kernels)
+hipError_t launch_reaction_range(const int32_t *cnt, int64_t M, ReactionRange *rr, hipStream_t s);
+
 struct StepArgs {
   const float2 *y;        // positions read (Y_n)
   const float2 *h;        // positions the forces are taken at: y, or H = Y + a V (nesterov)
@@ -167,8 +183,13 @@ struct StepArgs {
   const int32_t *rn_idx;  // [M][rn]
   const int32_t *nn_ptr, *nn_src;   // CSC of nn edges
   const int32_t *rn_ptr, *rn_src;   // CSC of rn edges
-  float2 *fbuf;           // atomic mode: accumulator of the rn reactions [M]
+  float2 *fbuf;           // atomic mode: float accumulator of the rn reactions outside the fixed range [M]
   float2 *fown;           // atomic mode: each vertex's own share of its force [M]
+  uint64_t *facc;         // atomic mode: packed fixed-point accumulator of the rn reactions [M]
+  const ReactionRange *rx;   // atomic mode: the fixed-point range of the current draw
+  float rx_unit, rx_inv_unit;   // atomic mode: the fixed-point unit c 2^-kReactionFracBits and its inverse
+  int32_t *fflag;         // atomic mode: [2] set when a pass 1 used fbuf (slot fpar); see gather_reactions
+  int32_t fpar;           // atomic mode: the slot of this iteration (alternates from one to the next)
   int32_t *flags;
   const float *gscale;    // gradient kernels: output scaled by *gscale (NULL = 1)
   const int32_t *out_perm;   // gradient kernels: vertex i's output goes to out[out_perm[i]] (NULL: out[i])
@@ -206,7 +227,7 @@ hipError_t launch_adapt_decide(const double *part, int nparts, double tau, float
 hipError_t launch_adapt_commit(const AdaptState *st, const float2 *y, const float2 *v, int64_t M, float2 *y_next,
                                float2 *v_next, hipStream_t s);
 hipError_t launch_step_atomic(const StepArgs &a, hipStream_t s);   // two kernels
-// grad E = -2 f at positions a.y into out (det gather; or atomic scatter via fbuf)
+// grad E = -2 f at positions a.y into out (det gather; or the atomic mode's two passes)
 hipError_t launch_grad_det(const StepArgs &a, float2 *out, hipStream_t s);
 hipError_t launch_grad_atomic(const StepArgs &a, float2 *out, hipStream_t s);
 

@@ -29,11 +29,15 @@
 // Atomic mode: pass 1 is the deterministic kernel's walk without the rn
 // in-edges: each vertex gathers its nn edges both ways and its rn out-edges
 // (its own share, stored to fown) and adds each rn out-edge's reaction to
-// the other end's accumulator with float atomics; pass 2 adds the two,
-// applies the update and clears the accumulator.  Float atomics run at a
-// fixed rate of about 21 G/s on this chip whatever the footprint (measured),
-// so the mode keeps them to the rn edges: two per rn edge instead of two per
-// edge end.
+// the other end's accumulator with atomics; pass 2 adds them up, applies the
+// update and clears the accumulators.  Atomics run at a fixed rate per
+// operation on this chip whatever the footprint or memory scope (measured:
+// about 21 G/s for 32-bit float adds, 23 G/s for 64-bit integer adds), so
+// the mode keeps them to the rn edges and gives each reaction one 64-bit
+// integer atomic: x and y in fixed point, packed.  Integer sums do not
+// depend on the order of arrival, so the mode is bitwise reproducible as
+// long as every reaction fits the fixed-point range (the rare ones that do
+// not take two float atomics).
 //
 // Variants of the thesis, chosen per context and compiled as template
 // parameters so the plain loop carries none of their cost:
@@ -98,6 +102,32 @@ __device__ __forceinline__ double rn_stress(float2 yi, float2 yo, double c) {
   const double dx = (double)yi.x - (double)yo.x, dy = (double)yi.y - (double)yo.y;
   const double d = L1 ? fabs(dx) + fabs(dy) : sqrt(dx * dx + dy * dy);
   return c * (1.0 - d) * (1.0 - d);
+}
+
+// atomic mode: the reaction -t of an rn out-edge on its other end k.  Both
+// coordinates in units of A.rx_unit, rounded to the nearest integer, go to
+// k's fixed-point accumulator in one 64-bit integer atomic (y in the high
+// field, x in the low one, as y 2^32 + x); a reaction outside the range of
+// the current draw (or not finite) goes to the float accumulator instead.
+__device__ __forceinline__ void add_reaction(const StepArgs &A, int32_t k, float2 t) {
+  const float cap = A.rx->cap;
+  const float qx = -t.x * A.rx_inv_unit, qy = -t.y * A.rx_inv_unit;
+  if (fabsf(qx) <= cap && fabsf(qy) <= cap) {
+    const int32_t ix = (int32_t)rintf(qx), iy = (int32_t)rintf(qy);
+    const uint64_t w = ((uint64_t)(uint32_t)iy << 32) + (uint64_t)(int64_t)ix;
+    atomicAdd((unsigned long long *)&A.facc[k], (unsigned long long)w);
+  } else {
+    unsafeAtomicAdd(&A.fbuf[k].x, -t.x);
+    unsafeAtomicAdd(&A.fbuf[k].y, -t.y);
+    A.fflag[A.fpar] = 1;
+  }
+}
+
+// the two fields of a fixed-point accumulator, in float
+__device__ __forceinline__ float2 fixed_reactions(uint64_t w, float unit) {
+  const int32_t x = (int32_t)(uint32_t)w;
+  const int32_t y = (int32_t)(uint32_t)((w - (uint64_t)(int64_t)x) >> 32);
+  return make_float2((float)x * unit, (float)y * unit);
 }
 
 // in-edge segment [s, e) of a light vertex, eight (then four) gathers in
@@ -181,10 +211,7 @@ __device__ __forceinline__ float2 light_force(const StepArgs &A, int64_t i, floa
       const float2 t = rn_term<L1>(yi, yk, A.c, A.eps);
       fx += t.x; fy += t.y;
       if (ST) es += rn_stress<L1>(yi, yk, (double)A.c);
-      if (ARN) {
-        unsafeAtomicAdd(&A.fbuf[k].x, -t.x);
-        unsafeAtomicAdd(&A.fbuf[k].y, -t.y);
-      }
+      if (ARN) add_reaction(A, k, t);
     }
   }
   gather_segment<false, L1>(y, A.nn_src, ns, ne, yi, A.c, A.eps, fx, fy);
@@ -248,10 +275,7 @@ __device__ __forceinline__ float2 spread_force(const StepArgs &A, int64_t i, flo
       if (ST && e0 + u * G < n_out)
         es += kind[u] == 1 ? nn_stress<L1>(yi, yo[u]) : rn_stress<L1>(yi, yo[u], (double)A.c);
       // an rn out-edge (the only rn edges listed with ARN): its reaction by atomics
-      if (ARN && kind[u] == 2) {
-        unsafeAtomicAdd(&A.fbuf[other[u]].x, -t.x);
-        unsafeAtomicAdd(&A.fbuf[other[u]].y, -t.y);
-      }
+      if (ARN && kind[u] == 2) add_reaction(A, other[u], t);
     }
   }
 #pragma unroll
@@ -324,7 +348,7 @@ __device__ __forceinline__ void block_sum_store(double x, double *out) {
 // iteration (force + update).  No thread leaves before the block sums.
 // ARN = true is pass 1 of the atomic mode: each vertex's own share (its nn
 // edges both ways and its rn out-edges) goes to A.fown, the rn reactions to
-// A.fbuf by atomics; no update.
+// A.facc (A.fbuf outside the fixed range) by atomics; no update.
 // G = lanes per light vertex (A.lanes): 1, or kSmallGraphLanes on graphs of
 // fewer than kSmallGraphVertices vertices, where one lane per vertex leaves
 // too few wavefronts to hide each lane's chain of dependent loads.
@@ -392,27 +416,76 @@ __global__ void heavy_list_kernel(const int32_t *__restrict__ nn_ptr, int64_t M,
   if (nn_ptr[i + 1] - nn_ptr[i] > heavy_deg) list[atomicAdd(count, 1)] = (int32_t)i;
 }
 
+// the force on vertex i after pass 1 of the atomic mode: own share, then
+// the fixed-point reactions, then the float ones; the accumulators cleared.
+// The float accumulator is read (and cleared) only when the flag of this
+// iteration's slot is set; the other slot is cleared here for the next
+// iteration.  A flag left set from an earlier iteration only costs a read
+// of zeros, while every pass 1 that used fbuf has set the slot its pass 2
+// reads: nothing between them clears that slot.
+__device__ __forceinline__ float2 gather_reactions(const StepArgs &A, int64_t i) {
+  const float2 fo = A.fown[i];
+  if (A.rn == 0) return fo;
+  if (i == 0) A.fflag[A.fpar ^ 1] = 0;
+  const float2 fx = fixed_reactions(A.facc[i], A.rx_unit);
+  A.facc[i] = 0;
+  float2 f = make_float2(fo.x + fx.x, fo.y + fx.y);
+  if (A.fflag[A.fpar]) {
+    const float2 fr = A.fbuf[i];
+    A.fbuf[i] = make_float2(0.f, 0.f);
+    f = make_float2(f.x + fr.x, f.y + fr.y);
+  }
+  return f;
+}
+
 // update after the scatter pass; in place (y_out == y), H rewritten in place
 template <int OPT>
 __global__ void __launch_bounds__(kBlock) atomic_update_kernel(StepArgs A) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.M) return;
-  const float2 fo = A.fown[i], fr = A.fbuf[i];
-  const float2 f = make_float2(fo.x + fr.x, fo.y + fr.y);
-  A.fbuf[i] = make_float2(0.f, 0.f);
+  const float2 f = gather_reactions(A, i);
   (void)apply_update<OPT>(A, i, OPT == OPT_NEST ? make_float2(0.f, 0.f) : A.y[i], f);
 }
 
-__global__ void __launch_bounds__(kBlock) atomic_grad_out_kernel(const float2 *fown, float2 *fbuf, int64_t M,
-                                                                const float *gscale, const int32_t *out_perm,
-                                                                float2 *out) {
+__global__ void __launch_bounds__(kBlock) atomic_grad_out_kernel(StepArgs A, float2 *out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= M) return;
-  const float2 fo = fown[i], fr = fbuf[i];
-  const float2 f = make_float2(fo.x + fr.x, fo.y + fr.y);
-  fbuf[i] = make_float2(0.f, 0.f);
-  const float g = -2.f * (gscale ? *gscale : 1.f);
-  out[out_perm ? out_perm[i] : i] = make_float2(g * f.x, g * f.y);
+  if (i >= A.M) return;
+  const float2 f = gather_reactions(A, i);
+  const float g = -2.f * (A.gscale ? *A.gscale : 1.f);
+  out[A.out_perm ? A.out_perm[i] : i] = make_float2(g * f.x, g * f.y);
+}
+
+// rr->part[b]: the largest count of block b's stride of cnt[0..M)
+__global__ void __launch_bounds__(kBlock) range_parts_kernel(const int32_t *__restrict__ cnt, int64_t M,
+                                                             ReactionRange *rr) {
+  __shared__ int32_t lds[kBlock];
+  int32_t m = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < M; i += (int64_t)gridDim.x * kBlock)
+    m = max(m, cnt[i]);
+  lds[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) lds[threadIdx.x] = max(lds[threadIdx.x], lds[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) rr->part[blockIdx.x] = lds[0];
+}
+
+// rr->cap = 2^(30 - ceil(log2 K)), K the largest of the nparts partial maxima
+// (at least 1): K reactions of at most cap units each sum to at most 2^30
+__global__ void __launch_bounds__(kRangeParts) range_cap_kernel(ReactionRange *rr, int nparts) {
+  __shared__ int32_t lds[kRangeParts];
+  lds[threadIdx.x] = (int)threadIdx.x < nparts ? rr->part[threadIdx.x] : 0;
+  __syncthreads();
+  for (int s = kRangeParts / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) lds[threadIdx.x] = max(lds[threadIdx.x], lds[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const uint32_t k = (uint32_t)max(lds[0], 1);
+    const int ceil_log2 = 32 - __clz((int)(k - 1u));
+    rr->cap = ldexpf(1.f, 30 - ceil_log2);
+  }
 }
 
 __global__ void adam_prep_kernel(AdamState *st, float beta1, float beta2) {
@@ -555,7 +628,15 @@ hipError_t launch_grad_det(const StepArgs &a, float2 *out, hipStream_t s) {
 hipError_t launch_grad_atomic(const StepArgs &a, float2 *out, hipStream_t s) {
   if (a.l1) launch_det<false, true, OPT_PLAIN, true>(a, nullptr, s);
   else launch_det<false, false, OPT_PLAIN, true>(a, nullptr, s);
-  atomic_grad_out_kernel<<<grid_for(a.M), kBlock, 0, s>>>(a.fown, a.fbuf, a.M, a.gscale, a.out_perm, out);
+  atomic_grad_out_kernel<<<grid_for(a.M), kBlock, 0, s>>>(a, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reaction_range(const int32_t *cnt, int64_t M, ReactionRange *rr, hipStream_t s) {
+  const unsigned g = grid_for(M);
+  const int nparts = g < (unsigned)kRangeParts ? (int)g : kRangeParts;
+  range_parts_kernel<<<nparts, kBlock, 0, s>>>(cnt, M, rr);
+  range_cap_kernel<<<1, kRangeParts, 0, s>>>(rr, nparts);
   return hipGetLastError();
 }
 

@@ -123,6 +123,86 @@ def test_single_step_at_full_size(ivhd, mode):
     ctx.close()
 
 
+def _atomic_step_check(ivhd, nn_idx, Y, V, rn, seed, mask=None):
+    a, b, c, eps = f32(0.9), f32(0.01), f32(0.1), f32(1e-12)
+    ctx = _ctx(ivhd, nn_idx, Y, V, rn=rn, a=a, b=b, c=c, eps=eps, seed=seed, mode="atomic")
+    rn_idx = ctx.rn_edges().cpu().numpy()
+    f_ref = oracle.force(Y, nn_idx, rn_idx, c, eps)
+    g = ctx.grad().cpu().numpy()
+    assert _rel(-0.5 * g, f_ref) <= 1e-5
+    if mask is not None:
+        # vertices whose edges all stay inside the fixed-point range, on their own scale
+        keep = mask(rn_idx)
+        assert keep.sum() > 0
+        assert _rel(-0.5 * g[keep], f_ref[keep]) <= 1e-5
+    Y1_ref, V1_ref = oracle.step(Y, V, f_ref, a, b)
+    ctx.step(1)
+    torch.cuda.synchronize()
+    assert _rel(ctx.y.cpu().numpy(), Y1_ref) <= 1e-5
+    assert _rel(ctx.v.cpu().numpy(), V1_ref) <= 1e-5
+    # three more steps, each from the GPU's own state, one of them without a
+    # gradient call between (the float accumulator's flag slots alternate)
+    for k in range(3):
+        Yk, Vk = ctx.y.cpu().numpy(), ctx.v.cpu().numpy()
+        fk = oracle.force(Yk, nn_idx, rn_idx, c, eps)
+        if k != 1:
+            assert _rel(-0.5 * ctx.grad().cpu().numpy(), fk) <= 1e-5
+        Yn, Vn = oracle.step(Yk, Vk, fk, a, b)
+        ctx.step(1)
+        torch.cuda.synchronize()
+        assert _rel(ctx.y.cpu().numpy(), Yn) <= 1e-5, k
+        assert _rel(ctx.v.cpu().numpy(), Vn) <= 1e-5, k
+    ctx.close()
+
+
+def test_atomic_mode_reactions_beyond_the_fixed_range(ivhd):
+    # a far cluster: its rn reactions (about c * 1000) exceed the fixed-point
+    # range and take the float path, the rest stay in fixed point
+    M, far = 3000, 40
+    rng = np.random.default_rng(41)
+    labels = np.zeros(M, np.int32); labels[:far] = 1
+    nn_idx = synth.random_neighbour_graph(M, 2, rng, labels=labels)
+    Y = rng.normal(0, 2.0, size=(M, 2)).astype(np.float32)
+    Y[:far] += np.float32(1000.0)
+    V = (0.01 * rng.normal(size=(M, 2))).astype(np.float32)
+
+    def clear_of_the_far_cluster(rn_idx):
+        touched = np.zeros(M, bool)
+        touched[:far] = True
+        hit = (rn_idx < far) & (rn_idx >= 0)
+        touched[np.nonzero(hit.any(1))[0]] = True
+        touched[rn_idx[:far].ravel()] = True
+        return ~touched
+
+    _atomic_step_check(ivhd, nn_idx, Y, V, 2, 5, mask=clear_of_the_far_cluster)
+
+
+def test_atomic_mode_with_a_large_rn_in_degree(ivhd):
+    # rn = 40 of 80 vertices: in-degrees near 60 narrow the fixed-point range
+    # to a few c, so many reactions take the float path
+    nn_idx, Y, V = _case(80, 2, 40, 42)
+    _atomic_step_check(ivhd, nn_idx, Y, V, 40, 6)
+
+
+def test_atomic_mode_is_bitwise_reproducible(ivhd):
+    # the rn reactions are integer sums: the order of the atomics does not
+    # change a bit, with or without graph replay, over redraws
+    nn_idx, Y, V = _case(20000, 3, 2, 43)
+    runs = []
+    for graphs in (True, True, False):
+        ctx = _ctx(ivhd, nn_idx, Y, V, rn=2, b=0.002, seed=7, rn_resample_every=7, mode="atomic")
+        ctx.set_graphs(graphs)
+        ctx.step(40)
+        torch.cuda.synchronize()
+        runs.append((ctx.y.cpu().numpy(), ctx.v.cpu().numpy(), ctx.grad().cpu().numpy()))
+        ctx.close()
+    assert np.all(np.isfinite(runs[0][0])) and not np.array_equal(runs[0][0], Y)
+    for y, v, g in runs[1:]:
+        assert np.array_equal(y, runs[0][0])
+        assert np.array_equal(v, runs[0][1])
+        assert np.array_equal(g, runs[0][2])
+
+
 @pytest.mark.parametrize("M,nn,rn,seed,extra", CASES[:4])
 def test_fp64_stress_matches_oracle(ivhd, M, nn, rn, seed, extra):
     nn_idx, Y, V = _case(M, nn, rn, seed, **extra)
