@@ -172,6 +172,28 @@ def gather_ceiling(M, nn, rn, kernel_s, dev, reps=20):
     return res
 
 
+def atomic_floor(M, rn, dev, reps=20):
+    """The atomic mode's first pass delivers each of the M rn reactions of an
+    iteration with one 64-bit integer atomic to a random vertex: the time of
+    those atomics alone (the library's probe kernel), a labelled bound for
+    that pass."""
+    import torch
+    from paper_2303_05455_amd import ivhd_probe_atomic
+    n = M * rn
+    gen = torch.Generator().manual_seed(8)
+    idx = torch.randint(0, M, (n,), dtype=torch.int32, generator=gen).to(dev)
+    acc = torch.zeros(M, dtype=torch.int64, device=dev)
+    ivhd_probe_atomic(acc, idx)
+    torch.cuda.synchronize()
+    e0, e1 = events()
+    e0.record()
+    for _ in range(reps):
+        ivhd_probe_atomic(acc, idx)
+    e1.record()
+    torch.cuda.synchronize()
+    return {"atomics_per_iteration": n, "atomics_alone_us": e0.elapsed_time(e1) * 1e3 / reps}
+
+
 def calibrate_copy(mib: int):
     """A plain device copy of known size, for scaling the FETCH_SIZE and
     WRITE_SIZE counters (run under rocprofv3 --pmc)."""
@@ -282,6 +304,10 @@ def run_loop(args, cfg):
         }
         log(f"{mode}: {res[mode]['value']:.4g} edge-updates/s, {res[mode]['us_per_iter']:.2f} us/iter, "
             f"{res[mode]['gbps_alg']:.0f} GB/s algorithmic, E={E:.6g}")
+        if mode == "atomic" and rn > 0:
+            res[mode]["reaction_atomics"] = atomic_floor(M, rn, dev)
+            log(f"atomic mode: its {M * rn:,} reaction atomics alone take "
+                f"{res[mode]['reaction_atomics']['atomics_alone_us']:.1f} us")
 
     # per-launch time of the deterministic step kernel: back-to-back launches
     # (no draws), HIP events on the library's stream

@@ -75,6 +75,7 @@ SIGNATURES = {
     "ivhd_eval_ranks": (i32, [vp, i64, i32, vp, i64, vp, i32, vp, vp]),
     "ivhd_eval_scores": (i32, [i64, vp, i64, vp, i32, vp, i32, vp, vp, i32, vp, vp]),
     "ivhd_probe_gather": (i32, [vp, i64, vp, i64, vp, vp]),
+    "ivhd_probe_atomic": (i32, [vp, i64, vp, i64, vp]),
     "ivhd_last_error": (ctypes.c_char_p, []),
     "ivhd_version": (i32, []),
 }

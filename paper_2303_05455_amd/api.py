@@ -26,6 +26,7 @@ __all__ = [
     "ivhd_grad_edges_noalloc", "ivhd_set_adaptive",
     "ivhd_get_adaptive", "ivhd_rnn_mask", "ivhd_set_adam", "ivhd_ivf_train", "ivhd_ivf_search",
     "ivf_knn_graph", "ivhd_eval_neighbours", "ivhd_eval_ranks", "ivhd_eval_scores", "ivhd_probe_gather",
+    "ivhd_probe_atomic",
 ]
 
 
@@ -607,3 +608,14 @@ def ivhd_probe_gather(src: torch.Tensor, idx: torch.Tensor, out: Optional[torch.
     check(_lib.load().ivhd_probe_gather(src.data_ptr(), n_src, idx.data_ptr(), n, out.data_ptr(),
                                         _stream_handle(stream)))
     return out
+
+
+def ivhd_probe_atomic(acc: torch.Tensor, idx: torch.Tensor, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """acc[idx[t]] += 2**32 + 1 with one 64-bit integer atomic per index, on an
+    int64 [n_acc] tensor (a random-atomic rate probe)."""
+    n_acc = acc.shape[0]
+    _dev(acc, torch.int64, (n_acc,), "acc")
+    n = idx.shape[0]
+    _dev(idx, torch.int32, (n,), "idx")
+    check(_lib.load().ivhd_probe_atomic(acc.data_ptr(), n_acc, idx.data_ptr(), n, _stream_handle(stream)))
+    return acc

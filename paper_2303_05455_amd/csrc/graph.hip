@@ -394,6 +394,16 @@ hipError_t launch_unmap_lists(const int32_t *lists, int64_t M, int k, const int3
   return hipGetLastError();
 }
 
+__global__ void probe_atomic_kernel(uint64_t *acc, const int32_t *__restrict__ idx, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) atomicAdd((unsigned long long *)(acc + idx[t]), (1ull << 32) | 1ull);
+}
+
+hipError_t launch_probe_atomic(uint64_t *acc, const int32_t *idx, int64_t n, hipStream_t s) {
+  probe_atomic_kernel<<<grid_for(n), kBlock, 0, s>>>(acc, idx, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_gather_f2(const float2 *src, const int32_t *idx, int64_t M, float2 *dst, hipStream_t s) {
   gather_f2_kernel<<<grid_for(M), kBlock, 0, s>>>(src, idx, M, dst);
   return hipGetLastError();

@@ -94,6 +94,8 @@ hipError_t launch_map_lists(const int32_t *idx, int64_t M, int k, const int32_t 
 hipError_t launch_unmap_lists(const int32_t *lists, int64_t M, int k, const int32_t *perm, const int32_t *inv,
                               int32_t *out, hipStream_t s);
 hipError_t launch_gather_f2(const float2 *src, const int32_t *idx, int64_t M, float2 *dst, hipStream_t s);
+// acc[idx[t]] += 2^32 + 1 for t < n, one 64-bit integer atomic each (a rate probe)
+hipError_t launch_probe_atomic(uint64_t *acc, const int32_t *idx, int64_t n, hipStream_t s);
 // out[i][q] = nn_idx[i][q] when i is among helper[j][0..kh) for j = nn_idx[i][q] >= 0, else -1
 hipError_t launch_rnn_mask(const int32_t *nn_idx, int64_t M, int nn, const int32_t *helper, int kh, int32_t *out,
                            hipStream_t s);

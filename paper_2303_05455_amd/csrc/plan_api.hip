@@ -561,3 +561,13 @@ extern "C" int ivhd_probe_gather(const float *d_src, int64_t n_src, const int32_
   HIPCHK(launch_gather_f2((const float2 *)d_src, d_idx, n, (float2 *)d_dst, (hipStream_t)stream));
   return IVHD_OK;
 }
+
+extern "C" int ivhd_probe_atomic(uint64_t *d_acc, int64_t n_acc, const int32_t *d_idx, int64_t n, void *stream) {
+  clear_error();
+  if (n < 0 || n_acc < 1) return fail(IVHD_EINVAL, "n = %lld and n_acc = %lld must be >= 0 and >= 1",
+                                      (long long)n, (long long)n_acc);
+  if (n == 0) return IVHD_OK;
+  if (!d_acc || !d_idx) return fail(IVHD_EINVAL, "d_acc and d_idx must not be NULL");
+  HIPCHK(launch_probe_atomic(d_acc, d_idx, n, (hipStream_t)stream));
+  return IVHD_OK;
+}

@@ -178,6 +178,13 @@ def test_eval_calls_reject_bad_sizes_before_device_work(lib):
                                 None) == -1
 
 
+def test_probe_atomic_rejects_bad_sizes(lib):
+    assert lib.ivhd_probe_atomic(FAKE, 0, FAKE, 10, None) == -1
+    assert lib.ivhd_probe_atomic(FAKE, 10, FAKE, -1, None) == -1
+    assert lib.ivhd_probe_atomic(None, 10, FAKE, 5, None) == -1
+    assert lib.ivhd_probe_atomic(None, 10, None, 0, None) == 0
+
+
 def test_probe_gather_rejects_bad_sizes(lib):
     assert lib.ivhd_probe_gather(FAKE, 0, FAKE, 10, FAKE, None) == -1
     assert lib.ivhd_probe_gather(FAKE, 10, FAKE, -1, FAKE, None) == -1
