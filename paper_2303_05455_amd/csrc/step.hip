@@ -168,7 +168,7 @@ __device__ __forceinline__ void gather_segment(const float2 *__restrict__ y, con
 // force on a light vertex: out-nn, out-rn, in-nn, in-rn, in that order.
 // Positions are gathered from A.h (Y, or the look-ahead H = Y + a V).
 // With ARN (atomic mode) the rn in-edges are not gathered: each rn
-// out-edge's reaction goes to the other end's accumulator with float atomics.
+// out-edge's reaction goes to the other end's accumulator by add_reaction.
 // With ST the out-edges' stress terms are added to es in FP64 (out-nn, then
 // out-rn).
 template <bool L1, bool ARN, bool ST = false>
