@@ -231,6 +231,28 @@ def test_resample_schedule_matches_oracle_draws(ivhd, mode):
     ctx.close()
 
 
+@pytest.mark.parametrize("mode", ["det", "atomic"])
+def test_steps_across_redraws_match_the_oracle(ivhd, mode):
+    # every step from the GPU's own state against the oracle's step with the
+    # draw of that iteration's epoch: the transposed rn lists (det) and the
+    # fixed-point range of the reactions (atomic) are rebuilt at each redraw
+    M, nn, rn, R, seed = 3000, 2, 2, 3, 17
+    a, b, c, eps = f32(0.9), f32(0.005), f32(0.1), f32(1e-12)
+    nn_idx, Y, V = _case(M, nn, rn, seed)
+    ctx = _ctx(ivhd, nn_idx, Y, V, rn=rn, a=a, b=b, c=c, eps=eps, seed=seed, rn_resample_every=R, mode=mode)
+    for n in range(8):
+        Yn, Vn = ctx.y.cpu().numpy(), ctx.v.cpu().numpy()
+        rn_e = oracle.rn_sample(nn_idx, rn, seed, n // R)
+        f_ref = oracle.force(Yn, nn_idx, rn_e, c, eps)
+        Y1, V1 = oracle.step(Yn, Vn, f_ref, a, b)
+        ctx.step(1)
+        torch.cuda.synchronize()
+        assert np.array_equal(ctx.rn_edges().cpu().numpy(), rn_e), n
+        assert _rel(ctx.y.cpu().numpy(), Y1) <= 1e-5, n
+        assert _rel(ctx.v.cpu().numpy(), V1) <= 1e-5, n
+    ctx.close()
+
+
 def _components(nn_idx, M):
     """Component label (smallest id) of each vertex of the undirected nn graph."""
     import scipy.sparse as sp
